@@ -1,0 +1,310 @@
+"""FP64 CPU oracle of the w-stacking imager -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The HIP library never calls it and shares no code with
+it.  Everything here runs in float64 / complex128.
+
+Method (De Rubeis et al., "Accelerating radio astronomy imaging with RICK",
+arXiv 2411.07321, Sec. 2):
+
+  O1 geometry   pixel p has l_p = (p - N/2) dl, cell i has u_i = (i - N/2)/(N dl)
+                (Sec. 2: the N_u x N_v x N_w mesh; u,v,w in wavelengths).
+  O2 validity   unflagged, finite, weight > 0, footprint inside the mesh.
+  O3 planes     nearest of N_w cell-centred w-planes (Sec. 2, w-stacking paragraph).
+  O4 gridding   Eq. 3 with a separable Gaussian of support S    (wsg_oracle.c)
+  O5 transform  unnormalised centred 2D inverse DFT of every plane (Sec. 2, third
+                component; sign + from Eq. 2).  numpy.fft is the library step.
+  O6 w-correct  A = sum_k F_k exp(+2 pi i w_k (n - 1)) (Eq. 2; fourth component).
+  O7 post       D = Re A / (sum W * C(nu_p) C(nu_q)): grid correction by the
+                continuous transform C of the truncated kernel, and weight
+                normalisation (a reading: the paper does not state either).
+  O8 channels   one image per channel, or all channels into one image.
+
+Parity status: every step is pinned by tests/test_oracle_pins.py against
+brute-force direct transforms, closed forms (pure fringe, flat field,
+quadrature vs complex-erf) and invariants (Parseval, grid sum, permutation,
+linearity).  The paper prints no image or accuracy figure, so agreement with
+the paper's own outputs is unpinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wsg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [("n_used", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
+                ("n_dropped", ctypes.c_int64), ("sum_w", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_w_range.restype = ctypes.c_int64
+        lib.oracle_w_range.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       P, P]
+        lib.oracle_grid.restype = ctypes.c_int
+        lib.oracle_grid.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        lib.oracle_pixels.restype = ctypes.c_int
+        lib.oracle_pixels.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Params:
+    """Imaging parameters (the same quantities the library takes)."""
+    grid_n: int
+    n_wplanes: int
+    support: int
+    cell_rad: float
+    kernel_sigma: float = 0.9
+    w_min: float = float("nan")        # nan -> range of the data
+    w_max: float = float("nan")
+    plane_lo: int = 0
+    plane_hi: int = 0                  # 0 -> all planes
+    grid_correct: bool = True
+    normalize: bool = True
+    per_channel: bool = False
+
+
+@dataclass
+class Inputs:
+    """Measurements in float64: uvw [rows,3]; vis [rows,n_chan] complex128."""
+    uvw: np.ndarray
+    freq_hz: np.ndarray | None
+    vis: np.ndarray
+    weights: np.ndarray | None
+    flags: np.ndarray | None
+
+    @staticmethod
+    def make(uvw, freq_hz, vis, weights=None, flags=None) -> "Inputs":
+        uvw = np.ascontiguousarray(uvw, dtype=np.float64)
+        vis = np.ascontiguousarray(vis, dtype=np.complex128)
+        if vis.ndim == 1:
+            vis = vis[:, None]
+        if weights is not None:
+            weights = np.ascontiguousarray(weights, dtype=np.float64).reshape(vis.shape)
+        if flags is not None:
+            flags = np.ascontiguousarray(flags, dtype=np.uint8).reshape(vis.shape)
+        f = None if freq_hz is None else np.ascontiguousarray(freq_hz, dtype=np.float64)
+        return Inputs(uvw, f, vis, weights, flags)
+
+    @property
+    def n_rows(self):
+        return self.uvw.shape[0]
+
+    @property
+    def n_chan(self):
+        return self.vis.shape[1]
+
+    def chan_scale(self) -> np.ndarray:
+        """Per-channel factor from metres to wavelengths (f/c), or 1 for uvw in wavelengths."""
+        if self.freq_hz is None:
+            return np.ones(self.n_chan, dtype=np.float64)
+        return self.freq_hz / C_LIGHT
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------
+# O2/O3: data range of w and counts
+# ----------------------------------------------------------------------------
+def w_range(inp: Inputs, prm: Params, chan: int = -1):
+    """(w_min, w_max) for the plane placement: the caller's range if given, else the
+    range over valid measurements; (0, 0) when nothing is valid."""
+    if math.isfinite(prm.w_min) and math.isfinite(prm.w_max):
+        return float(prm.w_min), float(prm.w_max)
+    lib = _load()
+    sc = inp.chan_scale()
+    lo, hi = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    lib.oracle_w_range(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
+                       _ptr(inp.weights), _ptr(inp.flags), prm.grid_n, prm.support,
+                       prm.cell_rad, chan, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def plane_w(k: np.ndarray | int, w_min: float, w_max: float, n_w: int):
+    """w of plane k: w_min + (k + 1/2) dw, or w_min when dw = 0 (O3)."""
+    dw = (w_max - w_min) / n_w
+    k = np.asarray(k, dtype=np.float64)
+    if dw == 0.0:
+        return np.full_like(k, w_min)
+    return w_min + (k + 0.5) * dw
+
+
+# ----------------------------------------------------------------------------
+# O4: gridding (Eq. 3)
+# ----------------------------------------------------------------------------
+def grid(inp: Inputs, prm: Params, w_min: float, w_max: float, plane_lo: int = 0,
+         plane_hi: int | None = None, chan: int = -1):
+    """Gridded planes [plane_hi-plane_lo, N, N] complex128 (row j = v index, column i =
+    u index) and the counts (used, flagged, dropped, sum of weights)."""
+    if plane_hi is None:
+        plane_hi = prm.n_wplanes
+    lib = _load()
+    n = prm.grid_n
+    g = np.zeros((plane_hi - plane_lo, n, n), dtype=np.complex128)
+    cnt = _Counts()
+    sc = inp.chan_scale()
+    rc = lib.oracle_grid(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
+                         _ptr(inp.weights), _ptr(inp.flags), n, prm.n_wplanes, prm.support,
+                         prm.cell_rad, prm.kernel_sigma, w_min, w_max, plane_lo, plane_hi,
+                         chan, _ptr(g), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle_grid: unsupported support")
+    return g, {"n_used": cnt.n_used, "n_flagged": cnt.n_flagged, "n_dropped": cnt.n_dropped,
+               "sum_w": cnt.sum_w}
+
+
+# ----------------------------------------------------------------------------
+# O5: transform
+# ----------------------------------------------------------------------------
+def fft_planes(g: np.ndarray) -> np.ndarray:
+    """F[q,p] = sum_{j,i} g[j,i] exp(+2 pi i ((i-N/2)(p-N/2) + (j-N/2)(q-N/2))/N):
+    the unnormalised inverse DFT with the origin at index N/2 on both sides."""
+    x = np.fft.ifftshift(g, axes=(-2, -1))
+    x = np.fft.ifft2(x, axes=(-2, -1), norm="forward")
+    return np.fft.fftshift(x, axes=(-2, -1))
+
+
+# ----------------------------------------------------------------------------
+# O6: w-correction and plane sum (Eq. 2)
+# ----------------------------------------------------------------------------
+def n_minus_1(n: int, cell: float):
+    """(n - 1) on the pixel grid in the cancellation-free form -eta/(1 + sqrt(1 - eta)),
+    eta = l^2 + m^2; and the mask eta < 1 of pixels on the celestial sphere."""
+    c = (np.arange(n, dtype=np.float64) - n / 2) * cell
+    eta = c[None, :] ** 2 + c[:, None] ** 2          # [q, p]
+    inside = eta < 1.0
+    e = np.where(inside, eta, 0.0)
+    return -e / (1.0 + np.sqrt(1.0 - e)), inside
+
+
+def wcorrect(F: np.ndarray, w_min: float, w_max: float, n_w: int, cell: float,
+             plane_lo: int = 0) -> np.ndarray:
+    """A[q,p] = sum_k F_k[q,p] exp(+2 pi i w_k (n_pq - 1)); 0 off the sphere."""
+    n = F.shape[-1]
+    nm1, inside = n_minus_1(n, cell)
+    acc = np.zeros((n, n), dtype=np.complex128)
+    for kk in range(F.shape[0]):
+        wk = float(plane_w(plane_lo + kk, w_min, w_max, n_w))
+        acc += F[kk] * np.exp(2j * np.pi * wk * nm1)
+    acc[~inside] = 0.0
+    return acc
+
+
+# ----------------------------------------------------------------------------
+# O7: grid correction and normalisation
+# ----------------------------------------------------------------------------
+def kernel_transform(n: int, support: int, sigma: float, nodes: int = 64) -> np.ndarray:
+    """C(nu_p) = int_{-S/2}^{S/2} exp(-d^2/(2 sigma^2)) cos(2 pi nu_p d) dd at
+    nu_p = (p - N/2)/N, by Gauss-Legendre quadrature."""
+    x, wq = np.polynomial.legendre.leggauss(nodes)
+    a = support / 2.0
+    d = a * x
+    nu = (np.arange(n, dtype=np.float64) - n / 2) / n
+    f = np.exp(-d * d / (2.0 * sigma * sigma))
+    return a * (np.cos(2.0 * np.pi * nu[:, None] * d[None, :]) * (wq * f)[None, :]).sum(axis=1)
+
+
+def post(A: np.ndarray, sum_w: float, prm: Params) -> np.ndarray:
+    """D = Re A / (sum W * C(nu_p) C(nu_q)), each factor switchable; 0 if sum W = 0."""
+    d = A.real.copy()
+    if prm.grid_correct:
+        c = kernel_transform(prm.grid_n, prm.support, prm.kernel_sigma)
+        d /= c[:, None] * c[None, :]
+    if prm.normalize:
+        if sum_w > 0.0:
+            d /= sum_w
+        else:
+            d[:] = 0.0
+    return d
+
+
+# ----------------------------------------------------------------------------
+# whole method
+# ----------------------------------------------------------------------------
+def image(inp: Inputs, prm: Params, plane_chunk: int | None = None, keep_stages: bool = False):
+    """The imaging method end to end.  Returns dict(image [n_img,N,N] f64, raw
+    [n_img,N,N] complex128 (A before post), stats per image, and, with keep_stages,
+    grid and planes of the first image)."""
+    chans = list(range(inp.n_chan)) if prm.per_channel else [-1]
+    lo = prm.plane_lo
+    hi = prm.plane_hi if prm.plane_hi > 0 else prm.n_wplanes
+    step = plane_chunk or (hi - lo)
+    imgs, raws, stats = [], [], []
+    stages = {}
+    for ci, ch in enumerate(chans):
+        wmin, wmax = w_range(inp, prm, ch)
+        acc = np.zeros((prm.grid_n, prm.grid_n), dtype=np.complex128)
+        cnt = None
+        for k0 in range(lo, hi, step):
+            k1 = min(hi, k0 + step)
+            g, cnt = grid(inp, prm, wmin, wmax, k0, k1, ch)
+            F = fft_planes(g)
+            if keep_stages and ci == 0 and step == hi - lo:
+                stages = {"grid": g, "planes": F}
+            acc += wcorrect(F, wmin, wmax, prm.n_wplanes, prm.cell_rad, k0)
+            del g, F
+        if cnt is None:
+            _, cnt = grid(inp, prm, wmin, wmax, 0, 0, ch)
+        raws.append(acc)
+        imgs.append(post(acc, cnt["sum_w"], prm))
+        stats.append(dict(cnt, w_min=wmin, w_max=wmax))
+    out = {"image": np.stack(imgs), "raw": np.stack(raws), "stats": stats}
+    out.update(stages)
+    return out
+
+
+def pixels(inp: Inputs, prm: Params, pix_q, pix_p, chan: int = -1) -> np.ndarray:
+    """Raw image A at the listed pixels, evaluated directly from the measurements
+    (for sampled checks at full size).  complex128 [n_pix]."""
+    lib = _load()
+    wmin, wmax = w_range(inp, prm, chan)
+    q = np.ascontiguousarray(pix_q, dtype=np.int32)
+    p = np.ascontiguousarray(pix_p, dtype=np.int32)
+    out = np.zeros(len(q), dtype=np.complex128)
+    sc = inp.chan_scale()
+    rc = lib.oracle_pixels(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
+                           _ptr(inp.weights), _ptr(inp.flags), prm.grid_n, prm.n_wplanes,
+                           prm.support, prm.cell_rad, prm.kernel_sigma, wmin, wmax, chan,
+                           len(q), _ptr(q), _ptr(p), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_pixels failed")
+    return out

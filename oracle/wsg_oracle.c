@@ -1,0 +1,315 @@
+/*
+ * FP64 CPU oracle of the w-stacking imager -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the slow, plain reference against which the HIP library is
+ * checked.  Only the test-suite, the smoke check and the benchmark's CPU
+ * baseline may load it; the product path never does.  It shares no code,
+ * header or table with the HIP library.
+ *
+ * Paper: De Rubeis et al., "Accelerating radio astronomy imaging with RICK"
+ * (arXiv 2411.07321).  Sec. 2 defines the method:
+ *   - visibilities V(u,v,w), (u,v,w) in wavelengths (Eq. 1 and the text below it);
+ *   - each visibility goes to the closest w-plane (Sec. 2, w-stacking paragraph);
+ *   - it is convolved onto the (u,v) mesh of its plane with a kernel G (Eq. 3);
+ *   - each plane is inverse-Fourier transformed, phase-corrected with
+ *     exp(+2 pi i w (sqrt(1-l^2-m^2) - 1)) and the planes are summed (Eq. 2,
+ *     and the description of the third and fourth algorithmic components).
+ *
+ * Readings of points the paper leaves open (listed in the design notes):
+ *   - G(d) = exp(-d^2 / (2 sigma^2)), separable in u and v, support S odd,
+ *     h = (S-1)/2 cells on each side of the nearest cell i0 = floor(x + 1/2);
+ *   - x = u * (N * dl) + N/2 with no fused multiply-add, so that the cell and
+ *     plane decisions are reproducible bit for bit;
+ *   - N_w cell-centred planes over [w_min, w_max]: dw = (w_max - w_min)/N_w,
+ *     k = min(N_w - 1, floor((w - w_min)/dw)), w_k = w_min + (k + 1/2) dw;
+ *     dw = 0 puts everything on plane 0 at w_0 = w_min;
+ *   - a measurement is used iff it is unflagged, its weight is finite and > 0,
+ *     u, v, w and V are finite, its footprint lies inside the grid and its w
+ *     lies inside [w_min, w_max]; everything else is skipped and counted.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int64_t n_used;     /* measurements that enter the image (all planes)      */
+    int64_t n_flagged;  /* flag != 0                                           */
+    int64_t n_dropped;  /* unflagged but unused (bad value, off-grid, off-w)   */
+    double  sum_w;      /* sum of weights of used measurements                 */
+} oracle_counts;
+
+/* Position of one measurement on the mesh (Eq. 3 support placement). */
+static void position(double u, double v, double scale, int n, double *x, double *y)
+{
+    double half = 0.5 * (double)n;
+    double ux = u * scale;          /* one rounding for the product ... */
+    double vy = v * scale;
+    *x = ux + half;                 /* ... and one for the sum          */
+    *y = vy + half;
+}
+
+/* Footprint test: i0 = floor(x + 1/2) must satisfy h <= i0 <= N-1-h. */
+static int fits(double x, int n, int h, int64_t *i0)
+{
+    double f = floor(x + 0.5);
+    if (!(f >= (double)h && f <= (double)(n - 1 - h))) return 0;
+    *i0 = (int64_t)f;
+    return 1;
+}
+
+static int is_valid0(const double *uvw_row, double sc, const double *vis_rc, double wt,
+                     uint8_t flag, double scale, int n, int h)
+{
+    if (flag) return 0;
+    if (!(wt > 0.0) || !isfinite(wt)) return 0;
+    double u = uvw_row[0] * sc, v = uvw_row[1] * sc, w = uvw_row[2] * sc;
+    if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return 0;
+    if (!isfinite(vis_rc[0]) || !isfinite(vis_rc[1])) return 0;
+    double x, y;
+    int64_t i0, j0;
+    position(u, v, scale, n, &x, &y);
+    return fits(x, n, h, &i0) && fits(y, n, h, &j0);
+}
+
+/*
+ * Range of w over the measurements that pass every test except the w-range
+ * cut (the "from the data" default of the plane placement).
+ * chan < 0: all channels; else only that channel.
+ * Returns the number of such measurements; *w_lo/*w_hi untouched if none.
+ */
+int64_t oracle_w_range(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
+                       const double *vis, const double *weights, const uint8_t *flags,
+                       int n, int support, double cell, int chan,
+                       double *w_lo, double *w_hi)
+{
+    int h = (support - 1) / 2;
+    double scale = (double)n * cell;
+    int64_t cnt = 0;
+    double lo = 0.0, hi = 0.0;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        for (int c = 0; c < n_chan; ++c) {
+            if (chan >= 0 && c != chan) continue;
+            int64_t rc = r * n_chan + c;
+            double wt = weights ? weights[rc] : 1.0;
+            uint8_t fl = flags ? flags[rc] : 0;
+            if (!is_valid0(uvw + 3 * r, chan_scale[c], vis + 2 * rc, wt, fl, scale, n, h))
+                continue;
+            double w = uvw[3 * r + 2] * chan_scale[c];
+            if (cnt == 0) { lo = w; hi = w; }
+            if (w < lo) lo = w;
+            if (w > hi) hi = w;
+            ++cnt;
+        }
+    }
+    if (cnt) { *w_lo = lo; *w_hi = hi; }
+    return cnt;
+}
+
+/* Nearest w-plane (cell-centred planes over [w_min, w_max]). */
+static int plane_of(double w, double w_min, double dw, int n_w)
+{
+    if (dw == 0.0) return 0;
+    double t = floor((w - w_min) / dw);
+    int k = (int)t;
+    if (k > n_w - 1) k = n_w - 1;
+    return k;
+}
+
+/*
+ * Eq. 3 on the (u,v) mesh of the nearest w-plane:
+ *   g_k[j0+b][i0+a] += W V G(i0+a-x) G(j0+b-y),  a, b in [-h, h].
+ * grid: complex128 interleaved [plane_hi-plane_lo][N][N] (row j, column i),
+ * accumulated into (the caller zeroes it).  Only planes in [plane_lo,
+ * plane_hi) are gridded; the counts cover every plane.
+ */
+int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
+                const double *vis, const double *weights, const uint8_t *flags,
+                int n, int n_w, int support, double cell, double sigma,
+                double w_min, double w_max, int plane_lo, int plane_hi, int chan,
+                double *grid, oracle_counts *counts)
+{
+    int h = (support - 1) / 2;
+    double scale = (double)n * cell;
+    double dw = (w_max - w_min) / (double)n_w;
+    double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    double gx[64], gy[64];
+    oracle_counts cnt = {0, 0, 0, 0.0};
+    if (support > 63) return -1;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        for (int c = 0; c < n_chan; ++c) {
+            if (chan >= 0 && c != chan) continue;
+            int64_t rc = r * n_chan + c;
+            double wt = weights ? weights[rc] : 1.0;
+            uint8_t fl = flags ? flags[rc] : 0;
+            if (fl) { cnt.n_flagged++; continue; }
+            if (!is_valid0(uvw + 3 * r, chan_scale[c], vis + 2 * rc, wt, fl, scale, n, h)) {
+                cnt.n_dropped++;
+                continue;
+            }
+            double u = uvw[3 * r + 0] * chan_scale[c];
+            double v = uvw[3 * r + 1] * chan_scale[c];
+            double w = uvw[3 * r + 2] * chan_scale[c];
+            if (!(w >= w_min && w <= w_max)) { cnt.n_dropped++; continue; }
+            cnt.n_used++;
+            cnt.sum_w += wt;
+            int k = plane_of(w, w_min, dw, n_w);
+            if (k < plane_lo || k >= plane_hi) continue;
+            double x, y;
+            int64_t i0, j0;
+            position(u, v, scale, n, &x, &y);
+            fits(x, n, h, &i0);
+            fits(y, n, h, &j0);
+            for (int a = -h; a <= h; ++a) {
+                double d = (double)(i0 + a) - x;
+                gx[a + h] = exp(-d * d * inv2s2);
+            }
+            for (int b = -h; b <= h; ++b) {
+                double d = (double)(j0 + b) - y;
+                gy[b + h] = exp(-d * d * inv2s2);
+            }
+            double wv_re = wt * vis[2 * rc + 0];
+            double wv_im = wt * vis[2 * rc + 1];
+            double *plane = grid + (size_t)(k - plane_lo) * (size_t)n * (size_t)n * 2;
+            for (int b = -h; b <= h; ++b) {
+                double *row = plane + ((size_t)(j0 + b) * (size_t)n) * 2;
+                for (int a = -h; a <= h; ++a) {
+                    double g = gx[a + h] * gy[b + h];
+                    size_t i = (size_t)(i0 + a) * 2;
+                    row[i + 0] += wv_re * g;
+                    row[i + 1] += wv_im * g;
+                }
+            }
+        }
+    }
+    if (counts) *counts = cnt;
+    return 0;
+}
+
+/*
+ * The raw image A(q,p) at a list of pixels, evaluated directly from the
+ * measurements instead of through the mesh (the same discrete sum, taken in
+ * the other order):
+ *   A(q,p) = sum_used W V [sum_a G(i0+a-x) e^{2 pi i (i0+a-N/2)(p-N/2)/N}]
+ *                        [sum_b G(j0+b-y) e^{2 pi i (j0+b-N/2)(q-N/2)/N}]
+ *                        e^{2 pi i w_k (n_pq - 1)},
+ * with n_pq - 1 = -eta/(1 + sqrt(1 - eta)), eta = l_p^2 + m_q^2, and A = 0
+ * where eta >= 1.  The integer product (i0+a-N/2)(p-N/2) is reduced mod N
+ * exactly before the exponential is taken.
+ * Used for sampled checks at sizes where the full mesh is too large.
+ * out: complex128 interleaved [n_pix].  Deterministic: partial sums per
+ * thread block of rows are added in block order.
+ */
+int oracle_pixels(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
+                  const double *vis, const double *weights, const uint8_t *flags,
+                  int n, int n_w, int support, double cell, double sigma,
+                  double w_min, double w_max, int chan,
+                  int n_pix, const int32_t *pix_q, const int32_t *pix_p, double *out)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    int h = (support - 1) / 2;
+    double scale = (double)n * cell;
+    double dw = (w_max - w_min) / (double)n_w;
+    double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    if (support > 63 || n_pix <= 0) return n_pix < 0 ? -1 : 0;
+
+    double *ct = (double *)malloc(sizeof(double) * (size_t)n);
+    double *st = (double *)malloc(sizeof(double) * (size_t)n);
+    double *wk = (double *)malloc(sizeof(double) * 2 * (size_t)n_pix * (size_t)n_w);
+    for (int t = 0; t < n; ++t) {
+        ct[t] = cos(two_pi * (double)t / (double)n);
+        st[t] = sin(two_pi * (double)t / (double)n);
+    }
+    for (int ip = 0; ip < n_pix; ++ip) {
+        double l = (double)(pix_p[ip] - n / 2) * cell;
+        double m = (double)(pix_q[ip] - n / 2) * cell;
+        double eta = l * l + m * m;
+        for (int k = 0; k < n_w; ++k) {
+            double *e = wk + 2 * ((size_t)ip * n_w + k);
+            if (eta >= 1.0) { e[0] = 0.0; e[1] = 0.0; continue; }
+            double nm1 = -eta / (1.0 + sqrt(1.0 - eta));
+            double wkk = (dw == 0.0) ? w_min : w_min + ((double)k + 0.5) * dw;
+            double ph = two_pi * wkk * nm1;
+            e[0] = cos(ph);
+            e[1] = sin(ph);
+        }
+    }
+
+    const int64_t block = 1 << 16;
+    int64_t n_blocks = (n_rows + block - 1) / block;
+    double *part = (double *)calloc((size_t)(n_blocks > 0 ? n_blocks : 1) * 2 * (size_t)n_pix,
+                                    sizeof(double));
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t bi = 0; bi < n_blocks; ++bi) {
+        double gx[64], gy[64];
+        double *acc = part + (size_t)bi * 2 * (size_t)n_pix;
+        int64_t r1 = (bi + 1) * block < n_rows ? (bi + 1) * block : n_rows;
+        for (int64_t r = bi * block; r < r1; ++r) {
+            for (int c = 0; c < n_chan; ++c) {
+                if (chan >= 0 && c != chan) continue;
+                int64_t rc = r * n_chan + c;
+                double wt = weights ? weights[rc] : 1.0;
+                uint8_t fl = flags ? flags[rc] : 0;
+                if (!is_valid0(uvw + 3 * r, chan_scale[c], vis + 2 * rc, wt, fl, scale, n, h))
+                    continue;
+                double u = uvw[3 * r + 0] * chan_scale[c];
+                double v = uvw[3 * r + 1] * chan_scale[c];
+                double w = uvw[3 * r + 2] * chan_scale[c];
+                if (!(w >= w_min && w <= w_max)) continue;
+                int k = plane_of(w, w_min, dw, n_w);
+                double x, y;
+                int64_t i0, j0;
+                position(u, v, scale, n, &x, &y);
+                fits(x, n, h, &i0);
+                fits(y, n, h, &j0);
+                for (int a = -h; a <= h; ++a) {
+                    double d = (double)(i0 + a) - x;
+                    gx[a + h] = exp(-d * d * inv2s2);
+                }
+                for (int b = -h; b <= h; ++b) {
+                    double d = (double)(j0 + b) - y;
+                    gy[b + h] = exp(-d * d * inv2s2);
+                }
+                double wv_re = wt * vis[2 * rc + 0];
+                double wv_im = wt * vis[2 * rc + 1];
+                for (int ip = 0; ip < n_pix; ++ip) {
+                    int64_t pp = pix_p[ip] - n / 2, qq = pix_q[ip] - n / 2;
+                    double kx_re = 0.0, kx_im = 0.0, ky_re = 0.0, ky_im = 0.0;
+                    for (int a = -h; a <= h; ++a) {
+                        int64_t t = ((i0 + a - n / 2) * pp) % n;
+                        if (t < 0) t += n;
+                        kx_re += gx[a + h] * ct[t];
+                        kx_im += gx[a + h] * st[t];
+                    }
+                    for (int b = -h; b <= h; ++b) {
+                        int64_t t = ((j0 + b - n / 2) * qq) % n;
+                        if (t < 0) t += n;
+                        ky_re += gy[b + h] * ct[t];
+                        ky_im += gy[b + h] * st[t];
+                    }
+                    const double *e = wk + 2 * ((size_t)ip * n_w + k);
+                    double k_re = kx_re * ky_re - kx_im * ky_im;
+                    double k_im = kx_re * ky_im + kx_im * ky_re;
+                    double z_re = k_re * e[0] - k_im * e[1];
+                    double z_im = k_re * e[1] + k_im * e[0];
+                    acc[2 * ip + 0] += wv_re * z_re - wv_im * z_im;
+                    acc[2 * ip + 1] += wv_re * z_im + wv_im * z_re;
+                }
+            }
+        }
+    }
+    for (int ip = 0; ip < n_pix; ++ip) { out[2 * ip] = 0.0; out[2 * ip + 1] = 0.0; }
+    for (int64_t bi = 0; bi < n_blocks; ++bi)
+        for (int ip = 0; ip < n_pix; ++ip) {
+            out[2 * ip + 0] += part[(size_t)bi * 2 * n_pix + 2 * ip + 0];
+            out[2 * ip + 1] += part[(size_t)bi * 2 * n_pix + 2 * ip + 1];
+        }
+    free(part);
+    free(wk);
+    free(st);
+    free(ct);
+    return 0;
+}

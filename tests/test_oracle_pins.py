@@ -1,0 +1,327 @@
+"""Pins of the FP64 oracle against things other than itself: brute-force transforms,
+closed forms, invariants and error bounds (De Rubeis et al., Sec. 2, Eqs. 1-3).
+
+A plausible slip anywhere in the oracle -- a sign in the transform, the origin
+at N/2, the plane index, the kernel argument, a dropped weight, the stable
+n - 1 -- fails at least one of these."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_07321_amd import synth
+from tests import pinlib
+
+SIG = 0.9
+
+
+def _inputs(uvw, vis, wts=None, flags=None, freq=None):
+    return oracle.Inputs.make(uvw, freq, vis, wts, flags)
+
+
+def _raw(inp, prm):
+    prm.grid_correct = False
+    prm.normalize = False
+    return oracle.image(inp, prm)["raw"][0]
+
+
+# ---------------------------------------------------------------- P1, P2: transform
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_fft_matches_direct_dft(n):
+    g = synth.random_planes(2, n, seed=n)
+    F = oracle.fft_planes(g)
+    for k in range(2):
+        ref = pinlib.direct_centred_idft(g[k])
+        assert np.linalg.norm(F[k] - ref) / np.linalg.norm(ref) < 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_fft_parseval(n):
+    g = synth.random_planes(3, n, seed=11)
+    F = oracle.fft_planes(g)
+    for k in range(3):
+        lhs = np.sum(np.abs(F[k]) ** 2)
+        rhs = n * n * np.sum(np.abs(g[k]) ** 2)
+        assert abs(lhs - rhs) / rhs < 1e-13
+
+
+def test_fft_single_cell_is_fringe():
+    # g = delta at (j, i) -> F[q,p] = exp(2 pi i ((i-N/2)(p-N/2) + (j-N/2)(q-N/2))/N)
+    n, i, j = 32, 21, 6
+    g = np.zeros((1, n, n), complex)
+    g[0, j, i] = 1.0
+    F = oracle.fft_planes(g)[0]
+    c = np.arange(n) - n / 2
+    ref = np.exp(2j * np.pi * ((i - n / 2) * c[None, :] + (j - n / 2) * c[:, None]) / n)
+    assert np.abs(F - ref).max() < 1e-13
+
+
+# ---------------------------------------------------------------- P3, single-visibility grid
+def test_grid_single_visibility_footprint():
+    n, cell, S = 64, 1.0 / 100, 7
+    uvw = np.array([[12.34567, -8.7654, 5.0]])
+    vis = np.array([[0.3 - 0.8j]])
+    wts = np.array([[1.7]])
+    prm = oracle.Params(n, 1, S, cell, SIG)
+    g, cnt = oracle.grid(_inputs(uvw, vis, wts), prm, 5.0, 5.0)
+    x, y = pinlib.positions(uvw, n, cell)
+    i0, j0 = int(math.floor(x[0] + 0.5)), int(math.floor(y[0] + 0.5))
+    ref = np.zeros((n, n), complex)
+    for b in range(-3, 4):
+        for a in range(-3, 4):
+            ref[j0 + b, i0 + a] = 1.7 * vis[0, 0] * pinlib.gauss(i0 + a - x[0], SIG) * \
+                pinlib.gauss(j0 + b - y[0], SIG)
+    assert np.abs(g[0] - ref).max() < 1e-15
+    assert cnt["n_used"] == 1 and cnt["sum_w"] == 1.7
+
+
+def test_grid_sum_invariant(config0):
+    ds = config0
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    inp = _inputs(ds.uvw, ds.vis, ds.weights)
+    wmin, wmax = oracle.w_range(inp, prm)
+    g, _ = oracle.grid(inp, prm, wmin, wmax)
+    x, y = pinlib.positions(ds.uvw, ds.grid_n, ds.cell_rad)
+    k, _ = pinlib.planes(ds.uvw[:, 2], wmin, wmax, ds.n_wplanes)
+    a = np.arange(-3, 4)
+    i0 = np.floor(x + 0.5)
+    j0 = np.floor(y + 0.5)
+    sx = pinlib.gauss(i0[:, None] + a[None, :] - x[:, None], SIG).sum(1)
+    sy = pinlib.gauss(j0[:, None] + a[None, :] - y[:, None], SIG).sum(1)
+    contrib = ds.weights[:, 0] * ds.vis[:, 0] * sx * sy
+    for kk in range(ds.n_wplanes):
+        ref = contrib[k == kk].sum()
+        got = g[kk].sum()
+        assert abs(got - ref) <= 1e-13 * max(1.0, np.abs(contrib[k == kk]).sum())
+    # planes are populated roughly evenly for an Earth-rotation track
+    assert all(np.any(k == kk) for kk in range(ds.n_wplanes))
+
+
+# ---------------------------------------------------------------- P4: pure fringe
+def test_pure_fringe_closed_form():
+    # N dl = 1/2 exactly, so x = u/2 + N/2 is exact for even u: the visibility sits on a cell
+    n, cell, S = 64, 1.0 / 128, 7
+    u, v, w = 2.0 * 9, 2.0 * -13, 37.5
+    inp = _inputs(np.array([[u, v, w]]), np.array([[1.0 + 0j]]))
+    A = _raw(inp, oracle.Params(n, 4, S, cell, SIG))
+    c = (np.arange(n) - n / 2)
+    l = c * cell
+    nu = c / n
+    a = np.arange(-3, 4)
+    cd = (pinlib.gauss(a, SIG)[None, :] * np.cos(2 * np.pi * a[None, :] * nu[:, None])).sum(1)
+    nm1 = np.sqrt(1 - l[None, :] ** 2 - l[:, None] ** 2) - 1
+    ref = np.exp(2j * np.pi * (u * l[None, :] + v * l[:, None] + w * nm1)) * cd[None, :] * cd[:, None]
+    assert np.abs(A - ref).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P5: flat image
+def test_flat_image_from_zero_spacing():
+    n, cell, S = 64, 1.0 / 200, 7
+    inp = _inputs(np.array([[0.0, 0.0, 0.0]]), np.array([[1.0 + 0j]]))
+    prm = oracle.Params(n, 1, S, cell, SIG)
+    A = _raw(inp, oracle.Params(n, 1, S, cell, SIG))
+    nu = (np.arange(n) - n / 2) / n
+    a = np.arange(-3, 4)
+    cd = (pinlib.gauss(a, SIG)[None, :] * np.cos(2 * np.pi * a[None, :] * nu[:, None])).sum(1)
+    assert np.abs(A - cd[None, :] * cd[:, None]).max() < 1e-13
+    D = oracle.image(inp, prm)["image"][0]
+    # corrected by the continuous transform C: 1 within (1+e)^2 - 1 in the inner half
+    eps = np.abs(cd / pinlib.c_closed_form(nu, S, SIG) - 1.0)
+    inner = np.abs(nu) <= 0.25
+    bound = (1 + eps[inner][None, :]) * (1 + eps[inner][:, None]) - 1
+    assert np.all(np.abs(D[np.ix_(inner, inner)] - 1.0) <= bound * 1.0001 + 1e-14)
+
+
+# ---------------------------------------------------------------- P6: unit point source
+def test_unit_source_at_phase_centre(config0):
+    ds = config0
+    vis = np.ones_like(ds.vis)                    # what Eq. 1 gives for S = 1 at l = m = 0
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    D = oracle.image(_inputs(ds.uvw, vis, ds.weights), prm)["image"][0]
+    eps = pinlib.kernel_eps(ds.support, SIG, 0.0, n_nu=1)
+    assert abs(D[128, 128] - 1.0) <= (2 * eps + eps * eps) * 1.1
+    assert eps < 1e-3
+
+
+# ---------------------------------------------------------------- P7: permutation, linearity
+def test_permutation_and_linearity(config0):
+    ds = config0
+    prm = lambda: oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(ds.n_rows)
+    A = _raw(_inputs(ds.uvw, ds.vis, ds.weights), prm())
+    Ap = _raw(_inputs(ds.uvw[perm], ds.vis[perm], ds.weights[perm]), prm())
+    assert np.linalg.norm(A - Ap) / np.linalg.norm(A) < 1e-13
+    v2 = (rng.standard_normal(ds.vis.shape) + 1j * rng.standard_normal(ds.vis.shape))
+    A2 = _raw(_inputs(ds.uvw, v2, ds.weights), prm())
+    Al = _raw(_inputs(ds.uvw, 0.7 * ds.vis - 1.3j * v2, ds.weights), prm())
+    ref = 0.7 * A - 1.3j * A2
+    assert np.linalg.norm(Al - ref) / np.linalg.norm(ref) < 1e-13
+
+
+# ---------------------------------------------------------------- P8, P9: error bounds vs DFT
+def _inner_pixels(n, step):
+    c = np.arange(n // 4, 3 * n // 4 + 1, step)
+    q, p = np.meshgrid(c, c, indexing="ij")
+    return q.ravel(), p.ravel()
+
+
+def test_against_quantised_and_exact_dft(config0):
+    ds = config0
+    sub = slice(0, None, 8)                      # 3,968 measurements
+    uvw, vis, wts = ds.uvw[sub], ds.vis[sub, 0], ds.weights[sub, 0]
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    out = oracle.image(_inputs(uvw, vis, wts), prm)
+    D = out["image"][0]
+    st = out["stats"][0]
+    q, p = _inner_pixels(ds.grid_n, 8)
+    Dq = pinlib.quantised_dft(uvw, vis, wts, st["w_min"], st["w_max"], ds.n_wplanes,
+                              ds.grid_n, ds.cell_rad, q, p)
+    eps = pinlib.kernel_eps(ds.support, SIG, 0.25)
+    amp = (wts * np.abs(vis)).sum() / wts.sum()
+    err_q = np.abs(D[q, p] - Dq)
+    assert err_q.max() <= (2 * eps + eps * eps) * amp * 1.1
+    assert err_q.max() > 0.0
+    # w quantisation: |D_q - D| <= 2 pi (dw/2) |n - 1| * sum W|V| / sum W
+    De = pinlib.exact_dft(uvw, vis, wts, ds.grid_n, ds.cell_rad, q, p)
+    dw = (st["w_max"] - st["w_min"]) / ds.n_wplanes
+    l = (p - ds.grid_n / 2) * ds.cell_rad
+    m = (q - ds.grid_n / 2) * ds.cell_rad
+    nm1 = np.abs(np.sqrt(1 - l * l - m * m) - 1)
+    assert np.all(np.abs(Dq - De) <= 2 * np.pi * dw / 2 * nm1 * amp * 1.0001 + 1e-14)
+
+
+def test_sources_recovered(config0):
+    ds = config0
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    D = oracle.image(_inputs(ds.uvw, ds.vis, ds.weights), prm)["image"][0]
+    for l, m, f in zip(ds.sky.l, ds.sky.m, ds.sky.flux):
+        p = int(round(l / ds.cell_rad)) + 128
+        q = int(round(m / ds.cell_rad)) + 128
+        assert abs(D[q, p] - f) < 0.1 * max(f, 0.3)
+
+
+# ---------------------------------------------------------------- P10: stable n - 1
+def test_stable_n_minus_1():
+    n, cell = 512, 0.9 / 256 * math.sqrt(0.5)        # eta up to 0.81 at the corners
+    nm1, inside = oracle.n_minus_1(n, cell)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, n, (400, 2))
+    c = (np.arange(n) - n / 2) * cell
+    eta = c[idx[:, 1]] ** 2 + c[idx[:, 0]] ** 2
+    ref = pinlib.n_minus_1_ld(eta)
+    got = nm1[idx[:, 0], idx[:, 1]]
+    ok = eta > 0
+    assert np.all(np.abs(got[ok] - ref[ok]) <= 6e-16 * np.abs(ref[ok]))
+    assert got[~ok].size == 0 or np.all(got[~ok] == 0)
+    assert inside.all()
+
+
+def test_off_sphere_pixels_are_zero():
+    # dl large enough that the corners have l^2 + m^2 >= 1
+    n, cell = 16, 0.1
+    F = np.ones((1, n, n), complex)
+    A = oracle.wcorrect(F, 0.0, 10.0, 1, cell)
+    c = (np.arange(n) - n / 2) * cell
+    off = (c[None, :] ** 2 + c[:, None] ** 2) >= 1.0
+    assert off.any() and np.all(A[off] == 0) and np.all(A[~off] != 0)
+
+
+# ---------------------------------------------------------------- P11: grid correction
+@pytest.mark.parametrize("S,sig", [(7, 0.9), (7, 1.0), (5, 0.7), (15, 2.0)])
+def test_kernel_transform_quadrature(S, sig):
+    n = 128
+    c = oracle.kernel_transform(n, S, sig)
+    nu = (np.arange(n) - n / 2) / n
+    ref = pinlib.c_closed_form(nu, S, sig)
+    assert np.abs(c - ref).max() <= 2e-15 * np.abs(ref).max()
+    # converged: another rule agrees to the accuracy of numpy's nodes (~1e-14)
+    c2 = oracle.kernel_transform(n, S, sig, nodes=48)
+    assert np.abs(c - c2).max() <= 2e-14 * np.abs(ref).max()
+
+
+def test_kernel_width_reading():
+    # sigma = 0.9 cells keeps the worst per-visibility error below 1e-3 over |nu| <= 1/4
+    assert pinlib.kernel_eps(7, 0.9, 0.25) < 1e-3
+    assert pinlib.kernel_eps(7, 1.0, 0.25) > pinlib.kernel_eps(7, 0.9, 0.25)
+
+
+# ---------------------------------------------------------------- O2/O3: counts, planes
+def test_validity_counts():
+    n, cell = 64, 1.0 / 100
+    du = 1.0 / (n * cell)
+    uvw = np.array([[10.0, 5.0, 1.0],          # used
+                    [10.0, 5.0, 2.0],          # flagged
+                    [np.nan, 5.0, 1.0],        # non-finite u
+                    [10.0, 5.0, 1.0],          # weight 0
+                    [(n / 2 - 3) * du, 0.0, 1.0],   # i0 = N-3 > N-1-h: off the grid
+                    [(n / 2 - 4) * du, 0.0, 3.0],   # i0 = N-4 = N-1-h: last that fits
+                    [-(n / 2 - 3) * du, 0.0, 1.5],  # i0 = 3 = h: first that fits
+                    [10.0, 5.0, 1.0]])         # vis inf
+    vis = np.array([1, 1, 1, 1, 1, 1, 1, np.inf + 0j], complex)[:, None]
+    wts = np.array([1, 1, 1, 0, 1, 1, 1, 1], float)[:, None]
+    fl = np.array([0, 1, 0, 0, 0, 0, 0, 0], np.uint8)[:, None]
+    inp = _inputs(uvw, vis, wts, fl)
+    prm = oracle.Params(n, 2, 7, cell, SIG)
+    wmin, wmax = oracle.w_range(inp, prm)
+    assert (wmin, wmax) == (1.0, 3.0)
+    _, cnt = oracle.grid(inp, prm, wmin, wmax)
+    assert cnt == {"n_used": 3, "n_flagged": 1, "n_dropped": 4, "sum_w": 3.0}
+    # a caller-given range that excludes w = 3 drops it too
+    _, cnt2 = oracle.grid(inp, prm, 0.0, 2.0)
+    assert cnt2["n_used"] == 2 and cnt2["n_dropped"] == 5
+
+
+def test_plane_rule_and_degenerate_range():
+    k, wk = pinlib.planes(np.array([0.0, 0.999, 1.0, 3.99, 4.0]), 0.0, 4.0, 4)
+    assert list(k) == [0, 0, 1, 3, 3] and list(wk) == [0.5, 0.5, 1.5, 3.5, 3.5]
+    assert list(oracle.plane_w(np.arange(4), 0.0, 4.0, 4)) == [0.5, 1.5, 2.5, 3.5]
+    assert list(oracle.plane_w(np.arange(2), 2.0, 2.0, 2)) == [2.0, 2.0]
+
+
+def test_empty_input_gives_zero_image():
+    inp = _inputs(np.zeros((0, 3)), np.zeros((0, 1), complex))
+    out = oracle.image(inp, oracle.Params(32, 2, 7, 0.01, SIG))
+    assert np.all(out["image"] == 0) and out["stats"][0]["n_used"] == 0
+
+
+# ---------------------------------------------------------------- sharding and sampling
+def test_plane_shards_sum_to_whole(config0):
+    ds = config0
+    inp = _inputs(ds.uvw, ds.vis, ds.weights)
+    full = _raw(inp, oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG))
+    wmin, wmax = oracle.w_range(inp, oracle.Params(ds.grid_n, 8, 7, ds.cell_rad))
+    parts = 0
+    for lo, hi in [(0, 3), (3, 8)]:
+        prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG,
+                            w_min=wmin, w_max=wmax, plane_lo=lo, plane_hi=hi)
+        parts = parts + _raw(inp, prm)
+    assert np.linalg.norm(parts - full) / np.linalg.norm(full) < 1e-13
+
+
+def test_pixel_evaluator_matches_mesh_path(config0):
+    ds = config0
+    inp = _inputs(ds.uvw, ds.vis, ds.weights)
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG)
+    A = _raw(inp, prm)
+    rng = np.random.default_rng(9)
+    q = rng.integers(0, ds.grid_n, 12)
+    p = rng.integers(0, ds.grid_n, 12)
+    got = oracle.pixels(inp, prm, q, p)
+    assert np.abs(got - A[q, p]).max() < 1e-12 * np.abs(A).max()
+
+
+def test_channels_cube_and_metres():
+    # uvw in metres with per-channel frequencies equals uvw pre-scaled per channel
+    rng = np.random.default_rng(4)
+    uvw_m = rng.uniform(-300, 300, (300, 3))
+    freq = np.array([120e6, 150e6, 180e6])
+    vis = rng.standard_normal((300, 3)) + 1j * rng.standard_normal((300, 3))
+    prm = oracle.Params(64, 4, 7, 0.2 / 64, SIG, per_channel=True)
+    cube = oracle.image(oracle.Inputs.make(uvw_m, freq, vis), prm)["image"]
+    for c in range(3):
+        one = oracle.image(oracle.Inputs.make(uvw_m * (freq[c] / oracle.C_LIGHT), None,
+                                              vis[:, c:c + 1]),
+                           oracle.Params(64, 4, 7, 0.2 / 64, SIG))["image"][0]
+        assert np.linalg.norm(cube[c] - one) <= 1e-13 * np.linalg.norm(one)
