@@ -1,0 +1,188 @@
+/*
+ * wsg.h -- w-stacking gridder/imager for AMD MI355X (gfx950), C ABI.
+ *
+ * The library images radio-interferometer visibilities with the w-stacking
+ * method described in Sec. 2 of De Rubeis et al., "Accelerating radio
+ * astronomy imaging with RICK" (arXiv 2411.07321):
+ *
+ *   1. every visibility (u,v,w in wavelengths, Eq. 1) goes to the closest of
+ *      N_w w-planes and is convolved onto the N x N (u,v) mesh of that plane
+ *      with a kernel G of support S (Eq. 3);
+ *   2. every plane is inverse Fourier transformed (2D, complex-to-complex);
+ *   3. each plane is multiplied by the phase screen exp(2 pi i w_k (n - 1)),
+ *      n = sqrt(1 - l^2 - m^2), and the planes are summed (Eq. 2); the real
+ *      part is the dirty image.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - mesh cell i has u_i = (i - N/2) du, du = 1/(N * cell_rad); image pixel p
+ *     has l_p = (p - N/2) * cell_rad; arrays are row-major with the u / l
+ *     index fastest: grid[k][j][i], image[q][p];
+ *   - a visibility sits at x = u * (N * cell_rad) + N/2 (no fused multiply-
+ *     add), nearest cell i0 = floor(x + 1/2), footprint i0-h .. i0+h with
+ *     h = (S-1)/2; G(d) = exp(-d^2 / (2 sigma^2)), separable in u and v;
+ *   - planes are N_w cells of width dw = (w_max - w_min)/N_w over [w_min,
+ *     w_max]; k = min(N_w-1, floor((w - w_min)/dw)), w_k = w_min + (k+1/2) dw;
+ *     dw = 0 puts everything on plane 0 at w_0 = w_min;
+ *   - the transform is F[q][p] = sum g[j][i] exp(+2 pi i ((i-N/2)(p-N/2) +
+ *     (j-N/2)(q-N/2))/N), unnormalised;
+ *   - n - 1 is formed as -eta / (1 + sqrt(1 - eta)), eta = l^2 + m^2; pixels
+ *     with eta >= 1 are 0;
+ *   - image = Re(A) / (sum W * C(nu_p) * C(nu_q)), C the continuous transform
+ *     of the truncated kernel, nu_p = (p - N/2)/N; each factor is switched by
+ *     WSG_GRID_CORRECT / WSG_NORMALIZE; sum W = 0 gives a zero image.
+ *
+ * Validity: a visibility is used iff it is unflagged, its weight is finite
+ * and > 0, u, v, w and V are finite, its footprint lies inside the mesh and
+ * w lies in [w_min, w_max].  Anything else is skipped and counted, never an
+ * error.
+ *
+ * Ownership: the caller owns every input and output buffer; the library never
+ * frees or keeps a caller pointer after the call returns (an enqueue-only call
+ * reads them until the stream reaches the end of its work).  The library owns
+ * its workspace (bins, records, plane stack, tables), keeps it in the context
+ * between calls and frees it in wsg_destroy.
+ *
+ * Errors: no C++ exception crosses this interface.  On error the outputs are
+ * unspecified and *stats is not written.  wsg_last_error() gives detail.
+ *
+ * Threads: a context is used by one host thread at a time; several contexts
+ * per device may be used concurrently from different threads.
+ */
+#ifndef WSG_H
+#define WSG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wsg_ctx wsg_ctx;
+typedef int32_t wsg_status;
+
+enum {
+    WSG_OK = 0,
+    WSG_EINVAL = -1,        /* bad parameter, NULL required pointer, bad memory space      */
+    WSG_ENOMEM = -2,        /* workspace above the context's budget or device memory        */
+    WSG_EDEVICE = -3,       /* HIP runtime error (no device, launch failure, ...)           */
+    WSG_EBUSY = -4,         /* the context still has enqueued work it must not overlap      */
+    WSG_EUNSUPPORTED = -5   /* valid but outside what this build supports (e.g. N > 4096)   */
+};
+
+/* Arithmetic of the mesh, the transform and the phase screen. */
+enum {
+    WSG_PREC_F64 = 0,          /* complex128 mesh and transform, FP64 phase, FP64 image      */
+    WSG_PREC_F32_PHASE64 = 1,  /* complex64 mesh and transform, FP64 phase and image sum     */
+    WSG_PREC_F32_PHASE32 = 2   /* complex64 mesh and transform, FP32 phase, FP64 image sum   */
+};
+
+enum { WSG_MEM_HOST = 0, WSG_MEM_DEVICE = 1 };
+
+enum {
+    WSG_GRID_CORRECT = 1u,   /* divide by C(nu_p) C(nu_q)                                    */
+    WSG_NORMALIZE = 2u,      /* divide by sum W                                              */
+    WSG_PER_CHANNEL = 4u,    /* one image per channel (a cube) instead of one image          */
+    WSG_NAIVE_NM1 = 8u       /* FP32 phase only: sqrt(1-eta)-1 instead of the stable form    */
+};
+
+typedef struct {
+    int32_t grid_n;        /* N: power of two, 16 .. 4096                                      */
+    int32_t n_wplanes;     /* N_w >= 1                                                         */
+    int32_t support;       /* S: odd, 1 .. 15, S <= N                                          */
+    int32_t precision;     /* WSG_PREC_*                                                       */
+    double cell_rad;       /* image pixel size dl in radians (> 0, finite)                     */
+    double kernel_sigma;   /* Gaussian width in cells (> 0); 0.9 is the reading for S = 7      */
+    double w_min, w_max;   /* plane range; both NaN: taken from the data                       */
+    int32_t plane_lo;      /* image only planes [plane_lo, plane_hi) of N_w (both 0: all);    */
+    int32_t plane_hi;      /*   needs a given w range, so that every shard agrees             */
+    uint32_t flags;        /* WSG_GRID_CORRECT | WSG_NORMALIZE | ...                           */
+    int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64/128 */
+} wsg_params;
+
+typedef struct {
+    int64_t n_rows;          /* rows (baseline x time samples)                                */
+    int32_t n_chan;          /* channels per row (>= 1)                                       */
+    int32_t mem;             /* WSG_MEM_* of uvw, vis, weights and flags                      */
+    const double *uvw;       /* [n_rows][3]; wavelengths if freq_hz is NULL, else metres      */
+    const double *freq_hz;   /* HOST array [n_chan] or NULL                                   */
+    const void *vis;         /* [n_rows][n_chan] interleaved (re, im): complex128 if F64,    */
+                             /*   else complex64                                               */
+    const void *weights;     /* [n_rows][n_chan]: double if F64 else float; NULL = all 1     */
+    const uint8_t *flags;    /* [n_rows][n_chan]: nonzero = skip; NULL = none                 */
+} wsg_vis;
+
+typedef struct {
+    int64_t n_used, n_flagged, n_dropped;
+    double sum_w, w_min, w_max;
+    float ms_total;          /* device time of the call (hipEvents), 0 if not measured        */
+} wsg_stats;
+
+/* ---------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------- */
+/* Bind a context to HIP device `device`.  *out is NULL on error. */
+wsg_status wsg_create(int device, wsg_ctx **out);
+/* Wait for the context's work, free its workspace and the context.  NULL is a no-op. */
+void wsg_destroy(wsg_ctx *ctx);
+const char *wsg_strerror(wsg_status s);
+/* Detail of the last failure on this context (never NULL). */
+const char *wsg_last_error(const wsg_ctx *ctx);
+/* Limit the context's workspace to `bytes` (0 = no limit); larger jobs fail with ENOMEM. */
+wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes);
+
+/* ---------------------------------------------------------------------------
+ * Host-side checks (no device needed)
+ * ------------------------------------------------------------------------- */
+/* Validate parameters and input description (pointers need not be dereferenceable). */
+wsg_status wsg_check(const wsg_params *p, const wsg_vis *v);
+/* Device workspace in bytes that wsg_image needs for this job (inputs staged
+ * from host memory included), for admission control. */
+wsg_status wsg_footprint(const wsg_params *p, const wsg_vis *v, uint64_t *bytes);
+/* Number of images the job produces: n_chan with WSG_PER_CHANNEL, else 1. */
+int32_t wsg_n_images(const wsg_params *p, const wsg_vis *v);
+
+/* ---------------------------------------------------------------------------
+ * The method, end to end (Sec. 2: gridding, transform, w-correction and sum)
+ * ------------------------------------------------------------------------- */
+/*
+ * image: [n_images][N][N] double, row-major (p fastest), in memory space
+ *        image_mem; written completely.
+ * stream: hipStream_t to run on (NULL: the context's own stream).
+ * stats:  NULL, or an array of n_images entries; when given, the call waits
+ *         for the device and fills it.  With stats NULL and a device image the
+ *         call may return before the work is done; synchronise `stream`.
+ */
+wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
+                     double *image, int32_t image_mem, void *stream, wsg_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Stages, separately (for checking each step)
+ * ------------------------------------------------------------------------- */
+/* Eq. 3 on the nearest plane: grid [n_images][hi-lo][N][N] complex (complex128
+ * for F64, else complex64), overwritten. */
+wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
+                          void *grid, int32_t mem, void *stream, wsg_stats *stats);
+/* Centred unnormalised inverse transform of n_planes N x N planes, in place. */
+wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_t n_planes,
+                         int32_t mem, void *stream);
+/* w-correction and plane sum of n_planes transformed planes that hold planes
+ * plane_lo .. plane_lo+n_planes-1 of the range [w_min, w_max] (Eq. 2), then
+ * the post factors with sum_w: image [N][N] double. */
+wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *planes,
+                              int64_t n_planes, double w_min, double w_max, double sum_w,
+                              double *image, int32_t mem, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Tuning
+ * ------------------------------------------------------------------------- */
+/* Time the binning tile sizes on this job's data and store the best per
+ * (N, N_w, S, precision, visibility-count decade) in the context (and in the
+ * text file cache_path if not NULL).  *best_tile receives the choice. */
+wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
+                        const char *cache_path, int32_t *best_tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSG_H */

@@ -1,0 +1,487 @@
+// Binning of visibilities by (image, w-plane, uv tile): a counting sort.
+//
+// Sec. 2 of the paper buckets the visibilities of each mesh slab before the
+// convolution ("an array is created for each slab").  Here the buckets are
+// square uv tiles of every w-plane, so that the gridding kernel can keep one
+// tile in LDS.  A visibility whose footprint crosses a tile edge is recorded
+// in every tile it touches (at most four); each tile then owns its cells and
+// writes them once, without global atomics.
+//
+// Pass structure (one thread per (row, channel) element, grid-stride loops
+// whose stride is a multiple of n_chan so that each thread stays on one
+// channel and can keep per-image partial sums in registers):
+//   k_prep     validity of every element, per-image w range and counts
+//   k_finalize plane geometry per image (given range or the data's)
+//   k_count    per-bin counts, n_used and sum of weights
+//   scan       bin offsets
+//   k_scatter  compact records into their bins
+#include "wsg_internal.h"
+
+#include <algorithm>
+
+namespace wsg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ unsigned long long order_key(double d) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// x = u * scale + half with two roundings (no contraction), as the method states.
+__device__ __forceinline__ double mesh_coord(double u, double scale, double half) {
+#pragma clang fp contract(off)
+    double t = u * scale;
+    return t + half;
+}
+
+__device__ __forceinline__ bool footprint_fits(double x, int N, int h, int &i0) {
+    double f = floor(x + 0.5);
+    if (!(f >= (double)h && f <= (double)(N - 1 - h))) return false;
+    i0 = (int)f;
+    return true;
+}
+
+template <typename VT, typename WT>
+struct ElemIO;
+
+template <>
+struct ElemIO<double, double> {
+    static __device__ __forceinline__ void load(const void *vis, const void *wts, int64_t e,
+                                                double &vr, double &vi, double &w) {
+        const double *v = (const double *)vis;
+        vr = v[2 * e];
+        vi = v[2 * e + 1];
+        w = wts ? ((const double *)wts)[e] : 1.0;
+    }
+};
+template <>
+struct ElemIO<float, float> {
+    static __device__ __forceinline__ void load(const void *vis, const void *wts, int64_t e,
+                                                double &vr, double &vi, double &w) {
+        const float2 v = ((const float2 *)vis)[e];
+        vr = (double)v.x;
+        vi = (double)v.y;
+        w = wts ? (double)((const float *)wts)[e] : 1.0;
+    }
+};
+
+__device__ __forceinline__ bool is_finite(double a) { return isfinite(a); }
+
+// Every test except the w range (O2 of the method's reading).
+template <typename VT>
+__device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, const void *vis,
+                                       const void *wts, const uint8_t *flags, int64_t e,
+                                       int64_t r, int c, bool &flagged, double &w_out) {
+    flagged = flags && flags[e];
+    if (flagged) return false;
+    double vr, vi, wt;
+    ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
+    if (!(wt > 0.0) || !is_finite(wt)) return false;
+    double sc = g.chan_scale[c];
+    double u = uvw[3 * r] * sc, v = uvw[3 * r + 1] * sc, w = uvw[3 * r + 2] * sc;
+    if (!is_finite(u) || !is_finite(v) || !is_finite(w)) return false;
+    if (!is_finite(vr) || !is_finite(vi)) return false;
+    int i0, j0;
+    if (!footprint_fits(mesh_coord(u, g.scale, g.half), g.N, g.h, i0)) return false;
+    if (!footprint_fits(mesh_coord(v, g.scale, g.half), g.N, g.h, j0)) return false;
+    w_out = w;
+    return true;
+}
+
+// grid-stride geometry: stride a multiple of n_chan
+__host__ int blocks_for(int64_t n_elem, int n_chan) {
+    int64_t want = (n_elem + kThreads - 1) / kThreads;
+    int64_t cap = 4096;
+    int64_t b = std::min<int64_t>(std::max<int64_t>(want, 1), cap);
+    // make b * kThreads a multiple of n_chan
+    int64_t g = n_chan;
+    int64_t t = kThreads;
+    while (t % 2 == 0 && g % 2 == 0) { t /= 2; g /= 2; }
+    // after removing common factors of two, b must be a multiple of the odd part
+    // of n_chan not shared with kThreads (kThreads is a power of two)
+    int64_t need = g;
+    b = ((b + need - 1) / need) * need;
+    return (int)b;
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__restrict__ uvw,
+                                                   const void *__restrict__ vis,
+                                                   const void *__restrict__ wts,
+                                                   const uint8_t *__restrict__ flags,
+                                                   uint8_t *__restrict__ mask, ImgState *st) {
+    __shared__ unsigned long long s_min[256], s_max[256], s_flag[256], s_valid[256];
+    const int n_img = g.n_img;
+    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
+        s_min[i] = ~0ull;
+        s_max[i] = 0ull;
+        s_flag[i] = 0;
+        s_valid[i] = 0;
+    }
+    __syncthreads();
+    const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long kmin = ~0ull, kmax = 0ull, nf = 0, nv = 0;
+    const int c = (int)(e0 % g.n_chan);
+    for (int64_t e = e0; e < n_elem; e += stride) {
+        int64_t r = e / g.n_chan;
+        bool fl;
+        double w;
+        bool ok = valid0<VT>(g, uvw, vis, wts, flags, e, r, c, fl, w);
+        mask[e] = ok ? 1 : 0;
+        nf += fl ? 1 : 0;
+        if (ok) {
+            ++nv;
+            unsigned long long k = order_key(w);
+            kmin = k < kmin ? k : kmin;
+            kmax = k > kmax ? k : kmax;
+        }
+    }
+    const int img = (n_img > 1) ? c : 0;
+    if (n_img == 1) {
+        // wave reduction, then one LDS atomic per wave
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned long long a = __shfl_xor(kmin, off);
+            unsigned long long b = __shfl_xor(kmax, off);
+            kmin = a < kmin ? a : kmin;
+            kmax = b > kmax ? b : kmax;
+            nf += __shfl_xor(nf, off);
+            nv += __shfl_xor(nv, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&s_min[0], kmin);
+            atomicMax(&s_max[0], kmax);
+            atomicAdd(&s_flag[0], nf);
+            atomicAdd(&s_valid[0], nv);
+        }
+    } else {
+        atomicMin(&s_min[img], kmin);
+        atomicMax(&s_max[img], kmax);
+        atomicAdd(&s_flag[img], nf);
+        atomicAdd(&s_valid[img], nv);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
+        if (s_valid[i]) {
+            atomicMin(&st[i].wmin_key, s_min[i]);
+            atomicMax(&st[i].wmax_key, s_max[i]);
+            atomicAdd(&st[i].n_valid0, s_valid[i]);
+        }
+        if (s_flag[i]) atomicAdd(&st[i].n_flagged, s_flag[i]);
+    }
+}
+
+__global__ void k_finalize(JobGeom g, ImgState *st) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n_img) return;
+    ImgState &s = st[i];
+    double lo, hi;
+    if (g.range_given) {
+        lo = g.w_min_given;
+        hi = g.w_max_given;
+    } else if (s.n_valid0 > 0) {
+        lo = key_value(s.wmin_key);
+        hi = key_value(s.wmax_key);
+    } else {
+        lo = 0.0;
+        hi = 0.0;
+    }
+    s.w_min = lo;
+    s.w_max = hi;
+    s.dw = (hi - lo) / (double)g.n_w;
+}
+
+__device__ __forceinline__ int plane_of(double w, double w_min, double dw, int n_w) {
+    if (dw == 0.0) return 0;
+    double t = floor((w - w_min) / dw);
+    int k = (int)t;
+    return k > n_w - 1 ? n_w - 1 : k;
+}
+
+struct Placed {
+    int k;
+    int i0, j0;
+    double x, y;
+};
+
+// A valid element inside the w range: its plane, nearest cell and position.
+__device__ __forceinline__ bool place(const JobGeom &g, const ImgState &s, const double *uvw,
+                                      int64_t r, int c, Placed &pl) {
+    double sc = g.chan_scale[c];
+    double w = uvw[3 * r + 2] * sc;
+    if (!(w >= s.w_min && w <= s.w_max)) return false;
+    double u = uvw[3 * r] * sc, v = uvw[3 * r + 1] * sc;
+    pl.x = mesh_coord(u, g.scale, g.half);
+    pl.y = mesh_coord(v, g.scale, g.half);
+    pl.i0 = (int)floor(pl.x + 0.5);
+    pl.j0 = (int)floor(pl.y + 0.5);
+    pl.k = plane_of(w, s.w_min, s.dw, g.n_w);
+    return true;
+}
+
+__device__ __forceinline__ int64_t bin_base(const JobGeom &g, int img, int kl) {
+    return ((int64_t)img * g.n_pl + kl) * (int64_t)g.NT * g.NT;
+}
+
+template <bool F64W>
+__global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
+                                                    const void *__restrict__ wts,
+                                                    const uint8_t *__restrict__ mask,
+                                                    ImgState *st, uint32_t *__restrict__ counts) {
+    __shared__ unsigned long long s_used[256];
+    __shared__ double s_sumw[256];
+    const int n_img = g.n_img;
+    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
+        s_used[i] = 0;
+        s_sumw[i] = 0.0;
+    }
+    __syncthreads();
+    const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(e0 % g.n_chan);
+    const int img = (n_img > 1) ? c : 0;
+    const ImgState s = st[img];
+    unsigned long long nu = 0;
+    double sw = 0.0;
+    for (int64_t e = e0; e < n_elem; e += stride) {
+        if (!mask[e]) continue;
+        int64_t r = e / g.n_chan;
+        Placed pl;
+        if (!place(g, s, uvw, r, c, pl)) continue;
+        ++nu;
+        sw += wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
+        int kl = pl.k - g.plane_lo;
+        if (kl < 0 || kl >= g.n_pl) continue;
+        int64_t base = bin_base(g, img, kl);
+        int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
+        int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&counts[base + (int64_t)ty * g.NT + tx], 1u);
+    }
+    if (n_img == 1) {
+        for (int off = 32; off > 0; off >>= 1) {
+            nu += __shfl_xor(nu, off);
+            sw += __shfl_xor(sw, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&s_used[0], nu);
+            atomicAdd(&s_sumw[0], sw);
+        }
+    } else {
+        atomicAdd(&s_used[img], nu);
+        atomicAdd(&s_sumw[img], sw);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
+        if (s_used[i]) {
+            atomicAdd(&st[i].n_used, s_used[i]);
+            atomicAdd(&st[i].sum_w, s_sumw[i]);
+        }
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
+                                                      const void *__restrict__ vis,
+                                                      const void *__restrict__ wts,
+                                                      const uint8_t *__restrict__ mask,
+                                                      const ImgState *st, uint32_t *cursor,
+                                                      void *__restrict__ records) {
+    const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(e0 % g.n_chan);
+    const int img = (g.n_img > 1) ? c : 0;
+    const ImgState s = st[img];
+    for (int64_t e = e0; e < n_elem; e += stride) {
+        if (!mask[e]) continue;
+        int64_t r = e / g.n_chan;
+        Placed pl;
+        if (!place(g, s, uvw, r, c, pl)) continue;
+        int kl = pl.k - g.plane_lo;
+        if (kl < 0 || kl >= g.n_pl) continue;
+        double vr, vi, wt;
+        ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
+        int64_t base = bin_base(g, img, kl);
+        int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
+        int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
+        double fx = pl.x - (double)pl.i0;
+        double fy = pl.y - (double)pl.j0;
+        if constexpr (sizeof(VT) == 8) {
+            RecF64 rec;
+            rec.fx = fx;
+            rec.fy = fy;
+            rec.re = wt * vr;
+            rec.im = wt * vi;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    uint32_t slot = atomicAdd(&cursor[base + (int64_t)ty * g.NT + tx], 1u);
+                    rec.li = pl.i0 - tx * g.T;
+                    rec.lj = pl.j0 - ty * g.T;
+                    ((RecF64 *)records)[slot] = rec;
+                }
+        } else {
+            uint32_t qx = (uint32_t)fmin((fx + 0.5) * 16777216.0 + 0.5, 16777215.0);
+            uint32_t qy = (uint32_t)fmin((fy + 0.5) * 16777216.0 + 0.5, 16777215.0);
+            float wr = (float)wt * (float)vr;
+            float wi = (float)wt * (float)vi;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    uint32_t slot = atomicAdd(&cursor[base + (int64_t)ty * g.NT + tx], 1u);
+                    RecF32 rec;
+                    rec.px = ((uint32_t)(pl.i0 - tx * g.T + g.h) << kFracBits) | qx;
+                    rec.py = ((uint32_t)(pl.j0 - ty * g.T + g.h) << kFracBits) | qy;
+                    rec.re = wr;
+                    rec.im = wi;
+                    ((RecF32 *)records)[slot] = rec;
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanBlock = 1024;   // elements per block (256 threads x 4)
+
+__global__ __launch_bounds__(256) void k_scan_block(const uint32_t *in, uint32_t *out, size_t n,
+                                                    uint32_t *block_sums) {
+    __shared__ uint32_t s[256];
+    size_t base = (size_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    uint32_t v[4];
+    uint32_t sum = 0;
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0u;
+        sum += v[i];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;   // exclusive prefix of this thread
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 255 && block_sums) block_sums[blockIdx.x] = s[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t *out, size_t n, const uint32_t *block_off) {
+    size_t base = (size_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    uint32_t add = block_off[blockIdx.x];
+    for (int i = 0; i < 4; ++i)
+        if (base + i < n) out[base + i] += add;
+}
+
+__global__ void k_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n, uint32_t chunk) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = counts[i];
+    nchunk[i] = c == 0 ? 1u : (c + chunk - 1) / chunk;
+}
+
+__global__ void k_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
+                           size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t o = item_off[i];
+    for (uint32_t c = 0; c < nchunk[i]; ++c) item_bin[o + c] = (uint32_t)i;
+}
+
+__global__ void k_post_norm(int n_img, ImgState *st, int normalize) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_img) return;
+    double sw = st[i].sum_w;
+    st[i].inv_norm = normalize ? (sw > 0.0 ? 1.0 / sw : 0.0) : 1.0;
+}
+
+}  // namespace
+
+void launch_prep(const JobGeom &g, bool f64, const double *uvw, const void *vis, const void *wts,
+                 const uint8_t *flags, uint8_t *mask, ImgState *st, hipStream_t s) {
+    int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    if (n_elem == 0) return;
+    int blocks = blocks_for(n_elem, g.n_chan);
+    if (f64)
+        k_prep<double><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, flags, mask, st);
+    else
+        k_prep<float><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, flags, mask, st);
+}
+
+void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s) {
+    k_finalize<<<(g.n_img + 63) / 64, 64, 0, s>>>(g, st);
+}
+
+void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
+                  const uint8_t *mask, ImgState *st, uint32_t *counts, hipStream_t s) {
+    int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    if (n_elem == 0) return;
+    int blocks = blocks_for(n_elem, g.n_chan);
+    if (f64)
+        k_count<true><<<blocks, kThreads, 0, s>>>(g, uvw, wts, mask, st, counts);
+    else
+        k_count<false><<<blocks, kThreads, 0, s>>>(g, uvw, wts, mask, st, counts);
+}
+
+void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
+                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
+                    void *records, hipStream_t s) {
+    int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
+    if (n_elem == 0) return;
+    int blocks = blocks_for(n_elem, g.n_chan);
+    if (f64)
+        k_scatter<double><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor, records);
+    else
+        k_scatter<float><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor, records);
+}
+
+size_t scan_tmp_elems(size_t n) {
+    size_t total = 0;
+    while (n > (size_t)kScanBlock) {
+        size_t nb = (n + kScanBlock - 1) / kScanBlock;
+        total += 2 * nb;   // block sums and their scan
+        n = nb;
+    }
+    return total + 1;
+}
+
+void launch_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp, hipStream_t s) {
+    if (n == 0) return;
+    size_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 1) {
+        k_scan_block<<<1, 256, 0, s>>>(in, out, n, nullptr);
+        return;
+    }
+    uint32_t *sums = tmp;
+    uint32_t *sums_scan = tmp + nb;
+    k_scan_block<<<(unsigned)nb, 256, 0, s>>>(in, out, n, sums);
+    launch_scan(sums, sums_scan, nb, tmp + 2 * nb, s);
+    k_scan_add<<<(unsigned)nb, 256, 0, s>>>(out, n, sums_scan);
+}
+
+void launch_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n_bins, uint32_t chunk,
+                   hipStream_t s) {
+    k_chunks<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(counts, nchunk, n_bins, chunk);
+}
+
+void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
+                     size_t n_bins, hipStream_t s) {
+    k_item_map<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(nchunk, item_off, item_bin, n_bins);
+}
+
+void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s) {
+    k_post_norm<<<(n_img + 63) / 64, 64, 0, s>>>(n_img, st, normalize ? 1 : 0);
+}
+
+}  // namespace wsg

@@ -1,0 +1,482 @@
+// 2D inverse transform of every w-plane and the w-correction (Eq. 2).
+//
+// The centred transform F[q][p] = sum g[j][i] e^{+2 pi i ((i-N/2)(p-N/2) +
+// (j-N/2)(q-N/2))/N} equals (-1)^(p+q) * IDFT2((-1)^(i+j) g) exactly when N is
+// a multiple of 4 (every supported N is), so both passes are plain
+// unnormalised inverse DFTs with sign flips folded into their loads / outputs.
+//
+// Each 1D transform is a Stockham autosort FFT: every thread keeps E = 16
+// points in registers, runs radix-16 (the first stage may use radix 2, 4 or 8)
+// butterflies there and exchanges through LDS between stages.
+//
+// Layout between the passes ("blocked"): pass 1 transforms B consecutive rows
+// of a plane X[a][b] along b and writes them back into the same region as
+// Y[a/B][b'][a%B], so pass 2, which transforms along a for B' consecutive
+// b', reads runs of B*B' contiguous elements (128 bytes for complex64) and
+// every HBM access of both passes is a full 128-byte run.
+//
+// In the imaging pipeline the gridder stores each plane transposed (G[i][j],
+// u index slow), pass 1 transforms along v (j -> q) and pass 2 along u
+// (i -> p) while it walks the planes of a strip of image rows q, multiplies by
+// the phase screen e^{2 pi i w_k (n-1)} and accumulates Re in FP64 registers;
+// the strip of the image is written once, with the post factors applied.
+#include "wsg_internal.h"
+
+namespace wsg {
+
+namespace {
+
+constexpr int E = 16;
+
+template <typename T> struct BlockRows;
+template <> struct BlockRows<float> { static constexpr int value = 4; };
+template <> struct BlockRows<double> { static constexpr int value = 2; };
+
+// transforms per workgroup: at least B, enough threads for 4 waves when N is small
+template <typename T, int N>
+struct Shape {
+    static constexpr int B = BlockRows<T>::value;
+    static constexpr int P = N / E;                  // threads per transform
+    static constexpr int want = 256 / P;
+    static constexpr int NTR0 = want > B ? want : B;
+    static constexpr int NTR = NTR0 > N ? N : NTR0;  // transforms per workgroup
+    static constexpr int THREADS = NTR * P;
+    static constexpr int NPAD = N + N / 16;           // LDS row length with padding
+};
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// first-stage radix: N = R0 * E^k
+template <int N>
+struct FirstRadix {
+    static constexpr int L = ilog2(N);
+    static constexpr int r = (L % 4 == 0) ? 16 : (1 << (L % 4));
+    static constexpr int stages = (L - ilog2(r)) / 4 + 1;
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// e^{+2 pi i idx / 16} times b, specialised for the trivial angles
+template <typename T>
+__device__ __forceinline__ C2<T> rot16(C2<T> b, int idx) {
+    const T r2 = (T)0.70710678118654752440084436210485;
+    const T c1 = (T)0.92387953251128675612818318939679;   // cos(pi/8)
+    const T s1 = (T)0.38268343236508977172845998403040;   // sin(pi/8)
+    switch (idx & 15) {
+    case 0: return b;
+    case 4: return C2<T>{-b.y, b.x};
+    case 8: return C2<T>{-b.x, -b.y};
+    case 12: return C2<T>{b.y, -b.x};
+    case 2: return C2<T>{(b.x - b.y) * r2, (b.x + b.y) * r2};
+    case 6: return C2<T>{(-b.x - b.y) * r2, (b.x - b.y) * r2};
+    case 10: return C2<T>{(b.y - b.x) * r2, (-b.x - b.y) * r2};
+    case 14: return C2<T>{(b.x + b.y) * r2, (b.y - b.x) * r2};
+    case 1: return cmul(b, C2<T>{c1, s1});
+    case 3: return cmul(b, C2<T>{s1, c1});
+    case 5: return cmul(b, C2<T>{-s1, c1});
+    case 7: return cmul(b, C2<T>{-c1, s1});
+    case 9: return cmul(b, C2<T>{-c1, -s1});
+    case 11: return cmul(b, C2<T>{-s1, -c1});
+    case 13: return cmul(b, C2<T>{s1, -c1});
+    default: return cmul(b, C2<T>{c1, -s1});   // 15
+    }
+}
+
+__host__ __device__ constexpr int bitrev(int i, int bits) {
+    int r = 0;
+    for (int k = 0; k < bits; ++k) r |= ((i >> k) & 1) << (bits - 1 - k);
+    return r;
+}
+
+// In-register inverse DFT of R points v[base + stride*s], s = 0..R-1 (R <= 16),
+// natural order in and out.
+template <typename T, int R, int STRIDE>
+__device__ __forceinline__ void dft_reg(C2<T> *v, int base) {
+    constexpr int LG = ilog2(R);
+    C2<T> x[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) x[bitrev(s, LG)] = v[base + STRIDE * s];
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len / 2;
+#pragma unroll
+        for (int i0 = 0; i0 < R; i0 += len) {
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                C2<T> a = x[i0 + k];
+                C2<T> b = rot16(x[i0 + k + half], k * (16 / len));
+                x[i0 + k] = cadd(a, b);
+                x[i0 + k + half] = csub(a, b);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[base + STRIDE * s] = x[s];
+}
+
+// One length-N inverse transform, cooperatively by the P threads of a row.
+// In:  v[m] = X[t + m*P] (m < E).  Out: v[s] = Y[t + s*P].
+// lre/lim: this transform's LDS rows (NPAD elements each).  Every thread of
+// the workgroup must call this together (it contains barriers when N > E).
+template <typename T, int N>
+__device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const C2<T> *__restrict__ tw) {
+    constexpr int P = N / E;
+    constexpr int R0 = FirstRadix<N>::r;
+    constexpr int NST = FirstRadix<N>::stages;
+    // ---- stage 1 (Ns = 1): E/R0 butterflies of radix R0 over m = u + s*(E/R0)
+#pragma unroll
+    for (int u = 0; u < E / R0; ++u) dft_reg<T, R0, E / R0>(v, u);
+    if constexpr (NST == 1) return;
+    // butterfly j = t + u*P writes Y[j*R0 + s]
+    int ns = R0;
+#pragma unroll
+    for (int st = 1; st < NST; ++st) {
+        __syncthreads();
+        if (st == 1) {
+#pragma unroll
+            for (int u = 0; u < E / R0; ++u) {
+                int j = t + u * P;
+#pragma unroll
+                for (int s = 0; s < R0; ++s) {
+                    int idx = lds_pad(j * R0 + s);
+                    lre[idx] = v[u + s * (E / R0)].x;
+                    lim[idx] = v[u + s * (E / R0)].y;
+                }
+            }
+        } else {
+            // previous radix-E stage with span ns/E: j = t
+            int nsp = ns / E;
+            int jm = t % nsp;
+            int o = (t / nsp) * nsp * E + jm;
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                int idx = lds_pad(o + s * nsp);
+                lre[idx] = v[s].x;
+                lim[idx] = v[s].y;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            int idx = lds_pad(t + s * P);
+            v[s] = C2<T>{lre[idx], lim[idx]};
+        }
+        // twiddles e^{+2 pi i (t mod ns) s / (ns E)} = W_N[(t mod ns) * s * N/(ns E)]
+        int step = (t % ns) * (N / (ns * E));
+#pragma unroll
+        for (int s = 1; s < E; ++s) v[s] = cmul(v[s], tw[step * s]);
+        dft_reg<T, E, 1>(v, 0);
+        ns *= E;
+    }
+}
+
+// ---------------------------------------------------------------- pass 1
+template <typename T, int N>
+__global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restrict__ planes,
+                                                                 const C2<T> *__restrict__ tw) {
+    using SH = Shape<T, N>;
+    constexpr int B = SH::B, P = SH::P, NTR = SH::NTR;
+    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    const int tid = threadIdx.x;
+    const int r_lo = tid % B;
+    const int t = (tid / B) % P;
+    const int r_hi = tid / (B * P);
+    const int r = r_hi * B + r_lo;
+    const int a = blockIdx.x * NTR + r;
+    C2<T> *X = planes + (size_t)blockIdx.y * N * N;
+    C2<T> v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int b = t + m * P;
+        C2<T> z = X[(size_t)a * N + b];
+        if ((a + b) & 1) z = C2<T>{-z.x, -z.y};
+        v[m] = z;
+    }
+    T *lre = lds + (size_t)r * SH::NPAD;
+    T *lim = lds + (size_t)(NTR + r) * SH::NPAD;
+    fft_line<T, N>(v, lre, lim, t, tw);
+    __syncthreads();   // every load of this region is done before it is overwritten
+    C2<T> *Y = X + (size_t)(a / B) * B * N;
+#pragma unroll
+    for (int s = 0; s < E; ++s) Y[(size_t)(t + s * P) * B + r_lo] = v[s];
+}
+
+// ---------------------------------------------------------------- pass 2
+// thread -> (t_lo, r, t_hi): reads of 16 consecutive lanes form one 128-byte run
+template <typename T, int N>
+struct P2Index {
+    using SH = Shape<T, N>;
+    int t, r;
+    __device__ __forceinline__ P2Index(int tid) {
+        constexpr int TB = SH::B < SH::P ? SH::B : SH::P;
+        constexpr int NTR = SH::NTR;
+        int t_lo = tid % TB;
+        r = (tid / TB) % NTR;
+        int t_hi = tid / (TB * NTR);
+        t = t_hi * TB + t_lo;
+    }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void load_blocked(C2<T> *v, const C2<T> *__restrict__ Y, int t, int bcol) {
+    constexpr int B = Shape<T, N>::B, P = N / E;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int a = t + m * P;
+        v[m] = Y[((size_t)(a / B) * N + bcol) * B + (a % B)];
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_store(const C2<T> *__restrict__ in,
+                                                                       C2<T> *__restrict__ out,
+                                                                       const C2<T> *__restrict__ tw) {
+    using SH = Shape<T, N>;
+    constexpr int P = SH::P, NTR = SH::NTR;
+    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    P2Index<T, N> ix(threadIdx.x);
+    const int bcol = blockIdx.x * NTR + ix.r;
+    const C2<T> *Y = in + (size_t)blockIdx.y * N * N;
+    C2<T> v[E];
+    load_blocked<T, N>(v, Y, ix.t, bcol);
+    fft_line<T, N>(v, lds + (size_t)ix.r * SH::NPAD, lds + (size_t)(NTR + ix.r) * SH::NPAD, ix.t, tw);
+    // stage through LDS so that the row-major writes are contiguous
+    __syncthreads();
+    C2<T> *st = (C2<T> *)lds;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        int ap = ix.t + s * P;
+        C2<T> z = v[s];
+        if ((ap + bcol) & 1) z = C2<T>{-z.x, -z.y};
+        st[ix.r * N + ap] = z;
+    }
+    __syncthreads();
+    C2<T> *Z = out + (size_t)blockIdx.y * N * N + (size_t)blockIdx.x * NTR * N;
+    for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) Z[i] = st[i];
+}
+
+// phase screen of one pixel for plane w: e^{2 pi i w (n-1)}
+template <bool PH32>
+struct Phase;
+
+template <>
+struct Phase<false> {
+    using R = double;
+    static __device__ __forceinline__ R nm1(double l, double m, int /*naive*/, bool &inside) {
+        double eta = l * l + m * m;
+        inside = eta < 1.0;
+        if (!inside) return 0.0;
+        return -eta / (1.0 + sqrt(1.0 - eta));
+    }
+    static __device__ __forceinline__ void screen(R nm1v, double w, double &c, double &s) {
+        sincospi(2.0 * (w * nm1v), &s, &c);
+    }
+};
+
+template <>
+struct Phase<true> {
+    using R = float;
+    static __device__ __forceinline__ R nm1(double l, double m, int naive, bool &inside) {
+        float lf = (float)l, mf = (float)m;
+        float eta = lf * lf + mf * mf;
+        inside = eta < 1.0f;
+        if (!inside) return 0.0f;
+        if (naive) return sqrtf(1.0f - eta) - 1.0f;
+        return -eta / (1.0f + sqrtf(1.0f - eta));
+    }
+    static __device__ __forceinline__ void screen(R nm1v, double w, double &c, double &s) {
+        float sf, cf;
+        sincospif(2.0f * ((float)w * nm1v), &sf, &cf);
+        c = cf;
+        s = sf;
+    }
+};
+
+template <typename T, int N, bool PH32>
+__global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2<T> *__restrict__ stack,
+                                                                       const C2<T> *__restrict__ tw,
+                                                                       WcorrArgs a,
+                                                                       double *__restrict__ image) {
+    using SH = Shape<T, N>;
+    using PR = typename Phase<PH32>::R;
+    constexpr int P = SH::P, NTR = SH::NTR;
+    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    P2Index<T, N> ix(threadIdx.x);
+    const int img = blockIdx.y;
+    const int q = blockIdx.x * NTR + ix.r;            // image row handled by this thread
+    const ImgState &st = a.st[img];
+    const double m = (double)(q - N / 2) * a.cell;
+    PR nm1[E];
+    bool inside[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        int p = ix.t + s * P;
+        double l = (double)(p - N / 2) * a.cell;
+        nm1[s] = Phase<PH32>::nm1(l, m, a.naive_nm1, inside[s]);
+    }
+    double acc[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) acc[s] = 0.0;
+    const double w_min = st.w_min, dw = st.dw;
+    T *lre = lds + (size_t)ix.r * SH::NPAD;
+    T *lim = lds + (size_t)(NTR + ix.r) * SH::NPAD;
+    for (int kl = 0; kl < a.n_pl; ++kl) {
+        const int k = a.plane_lo + kl;
+        const double wk = (dw == 0.0) ? w_min : w_min + ((double)k + 0.5) * dw;
+        const C2<T> *Y = stack + ((size_t)img * a.n_pl + kl) * N * N;
+        C2<T> v[E];
+        load_blocked<T, N>(v, Y, ix.t, q);
+        fft_line<T, N>(v, lre, lim, ix.t, tw);
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            double c, sn;
+            Phase<PH32>::screen(nm1[s], wk, c, sn);
+            acc[s] += (double)v[s].x * c - (double)v[s].y * sn;
+        }
+    }
+    // post factors and the output sign (-1)^(p+q); stage through LDS for
+    // contiguous row writes
+    const double inv_row = st.inv_norm * (a.inv_c ? a.inv_c[q] : 1.0);
+    __syncthreads();
+    double *stg = (double *)lds;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        int p = ix.t + s * P;
+        double d = inside[s] ? acc[s] * inv_row * (a.inv_c ? a.inv_c[p] : 1.0) : 0.0;
+        if ((p + q) & 1) d = -d;
+        stg[ix.r * N + p] = d;
+    }
+    __syncthreads();
+    double *D = image + (size_t)img * N * N + (size_t)blockIdx.x * NTR * N;
+    for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = stg[i];
+}
+
+// ---------------------------------------------------------------- w-correction alone
+template <typename T, bool PH32>
+__global__ __launch_bounds__(256) void k_wcorrect(const C2<T> *__restrict__ F, WcorrArgs a,
+                                                  double *__restrict__ image) {
+    using PR = typename Phase<PH32>::R;
+    const int N = a.N;
+    const size_t n2 = (size_t)N * N;
+    size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= n2) return;
+    const int q = (int)(pix / N), p = (int)(pix % N);
+    const ImgState &st = a.st[0];
+    bool inside;
+    PR nm1 = Phase<PH32>::nm1((double)(p - N / 2) * a.cell, (double)(q - N / 2) * a.cell,
+                              a.naive_nm1, inside);
+    double acc = 0.0;
+    for (int kl = 0; kl < a.n_pl; ++kl) {
+        const int k = a.plane_lo + kl;
+        const double wk = (st.dw == 0.0) ? st.w_min : st.w_min + ((double)k + 0.5) * st.dw;
+        C2<T> z = F[(size_t)kl * n2 + pix];
+        double c, s;
+        Phase<PH32>::screen(nm1, wk, c, s);
+        acc += (double)z.x * c - (double)z.y * s;
+    }
+    double d = inside ? acc * st.inv_norm * (a.inv_c ? a.inv_c[p] * a.inv_c[q] : 1.0) : 0.0;
+    image[pix] = d;
+}
+
+// ---------------------------------------------------------------- transpose
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const C2<T> *__restrict__ in, C2<T> *__restrict__ out, int N) {
+    __shared__ C2<T> tile[32][33];
+    const size_t plane = (size_t)blockIdx.z * N * N;
+    int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8)
+        if (y0 + k < N && x0 + (int)threadIdx.x < N)
+            tile[k][threadIdx.x] = in[plane + (size_t)(y0 + k) * N + x0 + threadIdx.x];
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8)
+        if (x0 + k < N && y0 + (int)threadIdx.x < N)
+            out[plane + (size_t)(x0 + k) * N + y0 + threadIdx.x] = tile[threadIdx.x][k];
+}
+
+template <typename T, int N>
+void pass1_n(void *planes, int64_t n_planes, const void *tw, hipStream_t s) {
+    using SH = Shape<T, N>;
+    dim3 grid(N / SH::NTR, (unsigned)n_planes);
+    k_pass1<T, N><<<grid, SH::THREADS, 0, s>>>((C2<T> *)planes, (const C2<T> *)tw);
+}
+
+template <typename T, int N>
+void pass2_store_n(const void *in, void *out, int64_t n_planes, const void *tw, hipStream_t s) {
+    using SH = Shape<T, N>;
+    dim3 grid(N / SH::NTR, (unsigned)n_planes);
+    k_pass2_store<T, N><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)in, (C2<T> *)out, (const C2<T> *)tw);
+}
+
+template <typename T, int N>
+void pass2_wcorr_n(const WcorrArgs &a, const void *stack, const void *tw, double *image, hipStream_t s) {
+    using SH = Shape<T, N>;
+    dim3 grid(N / SH::NTR, (unsigned)a.n_img);
+    if (a.phase32)
+        k_pass2_wcorr<T, N, true><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)stack, (const C2<T> *)tw, a, image);
+    else
+        k_pass2_wcorr<T, N, false><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)stack, (const C2<T> *)tw, a, image);
+}
+
+#define WSG_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+}  // namespace
+
+int fft_block_rows(bool f64) { return f64 ? BlockRows<double>::value : BlockRows<float>::value; }
+
+void launch_fft_pass1(int N, bool f64, void *planes, int64_t n_planes, const void *twiddle,
+                      hipStream_t s) {
+    if (n_planes <= 0) return;
+#define X(n)                                                                     \
+    case n:                                                                      \
+        if (f64) pass1_n<double, n>(planes, n_planes, twiddle, s);               \
+        else pass1_n<float, n>(planes, n_planes, twiddle, s);                    \
+        break;
+    switch (N) { WSG_FOR_EACH_N(X) default: break; }
+#undef X
+}
+
+void launch_fft_pass2_store(int N, bool f64, const void *in, void *out, int64_t n_planes,
+                            const void *twiddle, hipStream_t s) {
+    if (n_planes <= 0) return;
+#define X(n)                                                                     \
+    case n:                                                                      \
+        if (f64) pass2_store_n<double, n>(in, out, n_planes, twiddle, s);        \
+        else pass2_store_n<float, n>(in, out, n_planes, twiddle, s);             \
+        break;
+    switch (N) { WSG_FOR_EACH_N(X) default: break; }
+#undef X
+}
+
+void launch_fft_pass2_wcorr(const WcorrArgs &a, bool f64, const void *planes, const void *twiddle,
+                            double *image, hipStream_t s) {
+    if (a.n_img <= 0) return;
+#define X(n)                                                                     \
+    case n:                                                                      \
+        if (f64) pass2_wcorr_n<double, n>(a, planes, twiddle, image, s);         \
+        else pass2_wcorr_n<float, n>(a, planes, twiddle, image, s);              \
+        break;
+    switch (a.N) { WSG_FOR_EACH_N(X) default: break; }
+#undef X
+}
+
+void launch_wcorrect(const WcorrArgs &a, bool f64, const void *planes, double *image, hipStream_t s) {
+    size_t n2 = (size_t)a.N * a.N;
+    unsigned blocks = (unsigned)((n2 + 255) / 256);
+    if (f64) {
+        if (a.phase32) k_wcorrect<double, true><<<blocks, 256, 0, s>>>((const C2<double> *)planes, a, image);
+        else k_wcorrect<double, false><<<blocks, 256, 0, s>>>((const C2<double> *)planes, a, image);
+    } else {
+        if (a.phase32) k_wcorrect<float, true><<<blocks, 256, 0, s>>>((const C2<float> *)planes, a, image);
+        else k_wcorrect<float, false><<<blocks, 256, 0, s>>>((const C2<float> *)planes, a, image);
+    }
+}
+
+void launch_transpose(int N, bool f64, const void *in, void *out, int64_t n_planes, hipStream_t s) {
+    if (n_planes <= 0) return;
+    dim3 grid((N + 31) / 32, (N + 31) / 32, (unsigned)n_planes);
+    dim3 block(32, 8);
+    if (f64) k_transpose<double><<<grid, block, 0, s>>>((const C2<double> *)in, (C2<double> *)out, N);
+    else k_transpose<float><<<grid, block, 0, s>>>((const C2<float> *)in, (C2<float> *)out, N);
+}
+
+}  // namespace wsg

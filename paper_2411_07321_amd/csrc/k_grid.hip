@@ -1,0 +1,225 @@
+// Convolutional gridding (Eq. 3 of the paper) of binned records.
+//
+// One work item = one (image, plane, tile) bin, or one chunk of a bin that
+// holds more than `chunk` records.  The workgroup accumulates its records into
+// an LDS copy of the T x T tile (every record adds W V G(i0+a-x) G(j0+b-y) to
+// the cells of its S x S footprint that lie inside the tile), then writes the
+// tile to the plane stack with coalesced stores.  A tile covered by a single
+// chunk is stored (every cell of the stack is written exactly once, so the
+// stack needs no clearing); the chunks of a split bin add their partial tiles
+// with global atomics into a tile that k_zero_split cleared.
+//
+// The kernel G(d) = exp(-d^2 / (2 sigma^2)) is separable: 2*S exponentials per
+// record, S^2 multiply-adds.
+#include "wsg_internal.h"
+
+namespace wsg {
+
+namespace {
+
+constexpr int kGridThreads = 256;
+
+template <typename T>
+struct RecTraits;
+
+template <>
+struct RecTraits<float> {
+    using Rec = RecF32;
+    static __device__ __forceinline__ void decode(const Rec &r, int h, int &li, int &lj, float &fx,
+                                                  float &fy, float &re, float &im) {
+        li = (int)(r.px >> kFracBits) - h;
+        lj = (int)(r.py >> kFracBits) - h;
+        fx = (float)(r.px & 0xffffffu) * (1.0f / kFracScale) - 0.5f;
+        fy = (float)(r.py & 0xffffffu) * (1.0f / kFracScale) - 0.5f;
+        re = r.re;
+        im = r.im;
+    }
+    static __device__ __forceinline__ float gauss(float d, float inv2s2) { return expf(-d * d * inv2s2); }
+};
+
+template <>
+struct RecTraits<double> {
+    using Rec = RecF64;
+    static __device__ __forceinline__ void decode(const Rec &r, int, int &li, int &lj, double &fx,
+                                                  double &fy, double &re, double &im) {
+        li = r.li;
+        lj = r.lj;
+        fx = r.fx;
+        fy = r.fy;
+        re = r.re;
+        im = r.im;
+    }
+    static __device__ __forceinline__ double gauss(double d, double inv2s2) { return exp(-d * d * inv2s2); }
+};
+
+__device__ __forceinline__ void bin_coords(const JobGeom &g, uint32_t b, int &img, int &kl, int &ty,
+                                           int &tx) {
+    uint32_t per_plane = (uint32_t)g.NT * g.NT;
+    uint32_t pl = b / per_plane;
+    uint32_t t = b - pl * per_plane;
+    ty = (int)(t / g.NT);
+    tx = (int)(t - (uint32_t)ty * g.NT);
+    img = (int)(pl / g.n_pl);
+    kl = (int)(pl - (uint32_t)img * g.n_pl);
+}
+
+template <typename T>
+__device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, int i, int j,
+                                             bool transposed) {
+    size_t plane = ((size_t)img * g.n_pl + kl) * (size_t)g.N * g.N;
+    return plane + (transposed ? ((size_t)i * g.N + j) : ((size_t)j * g.N + i));
+}
+
+// LDS tile: TP = T+1 columns per row, separate real / imaginary arrays.
+template <typename T, int TT>
+__global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
+                                                        const uint32_t *__restrict__ offsets,
+                                                        const uint32_t *__restrict__ item_off,
+                                                        const uint32_t *__restrict__ item_bin,
+                                                        uint32_t chunk,
+                                                        const typename RecTraits<T>::Rec *__restrict__ rec,
+                                                        C2<T> *__restrict__ grid, int transposed) {
+    constexpr int TP = TT + 1;
+    __shared__ T s_re[TT * TP];
+    __shared__ T s_im[TT * TP];
+    const uint32_t item = blockIdx.x;
+    const uint32_t b = item_bin[item];
+    const uint32_t c = item - item_off[b];
+    const uint32_t cnt = counts[b];
+    const bool split = cnt > chunk;
+    const uint32_t r0 = offsets[b] + c * chunk;
+    const uint32_t r1 = offsets[b] + min(cnt, (c + 1) * chunk);
+
+    for (int i = threadIdx.x; i < TT * TP; i += blockDim.x) {
+        s_re[i] = T(0);
+        s_im[i] = T(0);
+    }
+    __syncthreads();
+
+    const int h = g.h;
+    const int S = g.S;
+    const T inv2s2 = (T)g.inv2s2;
+    for (uint32_t ri = r0 + threadIdx.x; ri < r1; ri += blockDim.x) {
+        int li, lj;
+        T fx, fy, re, im;
+        RecTraits<T>::decode(rec[ri], h, li, lj, fx, fy, re, im);
+        T gx[kMaxSupport], gy[kMaxSupport];
+#pragma unroll
+        for (int a = 0; a < kMaxSupport; ++a) {
+            if (a < S) {
+                gx[a] = RecTraits<T>::gauss((T)(a - h) - fx, inv2s2);
+                gy[a] = RecTraits<T>::gauss((T)(a - h) - fy, inv2s2);
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < kMaxSupport; ++bb) {
+            int j = lj + bb - h;
+            if (bb >= S || j < 0 || j >= TT) continue;
+            T wr = re * gy[bb], wi = im * gy[bb];
+#pragma unroll
+            for (int a = 0; a < kMaxSupport; ++a) {
+                int i = li + a - h;
+                if (a >= S || i < 0 || i >= TT) continue;
+                atomicAdd(&s_re[j * TP + i], wr * gx[a]);
+                atomicAdd(&s_im[j * TP + i], wi * gx[a]);
+            }
+        }
+    }
+    __syncthreads();
+
+    int img, kl, ty, tx;
+    bin_coords(g, b, img, kl, ty, tx);
+    const int gi0 = tx * TT, gj0 = ty * TT;
+    for (int t = threadIdx.x; t < TT * TT; t += blockDim.x) {
+        // fast index runs along the stored row of the plane
+        int fast = t % TT, slow = t / TT;
+        int i, j;
+        if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
+        T vr = s_re[j * TP + i], vi = s_im[j * TP + i];
+        size_t idx = cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0);
+        if (split) {
+            atomicAdd(&grid[idx].x, vr);
+            atomicAdd(&grid[idx].y, vi);
+        } else {
+            grid[idx] = C2<T>{vr, vi};
+        }
+    }
+}
+
+template <typename T, int TT>
+__global__ __launch_bounds__(kGridThreads) void k_zero_split(JobGeom g, const uint32_t *__restrict__ counts,
+                                                             uint32_t chunk, C2<T> *__restrict__ grid,
+                                                             int transposed) {
+    const uint32_t b = blockIdx.x;
+    if (counts[b] <= chunk) return;
+    int img, kl, ty, tx;
+    bin_coords(g, b, img, kl, ty, tx);
+    const int gi0 = tx * TT, gj0 = ty * TT;
+    for (int t = threadIdx.x; t < TT * TT; t += blockDim.x) {
+        int fast = t % TT, slow = t / TT;
+        int i, j;
+        if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
+        grid[cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0)] = C2<T>{T(0), T(0)};
+    }
+}
+
+template <typename T>
+void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
+                   const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
+                   uint32_t chunk, const void *records, void *grid, bool transposed,
+                   hipStream_t s) {
+    using Rec = typename RecTraits<T>::Rec;
+    const Rec *r = (const Rec *)records;
+    C2<T> *gp = (C2<T> *)grid;
+    int tr = transposed ? 1 : 0;
+    switch (g.T) {
+    case 16: k_grid<T, 16><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 32: k_grid<T, 32><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 64: k_grid<T, 64><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 128:
+        if constexpr (sizeof(T) == 4)
+            k_grid<T, 128><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr);
+        break;
+    default: break;
+    }
+}
+
+template <typename T>
+void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, void *grid,
+                   bool transposed, hipStream_t s) {
+    unsigned n_bins = (unsigned)((size_t)g.n_img * g.n_pl * g.NT * g.NT);
+    C2<T> *gp = (C2<T> *)grid;
+    int tr = transposed ? 1 : 0;
+    switch (g.T) {
+    case 16: k_zero_split<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 32: k_zero_split<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 64: k_zero_split<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 128: k_zero_split<T, 128><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    default: break;
+    }
+}
+
+}  // namespace
+
+void launch_zero_split(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
+                       void *grid, bool transposed, hipStream_t s) {
+    if (f64)
+        dispatch_zero<double>(g, counts, chunk, grid, transposed, s);
+    else
+        dispatch_zero<float>(g, counts, chunk, grid, transposed, s);
+}
+
+void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
+                 const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
+                 uint32_t chunk, const void *records, void *grid, bool transposed,
+                 hipStream_t s) {
+    if (n_items == 0) return;
+    if (f64)
+        dispatch_grid<double>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
+                              transposed, s);
+    else
+        dispatch_grid<float>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
+                             transposed, s);
+}
+
+}  // namespace wsg

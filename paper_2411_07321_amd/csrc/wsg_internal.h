@@ -1,0 +1,150 @@
+// Internal declarations of the w-stacking library: device types, per-job
+// state, and the host-side launchers of each kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace wsg {
+
+constexpr double kSpeedOfLight = 299792458.0;
+constexpr int kMaxN = 4096;
+constexpr int kMinN = 16;
+constexpr int kMaxSupport = 15;
+
+// ----------------------------------------------------------------------------
+// complex arithmetic (interleaved re, im; layout-compatible with complex64/128)
+// ----------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ----------------------------------------------------------------------------
+// binning records: one per (visibility, tile its footprint touches)
+// ----------------------------------------------------------------------------
+// complex64 mesh: the cell inside the tile and the sub-cell offset f = x - i0
+// in [-1/2, 1/2) as 24-bit fixed point share one word per axis.
+struct RecF32 {
+    uint32_t px, py;   // (local cell + h) << 24 | round((f + 1/2) * 2^24)
+    float re, im;      // W * V
+};
+// complex128 mesh: FP64 offsets.
+struct RecF64 {
+    double fx, fy;     // f = x - i0
+    double re, im;     // W * V
+    int32_t li, lj;    // cell relative to the tile origin
+};
+
+constexpr uint32_t kFracBits = 24;
+constexpr float kFracScale = 16777216.0f;        // 2^24
+
+// ----------------------------------------------------------------------------
+// per-image device state: reductions of the validity pass and plane geometry
+// ----------------------------------------------------------------------------
+struct ImgState {
+    unsigned long long wmin_key, wmax_key;   // order-preserving keys of w over valid rows
+    unsigned long long n_flagged;
+    unsigned long long n_valid0;             // pass every test but the w range
+    unsigned long long n_used;
+    double sum_w;
+    double w_min, w_max, dw;                 // plane geometry used by the job
+    double inv_norm;                         // 1/sum_w (or 1, or 0 for an empty image)
+    int32_t pad[2];
+};
+
+// Everything the binning and gridding kernels need about one job.
+struct JobGeom {
+    int64_t n_rows;
+    int32_t n_chan;
+    int32_t n_img;          // 1, or n_chan with one image per channel
+    int32_t N;
+    int32_t n_w;            // planes over [w_min, w_max]
+    int32_t plane_lo, n_pl; // planes imaged: [plane_lo, plane_lo + n_pl)
+    int32_t S, h;
+    int32_t T, NT;          // tile edge and tiles per axis
+    double scale;           // N * cell_rad
+    double half;            // N / 2
+    double sigma;
+    double inv2s2;          // 1 / (2 sigma^2)
+    int32_t range_given;
+    double w_min_given, w_max_given;
+    const double *chan_scale;  // device [n_chan]: f/c or 1
+};
+
+// ----------------------------------------------------------------------------
+// launchers (each enqueues on `s`; no host synchronisation)
+// ----------------------------------------------------------------------------
+// validity pass: mask[e] = valid except w range; per-image w range and counts
+void launch_prep(const JobGeom &g, bool f64, const double *uvw, const void *vis,
+                 const void *wts, const uint8_t *flags, uint8_t *mask, ImgState *st,
+                 hipStream_t s);
+void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s);
+// bin counts per (image, plane, tile); n_used and sum_w
+void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
+                  const uint8_t *mask, ImgState *st, uint32_t *counts, hipStream_t s);
+// exclusive scan of n entries (u32) into out; tmp holds >= scan_tmp_elems(n) u32
+size_t scan_tmp_elems(size_t n);
+void launch_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp, hipStream_t s);
+// chunks per bin for the gridding work list, then item -> bin map
+void launch_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n_bins, uint32_t chunk,
+                   hipStream_t s);
+void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
+                     size_t n_bins, hipStream_t s);
+void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
+                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
+                    void *records, hipStream_t s);
+void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
+
+// gridding of binned records into the plane stack [n_img][n_pl][N][N]
+// transposed: store plane k as [i][j] (u index slow) instead of [j][i]
+void launch_zero_split(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
+                       void *grid, bool transposed, hipStream_t s);
+void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
+                 const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
+                 uint32_t chunk, const void *records, void *grid, bool transposed,
+                 hipStream_t s);
+
+// transforms.  Pass 1: rows of planes [n][N][N] (in place) into the blocked
+// layout [N/B][N][B]; pass 2: along the other axis.
+void launch_fft_pass1(int N, bool f64, void *planes, int64_t n_planes, const void *twiddle,
+                      hipStream_t s);
+// pass 2 from the blocked layout `in` to row-major planes `out` (output row =
+// the untransformed index), out of place
+void launch_fft_pass2_store(int N, bool f64, const void *in, void *out, int64_t n_planes,
+                            const void *twiddle, hipStream_t s);
+// pass 2 fused with the phase screen, plane sum and post factors:
+// image[img][q][p] = post(Re sum_k F_k[q][p] e^{2 pi i w_k (n-1)})
+struct WcorrArgs {
+    int N;
+    int n_img;
+    int n_pl;                // planes per image in the stack
+    int plane_lo;            // absolute index of the first plane
+    int n_w;
+    int phase32;             // FP32 phase screen
+    int naive_nm1;           // FP32 phase with sqrt(1-eta)-1
+    double cell;
+    const ImgState *st;      // per image: w_min, dw, inv_norm
+    const double *inv_c;     // [N] 1/C(nu) or NULL for no grid correction
+};
+void launch_fft_pass2_wcorr(const WcorrArgs &a, bool f64, const void *planes,
+                            const void *twiddle, double *image, hipStream_t s);
+// w-correction alone on row-major transformed planes
+void launch_wcorrect(const WcorrArgs &a, bool f64, const void *planes, double *image,
+                     hipStream_t s);
+// transpose each N x N complex plane (for the row-major stage entry point)
+void launch_transpose(int N, bool f64, const void *in, void *out, int64_t n_planes,
+                      hipStream_t s);
+int fft_block_rows(bool f64);   // B of the blocked layout
+
+}  // namespace wsg

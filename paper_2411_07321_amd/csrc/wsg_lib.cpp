@@ -1,0 +1,851 @@
+// Host side of the w-stacking library: the C ABI of include/wsg.h.
+//
+// A job runs as one chain of kernels on one stream:
+//   [H2D of host inputs] -> prep -> finalize -> count -> scan -> (read the
+//   record total: the only host wait inside a job) -> scatter -> grid ->
+//   transform pass 1 -> transform pass 2 + w-correction + post -> [D2H]
+// Workspace lives in two device arenas per context that only grow, so a
+// steady stream of jobs allocates nothing after the first of its size.
+#include "wsg_internal.h"
+#include "../../include/wsg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace wsg;
+
+namespace {
+
+constexpr uint32_t kChunk = 4096;        // records per gridding work item
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Arena {
+    void *ptr = nullptr;
+    size_t size = 0;
+};
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t size = 0;
+};
+
+}  // namespace
+
+struct wsg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    uint64_t budget = 0;
+    Arena fixed, dyn;
+    // cached tables
+    std::map<std::pair<int, int>, DevBuf> twiddles;                       // (N, f64)
+    std::map<std::tuple<int, int, double>, DevBuf> inv_c;                 // (N, S, sigma)
+    std::map<std::tuple<int, int, int, int, int>, int> tuned;             // -> tile
+    // pinned host staging
+    void *pin = nullptr;
+    size_t pin_size = 0;
+    hipEvent_t pin_done = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+wsg_status fail(wsg_ctx *ctx, wsg_status s, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+#define WSG_HIP(ctx, call)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            wsg_status st_ = (e_ == hipErrorOutOfMemory) ? WSG_ENOMEM : WSG_EDEVICE;      \
+            return fail(ctx, st_, std::string(#call) + ": " + hipGetErrorString(e_));    \
+        }                                                                                \
+    } while (0)
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int n_images(const wsg_params *p, const wsg_vis *v) {
+    return (p->flags & WSG_PER_CHANNEL) ? v->n_chan : 1;
+}
+
+bool f64_mode(const wsg_params *p) { return p->precision == WSG_PREC_F64; }
+
+size_t cplx_size(const wsg_params *p) { return f64_mode(p) ? 16 : 8; }
+
+bool range_given(const wsg_params *p) { return std::isfinite(p->w_min) && std::isfinite(p->w_max); }
+
+wsg_status check_params(const wsg_params *p, std::string &why) {
+    if (!p) { why = "params is NULL"; return WSG_EINVAL; }
+    if (!is_pow2(p->grid_n) || p->grid_n < 4) { why = "grid_n must be a power of two"; return WSG_EINVAL; }
+    if (p->grid_n < kMinN || p->grid_n > kMaxN) { why = "grid_n outside 16..4096"; return WSG_EUNSUPPORTED; }
+    if (p->n_wplanes < 1) { why = "n_wplanes < 1"; return WSG_EINVAL; }
+    if (p->support < 1 || (p->support % 2) == 0 || p->support > p->grid_n) {
+        why = "support must be odd, >= 1 and <= grid_n";
+        return WSG_EINVAL;
+    }
+    if (p->support > kMaxSupport) { why = "support above 15"; return WSG_EUNSUPPORTED; }
+    if (p->precision < WSG_PREC_F64 || p->precision > WSG_PREC_F32_PHASE32) { why = "bad precision"; return WSG_EINVAL; }
+    if (!(p->cell_rad > 0.0) || !std::isfinite(p->cell_rad)) { why = "cell_rad must be finite and > 0"; return WSG_EINVAL; }
+    if (!(p->kernel_sigma > 0.0) || !std::isfinite(p->kernel_sigma)) { why = "kernel_sigma must be finite and > 0"; return WSG_EINVAL; }
+    bool lo_nan = std::isnan(p->w_min), hi_nan = std::isnan(p->w_max);
+    if (lo_nan != hi_nan) { why = "w_min and w_max must both be given or both NaN"; return WSG_EINVAL; }
+    if (!lo_nan && (!std::isfinite(p->w_min) || !std::isfinite(p->w_max) || p->w_min > p->w_max)) {
+        why = "w range must be finite with w_min <= w_max";
+        return WSG_EINVAL;
+    }
+    int lo = p->plane_lo, hi = p->plane_hi;
+    if (!(lo == 0 && hi == 0)) {
+        if (lo < 0 || hi > p->n_wplanes || lo >= hi) { why = "plane range outside [0, n_wplanes)"; return WSG_EINVAL; }
+        if (!(lo == 0 && hi == p->n_wplanes) && lo_nan) {
+            why = "a plane range needs a given w range";
+            return WSG_EINVAL;
+        }
+    }
+    if (p->flags & ~(uint32_t)(WSG_GRID_CORRECT | WSG_NORMALIZE | WSG_PER_CHANNEL | WSG_NAIVE_NM1)) {
+        why = "unknown flag bits";
+        return WSG_EINVAL;
+    }
+    if (p->tile != 0) {
+        if (!(p->tile == 16 || p->tile == 32 || p->tile == 64 || p->tile == 128) || p->tile > p->grid_n) {
+            why = "tile must be 16, 32, 64 or 128 and <= grid_n";
+            return WSG_EINVAL;
+        }
+        if (p->tile == 128 && p->precision == WSG_PREC_F64) { why = "tile 128 needs a complex64 mesh"; return WSG_EUNSUPPORTED; }
+    }
+    return WSG_OK;
+}
+
+wsg_status check_vis(const wsg_params *p, const wsg_vis *v, std::string &why) {
+    if (!v) { why = "vis is NULL"; return WSG_EINVAL; }
+    if (v->n_rows < 0 || v->n_chan < 1) { why = "n_rows < 0 or n_chan < 1"; return WSG_EINVAL; }
+    if (v->mem != WSG_MEM_HOST && v->mem != WSG_MEM_DEVICE) { why = "bad memory space"; return WSG_EINVAL; }
+    if (v->n_rows > 0 && (!v->uvw || !v->vis)) { why = "uvw or vis is NULL"; return WSG_EINVAL; }
+    int64_t n_elem = v->n_rows * (int64_t)v->n_chan;
+    // records (up to four per visibility) are addressed with 32-bit offsets
+    if (n_elem > (int64_t)1 << 29) { why = "more than 2^29 visibilities per call"; return WSG_EUNSUPPORTED; }
+    if ((p->flags & WSG_PER_CHANNEL) && v->n_chan > 256) { why = "more than 256 channels per cube"; return WSG_EUNSUPPORTED; }
+    if (v->n_chan > 4096) { why = "more than 4096 channels"; return WSG_EUNSUPPORTED; }
+    if (v->freq_hz) {
+        for (int c = 0; c < v->n_chan; ++c)
+            if (!(v->freq_hz[c] > 0.0) || !std::isfinite(v->freq_hz[c])) { why = "freq_hz must be finite and > 0"; return WSG_EINVAL; }
+    }
+    int n_img = n_images(p, v);
+    int n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    if ((size_t)n_img * n_pl > 65535) { why = "more than 65535 planes in one stack"; return WSG_EUNSUPPORTED; }
+    int tile = p->tile ? p->tile : std::min(f64_mode(p) ? 32 : 64, p->grid_n);
+    size_t nt = (size_t)(p->grid_n / tile);
+    if ((size_t)n_img * n_pl * nt * nt > ((size_t)1 << 27)) { why = "more than 2^27 (plane, tile) bins"; return WSG_EUNSUPPORTED; }
+    return WSG_OK;
+}
+
+int default_tile(const wsg_params *p) {
+    int t = f64_mode(p) ? 32 : 64;
+    return std::min(t, p->grid_n);
+}
+
+int decade(int64_t n) {
+    int d = 0;
+    while (n >= 10) { n /= 10; ++d; }
+    return d;
+}
+
+// ---------------------------------------------------------------- job plan
+struct Plan {
+    int N, n_w, n_pl, plane_lo, n_img, S, T, NT;
+    bool f64;
+    int64_t n_rows, n_elem;
+    size_t n_bins;
+    size_t vis_sz, wt_sz;
+    // byte offsets in the fixed arena
+    size_t o_uvw, o_vis, o_wts, o_flags, o_scale, o_mask, o_state, o_counts, o_offsets,
+        o_cursor, o_nchunk, o_itemoff, o_scan, o_tot, o_stack, o_image, o_aux, fixed_bytes;
+    size_t records_est, items_est;
+};
+
+Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image_out,
+               bool host_out_image) {
+    Plan pl{};
+    pl.N = p->grid_n;
+    pl.n_w = p->n_wplanes;
+    pl.plane_lo = (p->plane_hi > p->plane_lo) ? p->plane_lo : 0;
+    pl.n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    pl.n_img = n_images(p, v);
+    pl.S = p->support;
+    pl.T = tile;
+    pl.NT = pl.N / tile;
+    pl.f64 = f64_mode(p);
+    pl.n_rows = v->n_rows;
+    pl.n_elem = v->n_rows * (int64_t)v->n_chan;
+    pl.n_bins = (size_t)pl.n_img * pl.n_pl * pl.NT * pl.NT;
+    pl.vis_sz = pl.f64 ? 16 : 8;
+    pl.wt_sz = pl.f64 ? 8 : 4;
+    bool host_in = v->mem == WSG_MEM_HOST;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    pl.o_uvw = take(host_in ? (size_t)pl.n_rows * 24 : 0);
+    pl.o_vis = take(host_in ? (size_t)pl.n_elem * pl.vis_sz : 0);
+    pl.o_wts = take(host_in && v->weights ? (size_t)pl.n_elem * pl.wt_sz : 0);
+    pl.o_flags = take(host_in && v->flags ? (size_t)pl.n_elem : 0);
+    pl.o_scale = take((size_t)v->n_chan * 8);
+    pl.o_mask = take((size_t)pl.n_elem);
+    pl.o_state = take((size_t)pl.n_img * sizeof(ImgState));
+    size_t nb1 = pl.n_bins + 1;
+    pl.o_counts = take(nb1 * 4);
+    pl.o_offsets = take(nb1 * 4);
+    pl.o_cursor = take(nb1 * 4);
+    pl.o_nchunk = take(nb1 * 4);
+    pl.o_itemoff = take(nb1 * 4);
+    pl.o_scan = take(scan_tmp_elems(nb1) * 4);
+    pl.o_tot = take(16);
+    pl.o_stack = take((size_t)pl.n_img * pl.n_pl * pl.N * pl.N * (pl.f64 ? 16 : 8));
+    pl.o_image = take(host_out_image ? (size_t)pl.n_img * pl.N * pl.N * (stage_image_out ? 8 : 8) : 0);
+    pl.o_aux = take(0);
+    pl.fixed_bytes = off;
+    double rep = (double)(tile + pl.S - 1) / tile;
+    pl.records_est = (size_t)((double)pl.n_elem * rep * rep) + 1024;
+    pl.items_est = pl.n_bins + pl.records_est / kChunk + 1;
+    return pl;
+}
+
+size_t rec_size(bool f64) { return f64 ? sizeof(RecF64) : sizeof(RecF32); }
+
+size_t dyn_bytes(const Plan &pl, size_t records, size_t items) {
+    return align_up(records * rec_size(pl.f64)) + align_up(items * 4);
+}
+
+wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, size_t other_in_use) {
+    if (bytes <= a.size) return WSG_OK;
+    if (ctx->budget && bytes + other_in_use > ctx->budget)
+        return fail(ctx, WSG_ENOMEM, "workspace of " + std::to_string(bytes + other_in_use) +
+                                         " bytes exceeds the context budget");
+    if (a.ptr) {
+        WSG_HIP(ctx, hipDeviceSynchronize());
+        WSG_HIP(ctx, hipFree(a.ptr));
+        a.ptr = nullptr;
+        a.size = 0;
+    }
+    size_t sz = align_up(bytes + bytes / 16);
+    WSG_HIP(ctx, hipMalloc(&a.ptr, sz));
+    a.size = sz;
+    return WSG_OK;
+}
+
+wsg_status ensure_pin(wsg_ctx *ctx, size_t bytes) {
+    if (ctx->pin_done) WSG_HIP(ctx, hipEventSynchronize(ctx->pin_done));
+    if (bytes <= ctx->pin_size) return WSG_OK;
+    if (ctx->pin) WSG_HIP(ctx, hipHostFree(ctx->pin));
+    ctx->pin = nullptr;
+    ctx->pin_size = 0;
+    size_t sz = std::max<size_t>(align_up(bytes), 65536);
+    WSG_HIP(ctx, hipHostMalloc(&ctx->pin, sz, hipHostMallocDefault));
+    ctx->pin_size = sz;
+    return WSG_OK;
+}
+
+// ---------------------------------------------------------------- tables
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const double **out) {
+    *out = nullptr;
+    if (!(p->flags & WSG_GRID_CORRECT)) return WSG_OK;
+    auto key = std::make_tuple(p->grid_n, p->support, p->kernel_sigma);
+    auto it = ctx->inv_c.find(key);
+    if (it == ctx->inv_c.end()) {
+        int N = p->grid_n;
+        std::vector<double> xs, ws;
+        gauss_legendre(64, xs, ws);
+        double a = p->support / 2.0, s2 = 2.0 * p->kernel_sigma * p->kernel_sigma;
+        const double two_pi = 6.283185307179586476925286766559;
+        std::vector<double> h(N);
+        for (int i = 0; i < N; ++i) {
+            double nu = (double)(i - N / 2) / N;
+            double c = 0.0;
+            for (size_t k = 0; k < xs.size(); ++k) {
+                double d = a * xs[k];
+                c += ws[k] * std::exp(-d * d / s2) * std::cos(two_pi * nu * d);
+            }
+            h[i] = 1.0 / (a * c);
+        }
+        DevBuf b;
+        WSG_HIP(ctx, hipMalloc(&b.ptr, N * sizeof(double)));
+        b.size = N * sizeof(double);
+        WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
+        it = ctx->inv_c.emplace(key, b).first;
+    }
+    (void)s;
+    *out = (const double *)it->second.ptr;
+    return WSG_OK;
+}
+
+wsg_status get_twiddle(wsg_ctx *ctx, int N, bool f64, const void **out) {
+    auto key = std::make_pair(N, f64 ? 1 : 0);
+    auto it = ctx->twiddles.find(key);
+    if (it == ctx->twiddles.end()) {
+        const double two_pi = 6.283185307179586476925286766559;
+        DevBuf b;
+        if (f64) {
+            std::vector<double> h(2 * N);
+            for (int m = 0; m < N; ++m) {
+                h[2 * m] = std::cos(two_pi * m / N);
+                h[2 * m + 1] = std::sin(two_pi * m / N);
+            }
+            b.size = h.size() * sizeof(double);
+            WSG_HIP(ctx, hipMalloc(&b.ptr, b.size));
+            WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> h(2 * N);
+            for (int m = 0; m < N; ++m) {
+                h[2 * m] = (float)std::cos(two_pi * m / N);
+                h[2 * m + 1] = (float)std::sin(two_pi * m / N);
+            }
+            b.size = h.size() * sizeof(float);
+            WSG_HIP(ctx, hipMalloc(&b.ptr, b.size));
+            WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
+        }
+        it = ctx->twiddles.emplace(key, b).first;
+    }
+    *out = it->second.ptr;
+    return WSG_OK;
+}
+
+int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
+    if (p->tile) return p->tile;
+    auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
+                               decade(v->n_rows * (int64_t)v->n_chan));
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return std::min(it->second, p->grid_n);
+    return default_tile(p);
+}
+
+hipStream_t pick_stream(wsg_ctx *ctx, void *stream) {
+    return stream ? (hipStream_t)stream : ctx->stream;
+}
+
+// ---------------------------------------------------------------- the binned grid
+struct Binned {
+    Plan pl;
+    JobGeom g;
+    char *fx;              // fixed arena base
+    const double *uvw;
+    const void *vis, *wts;
+    const uint8_t *flags;
+    ImgState *st;
+    uint32_t *counts, *offsets, *cursor, *nchunk, *itemoff, *item_bin;
+    void *records;
+    uint32_t n_items;
+    uint32_t n_records;
+};
+
+// Stage inputs, validity pass, counting sort and record scatter.  Ends with
+// the records binned; the grid kernel is launched by the caller.
+wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStream_t s, bool image_host,
+                   Binned &b) {
+    int tile = choose_tile(ctx, p, v);
+    b.pl = make_plan(p, v, tile, true, image_host);
+    Plan &pl = b.pl;
+    if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
+    size_t dyn_est = dyn_bytes(pl, pl.records_est, pl.items_est);
+    if (ctx->budget && pl.fixed_bytes + dyn_est > ctx->budget)
+        return fail(ctx, WSG_ENOMEM, "job footprint " + std::to_string(pl.fixed_bytes + dyn_est) +
+                                         " bytes exceeds the context budget");
+    wsg_status rc = ensure_arena(ctx, ctx->fixed, pl.fixed_bytes, ctx->dyn.size);
+    if (rc) return rc;
+    char *fx = (char *)ctx->fixed.ptr;
+    b.fx = fx;
+    // inputs
+    if (v->mem == WSG_MEM_HOST) {
+        if (pl.n_rows > 0) {
+            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_uvw, v->uvw, (size_t)pl.n_rows * 24, hipMemcpyHostToDevice, s));
+            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_vis, v->vis, (size_t)pl.n_elem * pl.vis_sz, hipMemcpyHostToDevice, s));
+            if (v->weights)
+                WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_wts, v->weights, (size_t)pl.n_elem * pl.wt_sz, hipMemcpyHostToDevice, s));
+            if (v->flags)
+                WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_flags, v->flags, (size_t)pl.n_elem, hipMemcpyHostToDevice, s));
+        }
+        b.uvw = (const double *)(fx + pl.o_uvw);
+        b.vis = fx + pl.o_vis;
+        b.wts = v->weights ? fx + pl.o_wts : nullptr;
+        b.flags = v->flags ? (const uint8_t *)(fx + pl.o_flags) : nullptr;
+    } else {
+        b.uvw = v->uvw;
+        b.vis = v->vis;
+        b.wts = v->weights;
+        b.flags = v->flags;
+    }
+    JobGeom &g = b.g;
+    g.n_rows = pl.n_rows;
+    g.n_chan = v->n_chan;
+    g.n_img = pl.n_img;
+    g.N = pl.N;
+    g.n_w = pl.n_w;
+    g.plane_lo = pl.plane_lo;
+    g.n_pl = pl.n_pl;
+    g.S = pl.S;
+    g.h = (pl.S - 1) / 2;
+    g.T = pl.T;
+    g.NT = pl.NT;
+    g.scale = (double)pl.N * p->cell_rad;
+    g.half = 0.5 * (double)pl.N;
+    g.sigma = p->kernel_sigma;
+    g.inv2s2 = 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma);
+    g.range_given = range_given(p) ? 1 : 0;
+    g.w_min_given = p->w_min;
+    g.w_max_given = p->w_max;
+    g.chan_scale = (const double *)(fx + pl.o_scale);
+
+    b.st = (ImgState *)(fx + pl.o_state);
+    b.counts = (uint32_t *)(fx + pl.o_counts);
+    b.offsets = (uint32_t *)(fx + pl.o_offsets);
+    b.cursor = (uint32_t *)(fx + pl.o_cursor);
+    b.nchunk = (uint32_t *)(fx + pl.o_nchunk);
+    b.itemoff = (uint32_t *)(fx + pl.o_itemoff);
+    uint32_t *scan_tmp = (uint32_t *)(fx + pl.o_scan);
+    uint8_t *mask = (uint8_t *)(fx + pl.o_mask);
+
+    // state: keys start at +inf / -inf, counters at 0
+    std::vector<ImgState> init(pl.n_img);
+    for (auto &x : init) {
+        std::memset(&x, 0, sizeof(x));
+        x.wmin_key = ~0ull;
+        x.wmax_key = 0ull;
+    }
+    // per-channel scale and initial state through the pinned staging block
+    // (ensure_pin first waits for the previous copy out of it)
+    rc = ensure_pin(ctx, init.size() * sizeof(ImgState) + (size_t)v->n_chan * 8 + 64);
+    if (rc) return rc;
+    double *hs = (double *)ctx->pin;
+    for (int c = 0; c < v->n_chan; ++c) hs[c] = v->freq_hz ? v->freq_hz[c] / kSpeedOfLight : 1.0;
+    std::memcpy((char *)ctx->pin + align_up((size_t)v->n_chan * 8), init.data(), init.size() * sizeof(ImgState));
+    WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_scale, hs, (size_t)v->n_chan * 8, hipMemcpyHostToDevice, s));
+    WSG_HIP(ctx, hipMemcpyAsync(b.st, (char *)ctx->pin + align_up((size_t)v->n_chan * 8),
+                                init.size() * sizeof(ImgState), hipMemcpyHostToDevice, s));
+    WSG_HIP(ctx, hipEventRecord(ctx->pin_done, s));
+    WSG_HIP(ctx, hipMemsetAsync(b.counts, 0, (pl.n_bins + 1) * 4, s));
+
+    launch_prep(g, pl.f64, b.uvw, b.vis, b.wts, b.flags, mask, b.st, s);
+    launch_finalize_range(g, b.st, s);
+    launch_count(g, b.uvw, b.wts, pl.f64, mask, b.st, b.counts, s);
+    launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
+    // offsets over n_bins + 1 entries: the last one is the record total
+    launch_scan(b.counts, b.offsets, pl.n_bins + 1, scan_tmp, s);
+    launch_chunks(b.counts, b.nchunk, pl.n_bins, kChunk, s);
+    WSG_HIP(ctx, hipMemsetAsync(b.nchunk + pl.n_bins, 0, 4, s));
+    launch_scan(b.nchunk, b.itemoff, pl.n_bins + 1, scan_tmp, s);
+    WSG_HIP(ctx, hipMemcpyAsync(b.cursor, b.offsets, (pl.n_bins + 1) * 4, hipMemcpyDeviceToDevice, s));
+    // totals: records = offsets[n_bins], items = itemoff[n_bins]
+    uint32_t *tot = (uint32_t *)(fx + pl.o_tot);
+    WSG_HIP(ctx, hipMemcpyAsync(tot, b.offsets + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
+    WSG_HIP(ctx, hipMemcpyAsync(tot + 1, b.itemoff + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
+    rc = ensure_pin(ctx, 64);
+    if (rc) return rc;
+    uint32_t *htot = (uint32_t *)ctx->pin;
+    WSG_HIP(ctx, hipMemcpyAsync(htot, tot, 8, hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipStreamSynchronize(s));
+    b.n_records = htot[0];
+    b.n_items = htot[1];
+
+    size_t need = dyn_bytes(pl, b.n_records, b.n_items);
+    rc = ensure_arena(ctx, ctx->dyn, need, ctx->fixed.size);
+    if (rc) return rc;
+    char *dy = (char *)ctx->dyn.ptr;
+    b.records = dy;
+    b.item_bin = (uint32_t *)(dy + align_up((size_t)b.n_records * rec_size(pl.f64)));
+    launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
+    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, b.records, s);
+    return WSG_OK;
+}
+
+wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, hipStream_t s) {
+    launch_zero_split(b.g, b.pl.f64, b.counts, kChunk, grid, transposed, s);
+    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
+                b.records, grid, transposed, s);
+    WSG_HIP(ctx, hipGetLastError());
+    return WSG_OK;
+}
+
+wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream_t s,
+                      wsg_stats *stats, float ms) {
+    if (!stats) return WSG_OK;
+    size_t bytes = (size_t)b.pl.n_img * sizeof(ImgState);
+    wsg_status rc = ensure_pin(ctx, bytes);
+    if (rc) return rc;
+    WSG_HIP(ctx, hipMemcpyAsync(ctx->pin, b.st, bytes, hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipStreamSynchronize(s));
+    const ImgState *hs = (const ImgState *)ctx->pin;
+    int64_t per_img = (b.pl.n_img > 1) ? v->n_rows : v->n_rows * (int64_t)v->n_chan;
+    for (int i = 0; i < b.pl.n_img; ++i) {
+        stats[i].n_used = (int64_t)hs[i].n_used;
+        stats[i].n_flagged = (int64_t)hs[i].n_flagged;
+        stats[i].n_dropped = per_img - stats[i].n_used - stats[i].n_flagged;
+        stats[i].sum_w = hs[i].sum_w;
+        stats[i].w_min = hs[i].w_min;
+        stats[i].w_max = hs[i].w_max;
+        stats[i].ms_total = ms;
+    }
+    return WSG_OK;
+}
+
+wsg_status common_checks(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
+    if (!ctx) return WSG_EINVAL;
+    std::string why;
+    wsg_status rc = check_params(p, why);
+    if (rc) return fail(ctx, rc, why);
+    if (v) {
+        rc = check_vis(p, v, why);
+        if (rc) return fail(ctx, rc, why);
+    }
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    return WSG_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+wsg_status wsg_create(int device, wsg_ctx **out) {
+    if (!out) return WSG_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return WSG_EDEVICE;
+    if (device < 0 || device >= n) return WSG_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return WSG_EDEVICE;
+    wsg_ctx *ctx = new (std::nothrow) wsg_ctx();
+    if (!ctx) return WSG_ENOMEM;
+    ctx->device = device;
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->pin_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        wsg_destroy(ctx);
+        return WSG_EDEVICE;
+    }
+    *out = ctx;
+    return WSG_OK;
+}
+
+void wsg_destroy(wsg_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipDeviceSynchronize();
+    if (ctx->fixed.ptr) (void)hipFree(ctx->fixed.ptr);
+    if (ctx->dyn.ptr) (void)hipFree(ctx->dyn.ptr);
+    for (auto &kv : ctx->twiddles) (void)hipFree(kv.second.ptr);
+    for (auto &kv : ctx->inv_c) (void)hipFree(kv.second.ptr);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->pin_done) (void)hipEventDestroy(ctx->pin_done);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *wsg_strerror(wsg_status s) {
+    switch (s) {
+    case WSG_OK: return "ok";
+    case WSG_EINVAL: return "invalid argument";
+    case WSG_ENOMEM: return "out of memory (workspace budget or device memory)";
+    case WSG_EDEVICE: return "HIP device error";
+    case WSG_EBUSY: return "context busy";
+    case WSG_EUNSUPPORTED: return "unsupported by this build";
+    default: return "unknown status";
+    }
+}
+
+const char *wsg_last_error(const wsg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes) {
+    if (!ctx) return WSG_EINVAL;
+    ctx->budget = bytes;
+    return WSG_OK;
+}
+
+wsg_status wsg_check(const wsg_params *p, const wsg_vis *v) {
+    std::string why;
+    wsg_status rc = check_params(p, why);
+    if (rc) return rc;
+    if (v) return check_vis(p, v, why);
+    return WSG_OK;
+}
+
+int32_t wsg_n_images(const wsg_params *p, const wsg_vis *v) {
+    if (!p || !v) return 0;
+    return n_images(p, v);
+}
+
+wsg_status wsg_footprint(const wsg_params *p, const wsg_vis *v, uint64_t *bytes) {
+    if (!bytes) return WSG_EINVAL;
+    std::string why;
+    wsg_status rc = check_params(p, why);
+    if (rc) return rc;
+    rc = check_vis(p, v, why);
+    if (rc) return rc;
+    int tile = p->tile ? p->tile : default_tile(p);
+    Plan pl = make_plan(p, v, tile, true, false);
+    *bytes = pl.fixed_bytes + dyn_bytes(pl, pl.records_est, pl.items_est);
+    return WSG_OK;
+}
+
+wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                     int32_t image_mem, void *stream, wsg_stats *stats) {
+    wsg_status rc = common_checks(ctx, p, v);
+    if (rc) return rc;
+    if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
+    if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
+    hipStream_t s = pick_stream(ctx, stream);
+    bool host_img = image_mem == WSG_MEM_HOST;
+    if (stats) WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    Binned b;
+    rc = bin_job(ctx, p, v, s, host_img, b);
+    if (rc) return rc;
+    const Plan &pl = b.pl;
+    void *stack = b.fx + pl.o_stack;
+    rc = grid_binned(ctx, b, stack, true, s);
+    if (rc) return rc;
+    const void *tw = nullptr;
+    rc = get_twiddle(ctx, pl.N, pl.f64, &tw);
+    if (rc) return rc;
+    const double *inv_c = nullptr;
+    rc = get_inv_c(ctx, p, s, &inv_c);
+    if (rc) return rc;
+    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, tw, s);
+    WcorrArgs a{};
+    a.N = pl.N;
+    a.n_img = pl.n_img;
+    a.n_pl = pl.n_pl;
+    a.plane_lo = pl.plane_lo;
+    a.n_w = pl.n_w;
+    a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
+    a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
+    a.cell = p->cell_rad;
+    a.st = b.st;
+    a.inv_c = inv_c;
+    double *img_dev = host_img ? (double *)(b.fx + pl.o_image) : image;
+    launch_fft_pass2_wcorr(a, pl.f64, stack, tw, img_dev, s);
+    WSG_HIP(ctx, hipGetLastError());
+    if (host_img)
+        WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)pl.n_img * pl.N * pl.N * 8, hipMemcpyDeviceToHost, s));
+    float ms = 0.f;
+    if (stats) {
+        WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
+        WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
+        WSG_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    } else if (host_img) {
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+    }
+    return read_stats(ctx, b, v, s, stats, ms);
+}
+
+wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, void *grid,
+                          int32_t mem, void *stream, wsg_stats *stats) {
+    wsg_status rc = common_checks(ctx, p, v);
+    if (rc) return rc;
+    if (!grid) return fail(ctx, WSG_EINVAL, "grid is NULL");
+    if (mem != WSG_MEM_HOST && mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad grid memory space");
+    hipStream_t s = pick_stream(ctx, stream);
+    Binned b;
+    rc = bin_job(ctx, p, v, s, false, b);
+    if (rc) return rc;
+    const Plan &pl = b.pl;
+    void *dst = (mem == WSG_MEM_HOST) ? (void *)(b.fx + pl.o_stack) : grid;
+    rc = grid_binned(ctx, b, dst, false, s);
+    if (rc) return rc;
+    if (mem == WSG_MEM_HOST) {
+        size_t bytes = (size_t)pl.n_img * pl.n_pl * pl.N * pl.N * cplx_size(p);
+        WSG_HIP(ctx, hipMemcpyAsync(grid, dst, bytes, hipMemcpyDeviceToHost, s));
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+    }
+    return read_stats(ctx, b, v, s, stats, 0.f);
+}
+
+wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_t n_planes,
+                         int32_t mem, void *stream) {
+    wsg_status rc = common_checks(ctx, p, nullptr);
+    if (rc) return rc;
+    if (!planes || n_planes < 0) return fail(ctx, WSG_EINVAL, "planes is NULL or n_planes < 0");
+    if (mem != WSG_MEM_HOST && mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad memory space");
+    if (n_planes > 65535) return fail(ctx, WSG_EUNSUPPORTED, "more than 65535 planes");
+    if (n_planes == 0) return WSG_OK;
+    hipStream_t s = pick_stream(ctx, stream);
+    int N = p->grid_n;
+    bool f64 = f64_mode(p);
+    size_t bytes = (size_t)n_planes * N * N * cplx_size(p);
+    size_t need = (mem == WSG_MEM_HOST ? 2 : 1) * align_up(bytes);
+    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size);
+    if (rc) return rc;
+    char *fx = (char *)ctx->fixed.ptr;
+    void *src = planes;
+    void *work = fx;
+    if (mem == WSG_MEM_HOST) {
+        src = fx + align_up(bytes);
+        WSG_HIP(ctx, hipMemcpyAsync(src, planes, bytes, hipMemcpyHostToDevice, s));
+    }
+    const void *tw = nullptr;
+    rc = get_twiddle(ctx, N, f64, &tw);
+    if (rc) return rc;
+    launch_transpose(N, f64, src, work, n_planes, s);
+    launch_fft_pass1(N, f64, work, n_planes, tw, s);
+    launch_fft_pass2_store(N, f64, work, src, n_planes, tw, s);
+    WSG_HIP(ctx, hipGetLastError());
+    if (mem == WSG_MEM_HOST) {
+        WSG_HIP(ctx, hipMemcpyAsync(planes, src, bytes, hipMemcpyDeviceToHost, s));
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+    }
+    return WSG_OK;
+}
+
+wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *planes,
+                              int64_t n_planes, double w_min, double w_max, double sum_w,
+                              double *image, int32_t mem, void *stream) {
+    wsg_status rc = common_checks(ctx, p, nullptr);
+    if (rc) return rc;
+    if (!planes || !image || n_planes < 0) return fail(ctx, WSG_EINVAL, "NULL buffer or n_planes < 0");
+    if (mem != WSG_MEM_HOST && mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad memory space");
+    if (!std::isfinite(w_min) || !std::isfinite(w_max) || w_min > w_max || !std::isfinite(sum_w))
+        return fail(ctx, WSG_EINVAL, "bad w range or sum_w");
+    int lo = (p->plane_hi > p->plane_lo) ? p->plane_lo : 0;
+    if (lo + n_planes > p->n_wplanes) return fail(ctx, WSG_EINVAL, "planes beyond n_wplanes");
+    hipStream_t s = pick_stream(ctx, stream);
+    int N = p->grid_n;
+    size_t pbytes = (size_t)n_planes * N * N * cplx_size(p);
+    size_t ibytes = (size_t)N * N * 8;
+    size_t need = align_up(sizeof(ImgState)) + (mem == WSG_MEM_HOST ? align_up(pbytes) + align_up(ibytes) : 0);
+    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size);
+    if (rc) return rc;
+    char *fx = (char *)ctx->fixed.ptr;
+    ImgState *st = (ImgState *)fx;
+    const void *src = planes;
+    double *dst = image;
+    if (mem == WSG_MEM_HOST) {
+        src = fx + align_up(sizeof(ImgState));
+        dst = (double *)(fx + align_up(sizeof(ImgState)) + align_up(pbytes));
+        WSG_HIP(ctx, hipMemcpyAsync((void *)src, planes, pbytes, hipMemcpyHostToDevice, s));
+    }
+    rc = ensure_pin(ctx, sizeof(ImgState));
+    if (rc) return rc;
+    ImgState *hs = (ImgState *)ctx->pin;
+    std::memset(hs, 0, sizeof(ImgState));
+    hs->w_min = w_min;
+    hs->w_max = w_max;
+    hs->dw = (w_max - w_min) / (double)p->n_wplanes;
+    hs->sum_w = sum_w;
+    hs->inv_norm = (p->flags & WSG_NORMALIZE) ? (sum_w > 0.0 ? 1.0 / sum_w : 0.0) : 1.0;
+    WSG_HIP(ctx, hipMemcpyAsync(st, hs, sizeof(ImgState), hipMemcpyHostToDevice, s));
+    WSG_HIP(ctx, hipEventRecord(ctx->pin_done, s));
+    const double *inv_c = nullptr;
+    rc = get_inv_c(ctx, p, s, &inv_c);
+    if (rc) return rc;
+    WcorrArgs a{};
+    a.N = N;
+    a.n_img = 1;
+    a.n_pl = (int)n_planes;
+    a.plane_lo = lo;
+    a.n_w = p->n_wplanes;
+    a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
+    a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
+    a.cell = p->cell_rad;
+    a.st = st;
+    a.inv_c = inv_c;
+    launch_wcorrect(a, f64_mode(p), src, dst, s);
+    WSG_HIP(ctx, hipGetLastError());
+    if (mem == WSG_MEM_HOST) {
+        WSG_HIP(ctx, hipMemcpyAsync(image, dst, ibytes, hipMemcpyDeviceToHost, s));
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+    }
+    return WSG_OK;
+}
+
+wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, const char *cache_path,
+                        int32_t *best_tile) {
+    wsg_status rc = common_checks(ctx, p, v);
+    if (rc) return rc;
+    hipStream_t s = ctx->stream;
+    const int cands[] = {16, 32, 64, 128};
+    float best_ms = 1e30f;
+    int best = default_tile(p);
+    for (int t : cands) {
+        if (t > p->grid_n || (t == 128 && f64_mode(p))) continue;
+        wsg_params q = *p;
+        q.tile = t;
+        float acc = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
+            Binned b;
+            rc = bin_job(ctx, &q, v, s, false, b);
+            if (rc) return rc;
+            rc = grid_binned(ctx, b, b.fx + b.pl.o_stack, true, s);
+            if (rc) return rc;
+            WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
+            WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
+            float ms = 0.f;
+            WSG_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            if (rep > 0) acc += ms;   // first repetition warms the arenas
+        }
+        if (acc < best_ms) {
+            best_ms = acc;
+            best = t;
+        }
+    }
+    auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
+                               decade(v->n_rows * (int64_t)v->n_chan));
+    ctx->tuned[key] = best;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%d %d %d %d %d %d %.4f\n", p->grid_n, p->n_wplanes, p->support, p->precision,
+                         decade(v->n_rows * (int64_t)v->n_chan), best, best_ms / 2);
+            std::fclose(f);
+        }
+    }
+    if (best_tile) *best_tile = best;
+    return WSG_OK;
+}
+
+}  // extern "C"

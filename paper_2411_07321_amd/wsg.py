@@ -1,0 +1,283 @@
+"""ctypes binding of libwsg (include/wsg.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+numpy arrays / torch tensors into pointers, sizes and memory spaces, and
+turns status codes into exceptions.  There is no fallback: if libwsg.so is
+missing or no device is present, calls fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwsg.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PREC = {"f64": 0, "f32_phase64": 1, "f32_phase32": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1 = 1, 2, 4, 8
+
+# symbols declared in include/wsg.h
+SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_set_budget",
+           "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image", "wsg_stage_grid",
+           "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune")
+
+
+class WsgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"wsg status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid_n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32),
+                ("support", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cell_rad", ctypes.c_double), ("kernel_sigma", ctypes.c_double),
+                ("w_min", ctypes.c_double), ("w_max", ctypes.c_double),
+                ("plane_lo", ctypes.c_int32), ("plane_hi", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32)]
+
+
+class Vis(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_chan", ctypes.c_int32), ("mem", ctypes.c_int32),
+                ("uvw", ctypes.c_void_p), ("freq_hz", ctypes.c_void_p), ("vis", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_used", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
+                ("n_dropped", ctypes.c_int64), ("sum_w", ctypes.c_double),
+                ("w_min", ctypes.c_double), ("w_max", ctypes.c_double),
+                ("ms_total", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libwsg.so (built in-tree by paper_2411_07321_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, S = ctypes.c_void_p, ctypes.c_int32
+        lib.wsg_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        lib.wsg_destroy.argtypes = [P]
+        lib.wsg_destroy.restype = None
+        lib.wsg_strerror.argtypes = [S]
+        lib.wsg_strerror.restype = ctypes.c_char_p
+        lib.wsg_last_error.argtypes = [P]
+        lib.wsg_last_error.restype = ctypes.c_char_p
+        lib.wsg_set_budget.argtypes = [P, ctypes.c_uint64]
+        lib.wsg_check.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis)]
+        lib.wsg_footprint.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+        lib.wsg_n_images.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis)]
+        lib.wsg_image.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
+                                  ctypes.POINTER(Stats)]
+        lib.wsg_stage_grid.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
+                                       ctypes.POINTER(Stats)]
+        lib.wsg_stage_fft.argtypes = [P, ctypes.POINTER(Params), P, ctypes.c_int64, S, P]
+        lib.wsg_stage_wcorrect.argtypes = [P, ctypes.POINTER(Params), P, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           P, S, P]
+        lib.wsg_autotune.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis),
+                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+        for name in ("wsg_create", "wsg_set_budget", "wsg_check", "wsg_footprint", "wsg_image",
+                     "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune"):
+            getattr(lib, name).restype = S
+        lib.wsg_n_images.restype = S
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load().wsg_strerror(status).decode()
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr_mem(x):
+    """(pointer, memory space) of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None, None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return x.data_ptr(), (MEM_DEVICE if x.is_cuda else MEM_HOST)
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return x.ctypes.data, MEM_HOST
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def make_params(grid_n, n_wplanes, support, cell_rad, precision="f32_phase64", kernel_sigma=0.9,
+                w_min=None, w_max=None, plane_lo=0, plane_hi=0, grid_correct=True,
+                normalize=True, per_channel=False, naive_nm1=False, tile=0) -> Params:
+    flags = (GRID_CORRECT if grid_correct else 0) | (NORMALIZE if normalize else 0) | \
+        (PER_CHANNEL if per_channel else 0) | (NAIVE_NM1 if naive_nm1 else 0)
+    return Params(int(grid_n), int(n_wplanes), int(support), PREC[precision], float(cell_rad),
+                  float(kernel_sigma), math.nan if w_min is None else float(w_min),
+                  math.nan if w_max is None else float(w_max), int(plane_lo), int(plane_hi),
+                  flags, int(tile))
+
+
+@dataclass
+class VisBuffers:
+    """Keeps the arrays behind a Vis descriptor alive for the duration of a call."""
+    desc: Vis
+    keep: tuple
+
+
+def make_vis(uvw, vis, weights=None, flags=None, freq_hz=None) -> VisBuffers:
+    """Describe measurements: uvw [rows,3] f64, vis [rows,n_chan] complex, weights and flags
+    [rows,n_chan] or None, freq_hz (host) or None.  All buffers in one memory space."""
+    pu, mu = _ptr_mem(uvw)
+    pv, mv = _ptr_mem(vis)
+    pw, mw = _ptr_mem(weights)
+    pf, mf = _ptr_mem(flags)
+    spaces = {m for m in (mu, mv, mw, mf) if m is not None}
+    if len(spaces) > 1:
+        raise ValueError("uvw, vis, weights and flags must live in one memory space")
+    n_rows = uvw.shape[0]
+    n_chan = vis.shape[1] if vis.ndim == 2 else 1
+    fq = None
+    if freq_hz is not None:
+        fq = np.ascontiguousarray(freq_hz, dtype=np.float64)
+    d = Vis(int(n_rows), int(n_chan), spaces.pop() if spaces else MEM_HOST, pu, None if fq is None
+            else fq.ctypes.data, pv, pw, pf)
+    return VisBuffers(d, (uvw, vis, weights, flags, fq))
+
+
+def _stream_of(x, stream):
+    if stream is not None:
+        return stream
+    if _is_torch(x) and x.is_cuda:
+        import torch
+        return torch.cuda.current_stream(x.device).cuda_stream
+    return None
+
+
+class Context:
+    """One library context on one HIP device (owns workspace and its own stream)."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        st = lib.wsg_create(int(device), ctypes.byref(h))
+        if st != OK:
+            raise WsgError(st, f"wsg_create(device={device}) failed: {strerror(st)}")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wsg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st: int, what: str):
+        if st != OK:
+            detail = load().wsg_last_error(self._h).decode()
+            raise WsgError(st, f"{what}: {strerror(st)} ({detail})")
+
+    def set_budget(self, nbytes: int):
+        self._check(load().wsg_set_budget(self._h, int(nbytes)), "wsg_set_budget")
+
+    def image(self, params: Params, vb: VisBuffers, out, stream=None, stats: bool = True):
+        """Run the method; `out` is [n_images,N,N] (or [N,N]) float64 host array or device
+        tensor.  Returns per-image stats (list of dicts) when stats is True."""
+        po, mo = _ptr_mem(out)
+        n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
+        st_arr = (Stats * max(1, n_img))() if stats else None
+        s = _stream_of(out, stream)
+        rc = load().wsg_image(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
+                              s, st_arr)
+        self._check(rc, "wsg_image")
+        return [x.as_dict() for x in st_arr] if stats else None
+
+    def stage_grid(self, params: Params, vb: VisBuffers, out, stream=None):
+        po, mo = _ptr_mem(out)
+        n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
+        st_arr = (Stats * max(1, n_img))()
+        rc = load().wsg_stage_grid(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
+                                   _stream_of(out, stream), st_arr)
+        self._check(rc, "wsg_stage_grid")
+        return [x.as_dict() for x in st_arr]
+
+    def stage_fft(self, params: Params, planes, stream=None):
+        po, mo = _ptr_mem(planes)
+        n = planes.shape[0] if planes.ndim == 3 else 1
+        rc = load().wsg_stage_fft(self._h, ctypes.byref(params), po, int(n), mo,
+                                  _stream_of(planes, stream))
+        self._check(rc, "wsg_stage_fft")
+
+    def stage_wcorrect(self, params: Params, planes, w_min, w_max, sum_w, out, stream=None):
+        pp, mp = _ptr_mem(planes)
+        po, mo = _ptr_mem(out)
+        if mp != mo:
+            raise ValueError("planes and image must live in one memory space")
+        n = planes.shape[0] if planes.ndim == 3 else 1
+        rc = load().wsg_stage_wcorrect(self._h, ctypes.byref(params), pp, int(n), float(w_min),
+                                       float(w_max), float(sum_w), po, mo,
+                                       _stream_of(out, stream))
+        self._check(rc, "wsg_stage_wcorrect")
+
+    def autotune(self, params: Params, vb: VisBuffers, cache_path: str | None = None) -> int:
+        best = ctypes.c_int32(0)
+        rc = load().wsg_autotune(self._h, ctypes.byref(params), ctypes.byref(vb.desc),
+                                 None if cache_path is None else cache_path.encode(),
+                                 ctypes.byref(best))
+        self._check(rc, "wsg_autotune")
+        return int(best.value)
+
+
+def check(params: Params, vb: VisBuffers | None = None) -> int:
+    return load().wsg_check(ctypes.byref(params), None if vb is None else ctypes.byref(vb.desc))
+
+
+def footprint(params: Params, vb: VisBuffers) -> int:
+    out = ctypes.c_uint64(0)
+    st = load().wsg_footprint(ctypes.byref(params), ctypes.byref(vb.desc), ctypes.byref(out))
+    if st != OK:
+        raise WsgError(st, f"wsg_footprint: {strerror(st)}")
+    return int(out.value)
+
+
+def n_images(params: Params, vb: VisBuffers) -> int:
+    return int(load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc)))
+
+
+def params_for(ds, **over) -> Params:
+    """Parameters of a synthetic Dataset (paper_2411_07321_amd.synth), with overrides."""
+    kw = dict(grid_n=ds.grid_n, n_wplanes=ds.n_wplanes, support=ds.support, cell_rad=ds.cell_rad,
+              precision=ds.precision, kernel_sigma=ds.kernel_sigma, per_channel=ds.per_channel)
+    kw.update(over)
+    return make_params(**kw)

@@ -1,0 +1,107 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every symbol
+include/wsg.h declares, validates parameters and reports footprints."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_07321_amd import wsg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "wsg.h")).read()
+    return sorted(set(re.findall(r"\b(wsg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = wsg.load()
+    names = _declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(wsg.SYMBOLS)
+
+
+def _p(**kw):
+    base = dict(grid_n=256, n_wplanes=8, support=7, cell_rad=1e-4, precision="f64")
+    base.update(kw)
+    return wsg.make_params(**base)
+
+
+def _v(n_rows=10, n_chan=1, **kw):
+    uvw = np.zeros((n_rows, 3))
+    vis = np.zeros((n_rows, n_chan), np.complex128)
+    return wsg.make_vis(uvw, vis, **kw)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), wsg.OK),
+    (dict(grid_n=100), wsg.EINVAL),
+    (dict(grid_n=8), wsg.EUNSUPPORTED),
+    (dict(grid_n=8192), wsg.EUNSUPPORTED),
+    (dict(support=6), wsg.EINVAL),
+    (dict(support=0), wsg.EINVAL),
+    (dict(support=17), wsg.EUNSUPPORTED),
+    (dict(n_wplanes=0), wsg.EINVAL),
+    (dict(cell_rad=0.0), wsg.EINVAL),
+    (dict(cell_rad=math.nan), wsg.EINVAL),
+    (dict(kernel_sigma=-1.0), wsg.EINVAL),
+    (dict(w_min=1.0), wsg.EINVAL),                       # one-sided range
+    (dict(w_min=2.0, w_max=1.0), wsg.EINVAL),
+    (dict(w_min=-1.0, w_max=math.inf), wsg.EINVAL),
+    (dict(plane_lo=2, plane_hi=4), wsg.EINVAL),          # shard without a given range
+    (dict(plane_lo=2, plane_hi=4, w_min=0.0, w_max=1.0), wsg.OK),
+    (dict(plane_lo=4, plane_hi=4, w_min=0.0, w_max=1.0), wsg.EINVAL),
+    (dict(plane_lo=0, plane_hi=9, w_min=0.0, w_max=1.0), wsg.EINVAL),
+    (dict(tile=48), wsg.EINVAL),
+    (dict(tile=128), wsg.EUNSUPPORTED),                  # FP64 mesh tile limit
+    (dict(tile=128, precision="f32_phase64"), wsg.OK),
+])
+def test_parameter_validation(kw, code):
+    assert wsg.check(_p(**kw), _v()) == code
+
+
+def test_vis_validation():
+    assert wsg.check(_p(), _v(n_rows=0)) == wsg.OK
+    bad = _v()
+    bad.desc.n_chan = 0
+    assert wsg.check(_p(), bad) == wsg.EINVAL
+    bad = _v()
+    bad.desc.uvw = None
+    assert wsg.check(_p(), bad) == wsg.EINVAL
+    bad = _v()
+    bad.desc.mem = 7
+    assert wsg.check(_p(), bad) == wsg.EINVAL
+    assert wsg.check(_p(), _v(freq_hz=np.array([-1.0]))) == wsg.EINVAL
+    assert wsg.check(_p(per_channel=True), _v(n_chan=300)) == wsg.EUNSUPPORTED
+
+
+def test_footprint_scales_with_mesh():
+    f1 = wsg.footprint(_p(grid_n=256), _v(n_rows=1000))
+    f2 = wsg.footprint(_p(grid_n=512), _v(n_rows=1000))
+    # the plane stack dominates: 8 planes x N^2 x 16 bytes
+    assert f1 >= 8 * 256 * 256 * 16
+    assert 3.5 < f2 / f1 < 4.5
+    f3 = wsg.footprint(_p(grid_n=256, precision="f32_phase64"), _v(n_rows=1000))
+    assert f3 < f1
+    assert wsg.n_images(_p(per_channel=True), _v(n_chan=5)) == 5
+    assert wsg.n_images(_p(), _v(n_chan=5)) == 1
+
+
+def test_strerror():
+    assert wsg.strerror(wsg.OK) == "ok"
+    assert "invalid" in wsg.strerror(wsg.EINVAL)
+    assert "unknown" in wsg.strerror(-99)
+
+
+def test_no_device_is_a_loud_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(wsg.WsgError) as e:
+        wsg.Context(0)
+    assert e.value.status in (wsg.EDEVICE, wsg.EINVAL)
