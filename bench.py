@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the w-stacking imager on one MI355X.
+
+A step is one whole imaging job through the C ABI (wsg_image): validity pass,
+binning, gridding (Eq. 3), per-plane 2D inverse transforms and the w-correction
+with plane sum (Eq. 2), on the single-large-image workload: 256 antennas
+(log-radial, 20 km), 2,048 times, 4 channels -> 267,386,880 complex64
+visibilities onto a 4096^2 x 64-plane complex64 stack, support 7, FP64 phase.
+Inputs are synthetic (seeded), generated on and resident in HBM before timing.
+
+Prints ONE JSON line (rank 0).  See the design doc for the byte model behind the
+roofline figures.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_bin.hip", "k_grid.hip", "k_fft.hip", "wsg_lib.cpp", "wsg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2411_07321_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# stage name in wsg_stats -> (kernel(s), algorithmic bytes of that stage given the job)
+def stage_bytes(job) -> dict:
+    m, rows, nch = job["n_elem"], job["n_rows"], job["n_chan"]
+    n, nw = job["grid_n"], job["n_pl"]
+    csz = 16 if job["precision"] == "f64" else 8
+    vsz, wsz = (16, 8) if job["precision"] == "f64" else (8, 4)
+    b_in = rows * 24 + m * (vsz + wsz)
+    b_grid = nw * n * n * csz
+    b_img = n * n * 8
+    rec = 40 if job["precision"] == "f64" else 16
+    n_rec = job["n_records"]
+    return {
+        # validity pass: every input byte read once
+        "ms_prep": ("k_prep", b_in),
+        # counting: uvw read once
+        "ms_count": ("k_count", rows * 24),
+        # scatter: inputs read once, one record per (visibility, tile) written
+        "ms_scatter": ("k_scatter", b_in + n_rec * rec),
+        # gridding: records read once, every cell of the stack written once
+        "ms_grid": ("k_grid", n_rec * rec + b_grid),
+        # transform pass 1: the stack read and written once
+        "ms_fft1": ("k_pass1", 2 * b_grid),
+        # pass 2 + w-correction: the stack read once, the image written once
+        "ms_fft2_wcorr": ("k_pass2_wcorr", b_grid + b_img),
+    }, {"B_in": b_in, "B_grid": b_grid, "B_img": b_img,
+        "B_alg": b_in + 2 * b_grid + b_img}
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy-kernel calibration), if recorded for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    rec = t.get(workload, {}).get(kernel)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(ds_host: dict, params: dict, n_total: int) -> dict:
+    """The FP64 oracle (unchanged) on a bounded sample of the same workload, scaled to the
+    whole job: gridding of a row subsample with every measurement on one plane (the
+    per-visibility work does not depend on the plane count), plus one plane's transform
+    and w-correction, extrapolated to all visibilities and planes."""
+    import numpy as np
+    import oracle
+    uvw, vis, wts, freq = ds_host["uvw"], ds_host["vis"], ds_host["weights"], ds_host["freq"]
+    m_s = vis.size
+    inp = oracle.Inputs.make(uvw, freq, vis, wts)
+    n = params["grid_n"]
+    prm1 = oracle.Params(n, 1, params["support"], params["cell_rad"], params["kernel_sigma"])
+    t0 = time.perf_counter()
+    wmin, wmax = oracle.w_range(inp, prm1)
+    g, cnt = oracle.grid(inp, prm1, wmin, wmax)
+    t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F = oracle.fft_planes(g)
+    t_fft = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    A = oracle.wcorrect(F, wmin, wmax, 1, params["cell_rad"])
+    D = oracle.post(A, cnt["sum_w"], prm1)
+    t_wc = time.perf_counter() - t0
+    del g, F, A, D
+    nw = params["n_wplanes"]
+    t_est = t_grid * (n_total / m_s) + nw * (t_fft + t_wc)
+    return {"value": n_total / t_est, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle, 1 thread: {m_s:,} visibilities (row subsample) gridded on "
+                       f"the {n}^2 mesh in {t_grid:.2f} s, one plane transformed in "
+                       f"{t_fft:.2f} s and w-corrected in {t_wc:.2f} s; extrapolated to "
+                       f"{n_total:,} visibilities and {nw} planes = {t_est:.0f} s per job")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rows-stride", type=int, default=1,
+                    help="keep every k-th row (quick runs only; not the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=400_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build images on one GPU; multi-GPU runs (w-plane "
+                                   "sharding) are not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2411_07321_amd import synth, wsg
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    progress("generating config 1 on the device")
+    t0 = time.perf_counter()
+    d = synth.config1_device(dev, rows_stride=args.rows_stride)
+    torch.cuda.synchronize()
+    progress(f"inputs ready in {time.perf_counter() - t0:.1f} s: vis {tuple(d['vis'].shape)}")
+    prm = wsg.make_params(**d["params"])
+    vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"])
+    n = d["params"]["grid_n"]
+    out = torch.empty((1, n, n), dtype=torch.float64, device=dev)
+    ctx = wsg.Context(0)
+    ctx.set_timing(True)
+    for i in range(args.warmup):
+        st = ctx.image(prm, vb, out)
+        progress(f"warmup {i}: {st[0]['ms_total']:.2f} ms")
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = ctx.image(prm, vb, out)
+        stages.append(st[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    s0 = stages[-1]
+    n_used = int(s0["n_used"])
+    progress(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {n_used} visibilities used")
+
+    mean = {k: float(np.mean([s[k] for s in stages])) for k in
+            ("ms_prep", "ms_count", "ms_scatter", "ms_grid", "ms_fft1", "ms_fft2_wcorr", "ms_total")}
+    # records written by the scatter (one per visibility and tile its footprint touches)
+    job = {"n_elem": d["vis"].numel(), "n_rows": d["uvw"].shape[0], "n_chan": d["vis"].shape[1],
+           "grid_n": n, "n_pl": d["params"]["n_wplanes"], "precision": d["params"]["precision"],
+           "n_records": int(s0["n_records"])}
+    sb, model = stage_bytes(job)
+    dom = max(sb, key=lambda k: mean[k])
+    kname, kbytes = sb[dom]
+    achieved = kbytes / (mean[dom] * 1e-3) / 1e9
+    workload = "config1_4096sq_64w_2.67e8vis" if args.rows_stride == 1 else \
+        f"config1_rows_stride_{args.rows_stride}"
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(kname, workload), "avg_ms": round(mean[dom], 3),
+            "alg_bytes": kbytes}
+    path_gbs = model["B_alg"] / (ms_step * 1e-3) / 1e9
+    result = {
+        "metric": "visibilities gridded+imaged/s", "value": n_used / (ms_step * 1e-3),
+        "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 mesh+FFT, f64 phase+image",
+        "data": "synthetic (seeded, device-generated config-1 interferometer data)",
+        "config": {"workload": workload, "grid_n": n, "n_wplanes": d["params"]["n_wplanes"],
+                   "support": 7, "visibilities": int(d["vis"].numel()), "n_used": n_used,
+                   "precision": d["params"]["precision"], "tile": 0},
+        "roofline": roof,
+        "path_roofline": {"B_alg_bytes": model["B_alg"], "achieved": round(path_gbs, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "stage_ms": {k: round(v, 3) for k, v in mean.items()},
+    }
+    if not args.no_cpu_baseline:
+        progress("cpu baseline: oracle on a bounded sample")
+        k = max(1, d["uvw"].shape[0] // args.cpu_sample_rows)
+        host = {"uvw": d["uvw"][::k].cpu().numpy().copy(),
+                "vis": d["vis"][::k].cpu().numpy().astype(np.complex128),
+                "weights": d["weights"][::k].cpu().numpy().astype(np.float64),
+                "freq": d["freq_hz"]}
+        result["cpu_baseline"] = cpu_baseline(host, d["params"], int(d["vis"].numel()))
+        progress(f"cpu baseline {result['cpu_baseline']['value']:.3e} vis/s")
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

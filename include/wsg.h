@@ -113,8 +113,15 @@ typedef struct {
 
 typedef struct {
     int64_t n_used, n_flagged, n_dropped;
+    int64_t n_records;       /* binning records of the whole job: one per (visibility, uv     */
+                             /*   tile its footprint touches)                                 */
     double sum_w, w_min, w_max;
-    float ms_total;          /* device time of the call (hipEvents), 0 if not measured        */
+    /* device time in ms between hipEvents recorded on the job's stream, filled when
+     * timing is on (wsg_set_timing); all 0 otherwise.  The stages are: staging of
+     * host inputs and the validity pass; counting and scans; record scatter;
+     * gridding; transform pass 1; transform pass 2 with w-correction and plane sum.
+     * ms_total spans the whole call, host waits included. */
+    float ms_prep, ms_count, ms_scatter, ms_grid, ms_fft1, ms_fft2_wcorr, ms_total;
 } wsg_stats;
 
 /* ---------------------------------------------------------------------------
@@ -129,6 +136,9 @@ const char *wsg_strerror(wsg_status s);
 const char *wsg_last_error(const wsg_ctx *ctx);
 /* Limit the context's workspace to `bytes` (0 = no limit); larger jobs fail with ENOMEM. */
 wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes);
+/* Record hipEvents between the stages of wsg_image and report their durations in
+ * wsg_stats (on = 1) or not (on = 0, the default). */
+wsg_status wsg_set_timing(wsg_ctx *ctx, int32_t on);
 
 /* ---------------------------------------------------------------------------
  * Host-side checks (no device needed)

@@ -56,6 +56,9 @@ struct wsg_ctx {
     size_t pin_size = 0;
     hipEvent_t pin_done = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // stage timing: events recorded at the stage boundaries of wsg_image
+    int timing = 0;
+    hipEvent_t tev[8] = {};
 };
 
 namespace {
@@ -362,6 +365,13 @@ int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
     return default_tile(p);
 }
 
+// stage boundary marks (no-ops unless timing is on)
+enum { kMarkStart = 0, kMarkPrep, kMarkCount, kMarkScatterStart, kMarkScatter, kMarkGrid, kMarkFft1, kMarkEnd };
+
+void mark(wsg_ctx *ctx, int i, hipStream_t s) {
+    if (ctx->timing) (void)hipEventRecord(ctx->tev[i], s);
+}
+
 hipStream_t pick_stream(wsg_ctx *ctx, void *stream) {
     return stream ? (hipStream_t)stream : ctx->stream;
 }
@@ -469,6 +479,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
 
     launch_prep(g, pl.f64, b.uvw, b.vis, b.wts, b.flags, mask, b.st, s);
     launch_finalize_range(g, b.st, s);
+    mark(ctx, kMarkPrep, s);
     launch_count(g, b.uvw, b.wts, pl.f64, mask, b.st, b.counts, s);
     launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
     // offsets over n_bins + 1 entries: the last one is the record total
@@ -481,6 +492,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     uint32_t *tot = (uint32_t *)(fx + pl.o_tot);
     WSG_HIP(ctx, hipMemcpyAsync(tot, b.offsets + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
     WSG_HIP(ctx, hipMemcpyAsync(tot + 1, b.itemoff + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
+    mark(ctx, kMarkCount, s);
     rc = ensure_pin(ctx, 64);
     if (rc) return rc;
     uint32_t *htot = (uint32_t *)ctx->pin;
@@ -495,8 +507,10 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     char *dy = (char *)ctx->dyn.ptr;
     b.records = dy;
     b.item_bin = (uint32_t *)(dy + align_up((size_t)b.n_records * rec_size(pl.f64)));
+    mark(ctx, kMarkScatterStart, s);
     launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
     launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, b.records, s);
+    mark(ctx, kMarkScatter, s);
     return WSG_OK;
 }
 
@@ -509,8 +523,18 @@ wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, hip
 }
 
 wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream_t s,
-                      wsg_stats *stats, float ms) {
+                      wsg_stats *stats, bool timed) {
     if (!stats) return WSG_OK;
+    float t[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (timed) {
+        WSG_HIP(ctx, hipEventSynchronize(ctx->tev[kMarkEnd]));
+        const int pairs[7][2] = {{kMarkStart, kMarkPrep}, {kMarkPrep, kMarkCount},
+                                 {kMarkScatterStart, kMarkScatter}, {kMarkScatter, kMarkGrid},
+                                 {kMarkGrid, kMarkFft1}, {kMarkFft1, kMarkEnd},
+                                 {kMarkStart, kMarkEnd}};
+        for (int i = 0; i < 7; ++i)
+            WSG_HIP(ctx, hipEventElapsedTime(&t[i], ctx->tev[pairs[i][0]], ctx->tev[pairs[i][1]]));
+    }
     size_t bytes = (size_t)b.pl.n_img * sizeof(ImgState);
     wsg_status rc = ensure_pin(ctx, bytes);
     if (rc) return rc;
@@ -522,10 +546,17 @@ wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream
         stats[i].n_used = (int64_t)hs[i].n_used;
         stats[i].n_flagged = (int64_t)hs[i].n_flagged;
         stats[i].n_dropped = per_img - stats[i].n_used - stats[i].n_flagged;
+        stats[i].n_records = (int64_t)b.n_records;
         stats[i].sum_w = hs[i].sum_w;
         stats[i].w_min = hs[i].w_min;
         stats[i].w_max = hs[i].w_max;
-        stats[i].ms_total = ms;
+        stats[i].ms_prep = t[0];
+        stats[i].ms_count = t[1];
+        stats[i].ms_scatter = t[2];
+        stats[i].ms_grid = t[3];
+        stats[i].ms_fft1 = t[4];
+        stats[i].ms_fft2_wcorr = t[5];
+        stats[i].ms_total = t[6];
     }
     return WSG_OK;
 }
@@ -562,7 +593,12 @@ wsg_status wsg_create(int device, wsg_ctx **out) {
     ctx->device = device;
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->pin_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        [&] {
+            for (auto &e : ctx->tev)
+                if (hipEventCreate(&e) != hipSuccess) return true;
+            return false;
+        }()) {
         wsg_destroy(ctx);
         return WSG_EDEVICE;
     }
@@ -583,6 +619,8 @@ void wsg_destroy(wsg_ctx *ctx) {
     if (ctx->pin_done) (void)hipEventDestroy(ctx->pin_done);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (auto &e : ctx->tev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -604,6 +642,12 @@ const char *wsg_last_error(const wsg_ctx *ctx) { return ctx ? ctx->last_error.c_
 wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes) {
     if (!ctx) return WSG_EINVAL;
     ctx->budget = bytes;
+    return WSG_OK;
+}
+
+wsg_status wsg_set_timing(wsg_ctx *ctx, int32_t on) {
+    if (!ctx) return WSG_EINVAL;
+    ctx->timing = on ? 1 : 0;
     return WSG_OK;
 }
 
@@ -641,21 +685,23 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
     if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
     hipStream_t s = pick_stream(ctx, stream);
     bool host_img = image_mem == WSG_MEM_HOST;
-    if (stats) WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    mark(ctx, kMarkStart, s);
     Binned b;
     rc = bin_job(ctx, p, v, s, host_img, b);
     if (rc) return rc;
     const Plan &pl = b.pl;
     void *stack = b.fx + pl.o_stack;
-    rc = grid_binned(ctx, b, stack, true, s);
-    if (rc) return rc;
     const void *tw = nullptr;
     rc = get_twiddle(ctx, pl.N, pl.f64, &tw);
     if (rc) return rc;
     const double *inv_c = nullptr;
     rc = get_inv_c(ctx, p, s, &inv_c);
     if (rc) return rc;
+    rc = grid_binned(ctx, b, stack, true, s);
+    if (rc) return rc;
+    mark(ctx, kMarkGrid, s);
     launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, tw, s);
+    mark(ctx, kMarkFft1, s);
     WcorrArgs a{};
     a.N = pl.N;
     a.n_img = pl.n_img;
@@ -672,15 +718,9 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
     WSG_HIP(ctx, hipGetLastError());
     if (host_img)
         WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)pl.n_img * pl.N * pl.N * 8, hipMemcpyDeviceToHost, s));
-    float ms = 0.f;
-    if (stats) {
-        WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
-        WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
-        WSG_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    } else if (host_img) {
-        WSG_HIP(ctx, hipStreamSynchronize(s));
-    }
-    return read_stats(ctx, b, v, s, stats, ms);
+    mark(ctx, kMarkEnd, s);
+    if (!stats && host_img) WSG_HIP(ctx, hipStreamSynchronize(s));
+    return read_stats(ctx, b, v, s, stats, ctx->timing != 0);
 }
 
 wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, void *grid,
@@ -702,7 +742,7 @@ wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, v
         WSG_HIP(ctx, hipMemcpyAsync(grid, dst, bytes, hipMemcpyDeviceToHost, s));
         WSG_HIP(ctx, hipStreamSynchronize(s));
     }
-    return read_stats(ctx, b, v, s, stats, 0.f);
+    return read_stats(ctx, b, v, s, stats, false);
 }
 
 wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_t n_planes,

@@ -325,3 +325,62 @@ def random_visibilities(n_rows: int, n_chan: int, grid_n: int, cell: float, seed
     vis = rng.standard_normal((n_rows, n_chan)) + 1j * rng.standard_normal((n_rows, n_chan))
     wts = rng.uniform(0.5, 1.5, (n_rows, n_chan))
     return uvw, vis, wts
+
+
+# ----------------------------------------------------------------------------
+# large configurations generated on the device (torch), for benchmarks
+# ----------------------------------------------------------------------------
+def visibilities_device(uvw_dev, scale, sky: Sky, noise_sigma: float, seed: int,
+                        dtype=None, chunk: int = 1 << 18):
+    """As `visibilities` (Eq. 1, apparent fluxes, FP64) but on the device holding uvw_dev,
+    plus complex Gaussian noise from a seeded torch generator on that device; returns a
+    [rows, n_chan] tensor of `dtype` (complex64 by default) on the device."""
+    import torch
+    dev = uvw_dev.device
+    dtype = dtype or torch.complex64
+    eta = sky.l ** 2 + sky.m ** 2
+    nm1 = -eta / (1.0 + np.sqrt(1.0 - eta))
+    lmn = torch.tensor(np.stack([sky.l, sky.m, nm1], axis=0), dtype=torch.float64, device=dev)
+    flux = torch.tensor(sky.flux, dtype=torch.float64, device=dev)
+    rows, n_chan = uvw_dev.shape[0], len(scale)
+    out = torch.empty((rows, n_chan), dtype=dtype, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    two_pi = 2.0 * math.pi
+    for r0 in range(0, rows, chunk):
+        r1 = min(rows, r0 + chunk)
+        ph0 = uvw_dev[r0:r1] @ lmn
+        for c in range(n_chan):
+            ph = ph0 * (-two_pi * float(scale[c]))
+            re = (torch.cos(ph) * flux).sum(dim=1)
+            im = (torch.sin(ph) * flux).sum(dim=1)
+            if noise_sigma > 0:
+                z = torch.randn((r1 - r0, 2), dtype=torch.float64, device=dev, generator=gen)
+                re = re + noise_sigma * z[:, 0]
+                im = im + noise_sigma * z[:, 1]
+            out[r0:r1, c] = torch.complex(re, im).to(dtype)
+    return out
+
+
+def config1_device(device="cuda", seed: int = CONFIG_SEED0 + 1, grid_n: int = 4096,
+                   n_wplanes: int = 64, precision: str = "f32_phase64", rows_stride: int = 1):
+    """Config 1 (or, with grid_n=2048 / n_wplanes=32, config 2) with the arrays resident on
+    the device: dict(uvw f64 [rows,3], vis complex64/128 [rows,4], weights f32/f64
+    [rows,4], freq_hz numpy, params dict, sky).  Same layout, frequencies and sky as
+    config1(); the noise comes from a seeded torch generator on the device."""
+    import torch
+    rng = np.random.default_rng(seed)
+    en = layout_log_radial(256, 30.0, 10000.0, rng)
+    uvw = uvw_tracks(baselines_xyz(en), hour_angles(2048))
+    if rows_stride > 1:
+        uvw = np.ascontiguousarray(uvw[::rows_stride])
+    freq = (150.5 + (np.arange(4) - 1.5) * 0.48828) * 1e6
+    sky = point_sources(200, 0.095, 4096, 0.2 / 4096, rng)
+    uvw_d = torch.from_numpy(uvw).to(device)
+    f64 = precision == "f64"
+    vis = visibilities_device(uvw_d, freq / C_LIGHT, sky, 0.01, seed,
+                              dtype=torch.complex128 if f64 else torch.complex64)
+    wts = torch.ones(vis.shape, dtype=torch.float64 if f64 else torch.float32, device=device)
+    return {"uvw": uvw_d, "vis": vis, "weights": wts, "freq_hz": freq, "sky": sky,
+            "params": dict(grid_n=grid_n, n_wplanes=n_wplanes, support=7,
+                           cell_rad=0.2 / grid_n, precision=precision, kernel_sigma=0.9)}

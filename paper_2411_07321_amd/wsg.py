@@ -24,6 +24,7 @@ GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1 = 1, 2, 4, 8
 
 # symbols declared in include/wsg.h
 SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_set_budget",
+           "wsg_set_timing",
            "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image", "wsg_stage_grid",
            "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune")
 
@@ -51,8 +52,12 @@ class Vis(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_used", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
-                ("n_dropped", ctypes.c_int64), ("sum_w", ctypes.c_double),
+                ("n_dropped", ctypes.c_int64), ("n_records", ctypes.c_int64),
+                ("sum_w", ctypes.c_double),
                 ("w_min", ctypes.c_double), ("w_max", ctypes.c_double),
+                ("ms_prep", ctypes.c_float), ("ms_count", ctypes.c_float),
+                ("ms_scatter", ctypes.c_float), ("ms_grid", ctypes.c_float),
+                ("ms_fft1", ctypes.c_float), ("ms_fft2_wcorr", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
 
     def as_dict(self) -> dict:
@@ -79,6 +84,7 @@ def load() -> ctypes.CDLL:
         lib.wsg_last_error.argtypes = [P]
         lib.wsg_last_error.restype = ctypes.c_char_p
         lib.wsg_set_budget.argtypes = [P, ctypes.c_uint64]
+        lib.wsg_set_timing.argtypes = [P, S]
         lib.wsg_check.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis)]
         lib.wsg_footprint.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis),
                                       ctypes.POINTER(ctypes.c_uint64)]
@@ -93,7 +99,7 @@ def load() -> ctypes.CDLL:
                                            P, S, P]
         lib.wsg_autotune.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis),
                                      ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
-        for name in ("wsg_create", "wsg_set_budget", "wsg_check", "wsg_footprint", "wsg_image",
+        for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_image",
                      "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune"):
             getattr(lib, name).restype = S
         lib.wsg_n_images.restype = S
@@ -210,6 +216,9 @@ class Context:
 
     def set_budget(self, nbytes: int):
         self._check(load().wsg_set_budget(self._h, int(nbytes)), "wsg_set_budget")
+
+    def set_timing(self, on: bool):
+        self._check(load().wsg_set_timing(self._h, 1 if on else 0), "wsg_set_timing")
 
     def image(self, params: Params, vb: VisBuffers, out, stream=None, stats: bool = True):
         """Run the method; `out` is [n_images,N,N] (or [N,N]) float64 host array or device

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "wsg.h")).read()
-    return sorted(set(re.findall(r"\b(wsg_[a-z_0-9]+)\s*\(", src)))
+    decl = r"^\s*(?:wsg_status|void|const char \*|int32_t)\s*\*?\s*(wsg_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
 
 
 def test_header_symbols_exported():
