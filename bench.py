@@ -141,7 +141,7 @@ def main():
     torch.cuda.synchronize()
     progress(f"inputs ready in {time.perf_counter() - t0:.1f} s: vis {tuple(d['vis'].shape)}")
     prm = wsg.make_params(**d["params"])
-    vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"])
+    vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"], d["row_period"])
     n = d["params"]["grid_n"]
     out = torch.empty((1, n, n), dtype=torch.float64, device=dev)
     ctx = wsg.Context(0)

@@ -103,6 +103,9 @@ typedef struct {
     int64_t n_rows;          /* rows (baseline x time samples)                                */
     int32_t n_chan;          /* channels per row (>= 1)                                       */
     int32_t mem;             /* WSG_MEM_* of uvw, vis, weights and flags                      */
+    int64_t row_period;      /* performance hint, results do not depend on it: rows of one    */
+                             /*   baseline recur every row_period rows (the baselines per     */
+                             /*   time slice of time-major data); 0 or 1 = no such structure  */
     const double *uvw;       /* [n_rows][3]; wavelengths if freq_hz is NULL, else metres      */
     const double *freq_hz;   /* HOST array [n_chan] or NULL                                   */
     const void *vis;         /* [n_rows][n_chan] interleaved (re, im): complex128 if F64,    */
@@ -190,6 +193,44 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
  * text file cache_path if not NULL).  *best_tile receives the choice. */
 wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
                         const char *cache_path, int32_t *best_tile);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent imaging jobs on one device
+ * ------------------------------------------------------------------------- */
+/*
+ * A server owns n_slots worker threads, each with its own context (stream and
+ * workspace).  Submitted jobs wait in a FIFO queue and are admitted while a
+ * slot is free and the device memory held by all slots stays within
+ * hbm_budget bytes (0 = no limit): the first queued job that fits is started,
+ * so a large job does not block smaller ones behind it.  Admitted jobs run
+ * concurrently on their slots' streams; their staging copies, kernels and
+ * read-back overlap on the device.  A job that fails (bad parameters, a device
+ * error) completes with its error status; the other jobs are unaffected.
+ * Buffers of a job (inputs, freq_hz, image) must stay valid until it is
+ * reported done.  A job whose footprint alone exceeds the budget fails with
+ * WSG_ENOMEM.
+ */
+typedef struct wsg_server wsg_server;
+
+typedef struct {
+    wsg_status status;       /* result of the job                                            */
+    double t_submit, t_start, t_end;   /* seconds on a monotonic clock                       */
+    uint64_t footprint;      /* bytes accounted for admission                                */
+    wsg_stats stats;         /* stats of the (first) image                                   */
+} wsg_job_info;
+
+wsg_status wsg_server_create(int device, int32_t n_slots, uint64_t hbm_budget, wsg_server **out);
+/* Wait for every job, then stop the workers and free their workspace. */
+void wsg_server_destroy(wsg_server *srv);
+wsg_status wsg_server_submit(wsg_server *srv, const wsg_params *p, const wsg_vis *v, double *image,
+                             int32_t image_mem, uint64_t *ticket);
+/* *done = 1 and *info filled once the job has finished (either way). */
+wsg_status wsg_server_poll(wsg_server *srv, uint64_t ticket, int32_t *done, wsg_job_info *info);
+wsg_status wsg_server_wait(wsg_server *srv, uint64_t ticket, wsg_job_info *info);
+/* Current and peak device bytes held by the slots (their workspaces). */
+wsg_status wsg_server_memory(wsg_server *srv, uint64_t *held, uint64_t *peak);
+/* Release the workspace of every idle slot. */
+wsg_status wsg_trim(wsg_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -276,19 +276,23 @@ int oracle_pixels(int64_t n_rows, int n_chan, const double *uvw, const double *c
                 double wv_re = wt * vis[2 * rc + 0];
                 double wv_im = wt * vis[2 * rc + 1];
                 for (int ip = 0; ip < n_pix; ++ip) {
-                    int64_t pp = pix_p[ip] - n / 2, qq = pix_q[ip] - n / 2;
+                    /* (i0+a-N/2)(p-N/2) mod N, stepped exactly in a */
+                    int64_t pp = ((int64_t)(pix_p[ip] - n / 2) % n + n) % n;
+                    int64_t qq = ((int64_t)(pix_q[ip] - n / 2) % n + n) % n;
                     double kx_re = 0.0, kx_im = 0.0, ky_re = 0.0, ky_im = 0.0;
+                    int64_t t = (((i0 - h - n / 2) * pp) % n + n) % n;
                     for (int a = -h; a <= h; ++a) {
-                        int64_t t = ((i0 + a - n / 2) * pp) % n;
-                        if (t < 0) t += n;
                         kx_re += gx[a + h] * ct[t];
                         kx_im += gx[a + h] * st[t];
+                        t += pp;
+                        if (t >= n) t -= n;
                     }
+                    t = (((j0 - h - n / 2) * qq) % n + n) % n;
                     for (int b = -h; b <= h; ++b) {
-                        int64_t t = ((j0 + b - n / 2) * qq) % n;
-                        if (t < 0) t += n;
                         ky_re += gy[b + h] * ct[t];
                         ky_im += gy[b + h] * st[t];
+                        t += qq;
+                        if (t >= n) t -= n;
                     }
                     const double *e = wk + 2 * ((size_t)ip * n_w + k);
                     double k_re = kx_re * ky_re - kx_im * ky_im;

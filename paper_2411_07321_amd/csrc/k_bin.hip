@@ -7,14 +7,26 @@
 // in every tile it touches (at most four); each tile then owns its cells and
 // writes them once, without global atomics.
 //
-// Pass structure (one thread per (row, channel) element, grid-stride loops
-// whose stride is a multiple of n_chan so that each thread stays on one
-// channel and can keep per-image partial sums in registers):
-//   k_prep     validity of every element, per-image w range and counts
+// Pass structure:
+//   k_prep     validity of every element, per-image w range and counts (one
+//              thread per (row, channel) element, grid-stride loops whose
+//              stride is a multiple of n_chan so a thread stays on one channel)
 //   k_finalize plane geometry per image (given range or the data's)
 //   k_count    per-bin counts, n_used and sum of weights
 //   scan       bin offsets
 //   k_scatter  compact records into their bins
+//
+// k_count and k_scatter follow tracks: rows are viewed as [time][P] with P
+// the row period (baselines per time slice), and a thread walks one
+// (baseline, channel) through L consecutive time slices.  A track moves
+// slowly across the mesh, so consecutive elements of a thread mostly fall in
+// the same bins: a "run" is a maximal stretch of consecutive elements whose
+// footprints all touch one bin, and each run costs one global atomic instead
+// of one per element (the scatter looks ahead to size the run before it
+// reserves its slots).  This matters because the uv coverage is extremely
+// uneven: the short baselines of a dense core all land in the few central
+// tiles, and per-element atomics there serialise.  Records of one run stay
+// contiguous inside their bin.
 #include "wsg_internal.h"
 
 #include <algorithm>
@@ -231,6 +243,56 @@ __device__ __forceinline__ int64_t bin_base(const JobGeom &g, int img, int kl) {
     return ((int64_t)img * g.n_pl + kl) * (int64_t)g.NT * g.NT;
 }
 
+// Bins touched by one element's footprint (0, 1, 2 or 4), in a fixed order.
+struct Keys {
+    int n;
+    uint32_t k[4];
+};
+
+__device__ __forceinline__ bool has_key(const Keys &ks, uint32_t key) {
+    bool f = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f |= (i < ks.n) && ks.k[i] == key;
+    return f;
+}
+
+// keys of element (row r, channel c); false if the element is not gridded
+__device__ __forceinline__ bool element_keys(const JobGeom &g, const ImgState &s, const double *uvw,
+                                             const uint8_t *mask, int64_t r, int c, int img,
+                                             Placed &pl, Keys &ks) {
+    ks.n = 0;
+    int64_t e = r * g.n_chan + c;
+    if (!mask[e]) return false;
+    if (!place(g, s, uvw, r, c, pl)) return false;
+    int kl = pl.k - g.plane_lo;
+    if (kl < 0 || kl >= g.n_pl) return false;
+    int64_t base = bin_base(g, img, kl);
+    int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
+    int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) ks.k[ks.n++] = (uint32_t)(base + (int64_t)ty * g.NT + tx);
+    return true;
+}
+
+// (channel, baseline, time block) of a track thread
+struct Track {
+    int c;
+    int64_t b, t0, t1;
+    bool ok;
+};
+
+__device__ __forceinline__ Track track_of(const JobGeom &g, int64_t idx) {
+    Track tr;
+    tr.c = (int)(idx % g.n_chan);
+    int64_t rest = idx / g.n_chan;
+    tr.b = rest % g.P;
+    int64_t tb = rest / g.P;
+    tr.t0 = tb * g.L;
+    tr.t1 = min(g.n_t, tr.t0 + g.L);
+    tr.ok = tb < g.n_tb;
+    return tr;
+}
+
 template <bool F64W>
 __global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
                                                     const void *__restrict__ wts,
@@ -244,28 +306,53 @@ __global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__r
         s_sumw[i] = 0.0;
     }
     __syncthreads();
-    const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = (int)(e0 % g.n_chan);
-    const int img = (n_img > 1) ? c : 0;
-    const ImgState s = st[img];
+    const Track tr = track_of(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const int img = (n_img > 1) ? tr.c : 0;
     unsigned long long nu = 0;
     double sw = 0.0;
-    for (int64_t e = e0; e < n_elem; e += stride) {
-        if (!mask[e]) continue;
-        int64_t r = e / g.n_chan;
-        Placed pl;
-        if (!place(g, s, uvw, r, c, pl)) continue;
-        ++nu;
-        sw += wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
-        int kl = pl.k - g.plane_lo;
-        if (kl < 0 || kl >= g.n_pl) continue;
-        int64_t base = bin_base(g, img, kl);
-        int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
-        int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&counts[base + (int64_t)ty * g.NT + tx], 1u);
+    if (tr.ok) {
+        const ImgState s = st[img];
+        uint32_t okey[4] = {0, 0, 0, 0};
+        uint32_t ocnt[4] = {0, 0, 0, 0};
+        for (int64_t t = tr.t0; t < tr.t1; ++t) {
+            int64_t r = t * g.P + tr.b;
+            if (r >= g.n_rows) break;
+            Placed pl;
+            Keys ks;
+            int64_t e = r * g.n_chan + tr.c;
+            if (mask[e] && place(g, s, uvw, r, tr.c, pl)) {
+                ++nu;
+                sw += wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
+            }
+            element_keys(g, s, uvw, mask, r, tr.c, img, pl, ks);
+            // close runs whose bin this element does not touch
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ocnt[j] && !has_key(ks, okey[j])) {
+                    atomicAdd(&counts[okey[j]], ocnt[j]);
+                    ocnt[j] = 0;
+                }
+            // extend or open runs
+            for (int i = 0; i < ks.n; ++i) {
+                bool done = false;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (!done && ocnt[j] && okey[j] == ks.k[i]) {
+                        ++ocnt[j];
+                        done = true;
+                    }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (!done && ocnt[j] == 0) {
+                        okey[j] = ks.k[i];
+                        ocnt[j] = 1;
+                        done = true;
+                    }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ocnt[j]) atomicAdd(&counts[okey[j]], ocnt[j]);
     }
     if (n_img == 1) {
         for (int off = 32; off > 0; off >>= 1) {
@@ -276,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__r
             atomicAdd(&s_used[0], nu);
             atomicAdd(&s_sumw[0], sw);
         }
-    } else {
+    } else if (tr.ok) {
         atomicAdd(&s_used[img], nu);
         atomicAdd(&s_sumw[img], sw);
     }
@@ -290,60 +377,93 @@ __global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__r
 }
 
 template <typename VT>
+__device__ __forceinline__ void write_record(void *records, uint32_t slot, const JobGeom &g,
+                                             const Placed &pl, uint32_t key, double vr, double vi,
+                                             double wt) {
+    uint32_t t = key % (uint32_t)(g.NT * g.NT);
+    int ty = (int)(t / g.NT), tx = (int)(t % g.NT);
+    double fx = pl.x - (double)pl.i0;
+    double fy = pl.y - (double)pl.j0;
+    if constexpr (sizeof(VT) == 8) {
+        RecF64 rec;
+        rec.fx = fx;
+        rec.fy = fy;
+        rec.re = wt * vr;
+        rec.im = wt * vi;
+        rec.li = pl.i0 - tx * g.T;
+        rec.lj = pl.j0 - ty * g.T;
+        ((RecF64 *)records)[slot] = rec;
+    } else {
+        uint32_t qx = (uint32_t)fmin((fx + 0.5) * 16777216.0 + 0.5, 16777215.0);
+        uint32_t qy = (uint32_t)fmin((fy + 0.5) * 16777216.0 + 0.5, 16777215.0);
+        RecF32 rec;
+        rec.px = ((uint32_t)(pl.i0 - tx * g.T + g.h) << kFracBits) | qx;
+        rec.py = ((uint32_t)(pl.j0 - ty * g.T + g.h) << kFracBits) | qy;
+        rec.re = (float)wt * (float)vr;
+        rec.im = (float)wt * (float)vi;
+        ((RecF32 *)records)[slot] = rec;
+    }
+}
+
+template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
                                                       const void *__restrict__ vis,
                                                       const void *__restrict__ wts,
                                                       const uint8_t *__restrict__ mask,
                                                       const ImgState *st, uint32_t *cursor,
                                                       void *__restrict__ records) {
-    const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = (int)(e0 % g.n_chan);
-    const int img = (g.n_img > 1) ? c : 0;
+    const Track tr = track_of(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (!tr.ok) return;
+    const int img = (g.n_img > 1) ? tr.c : 0;
     const ImgState s = st[img];
-    for (int64_t e = e0; e < n_elem; e += stride) {
-        if (!mask[e]) continue;
-        int64_t r = e / g.n_chan;
+    uint32_t okey[4] = {0, 0, 0, 0};
+    uint32_t onext[4] = {0, 0, 0, 0};
+    uint32_t orem[4] = {0, 0, 0, 0};
+    for (int64_t t = tr.t0; t < tr.t1; ++t) {
+        int64_t r = t * g.P + tr.b;
+        if (r >= g.n_rows) break;
         Placed pl;
-        if (!place(g, s, uvw, r, c, pl)) continue;
-        int kl = pl.k - g.plane_lo;
-        if (kl < 0 || kl >= g.n_pl) continue;
+        Keys ks;
+        if (!element_keys(g, s, uvw, mask, r, tr.c, img, pl, ks)) continue;
+        int64_t e = r * g.n_chan + tr.c;
         double vr, vi, wt;
         ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
-        int64_t base = bin_base(g, img, kl);
-        int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
-        int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
-        double fx = pl.x - (double)pl.i0;
-        double fy = pl.y - (double)pl.j0;
-        if constexpr (sizeof(VT) == 8) {
-            RecF64 rec;
-            rec.fx = fx;
-            rec.fy = fy;
-            rec.re = wt * vr;
-            rec.im = wt * vi;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    uint32_t slot = atomicAdd(&cursor[base + (int64_t)ty * g.NT + tx], 1u);
-                    rec.li = pl.i0 - tx * g.T;
-                    rec.lj = pl.j0 - ty * g.T;
-                    ((RecF64 *)records)[slot] = rec;
+        for (int i = 0; i < ks.n; ++i) {
+            const uint32_t key = ks.k[i];
+            uint32_t slot = 0;
+            bool have = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (!have && orem[j] && okey[j] == key) {
+                    slot = onext[j]++;
+                    --orem[j];
+                    have = true;
                 }
-        } else {
-            uint32_t qx = (uint32_t)fmin((fx + 0.5) * 16777216.0 + 0.5, 16777215.0);
-            uint32_t qy = (uint32_t)fmin((fy + 0.5) * 16777216.0 + 0.5, 16777215.0);
-            float wr = (float)wt * (float)vr;
-            float wi = (float)wt * (float)vi;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    uint32_t slot = atomicAdd(&cursor[base + (int64_t)ty * g.NT + tx], 1u);
-                    RecF32 rec;
-                    rec.px = ((uint32_t)(pl.i0 - tx * g.T + g.h) << kFracBits) | qx;
-                    rec.py = ((uint32_t)(pl.j0 - ty * g.T + g.h) << kFracBits) | qy;
-                    rec.re = wr;
-                    rec.im = wi;
-                    ((RecF32 *)records)[slot] = rec;
+            if (!have) {
+                // a new run: its length is the number of consecutive elements of
+                // this track, from this one on, whose footprint touches `key`
+                uint32_t len = 1;
+                for (int64_t t2 = t + 1; t2 < tr.t1; ++t2) {
+                    int64_t r2 = t2 * g.P + tr.b;
+                    if (r2 >= g.n_rows) break;
+                    Placed pl2;
+                    Keys ks2;
+                    element_keys(g, s, uvw, mask, r2, tr.c, img, pl2, ks2);
+                    if (!has_key(ks2, key)) break;
+                    ++len;
                 }
+                uint32_t base = atomicAdd(&cursor[key], len);
+                slot = base;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (!have && orem[j] == 0) {
+                        okey[j] = key;
+                        onext[j] = base + 1;
+                        orem[j] = len - 1;
+                        have = true;
+                    }
+            }
+            write_record<VT>(records, slot, g, pl, key, vr, vi, wt);
         }
     }
 }
@@ -423,11 +543,13 @@ void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s) {
     k_finalize<<<(g.n_img + 63) / 64, 64, 0, s>>>(g, st);
 }
 
+int64_t track_threads(const JobGeom &g) { return (int64_t)g.n_chan * g.P * g.n_tb; }
+
 void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
                   const uint8_t *mask, ImgState *st, uint32_t *counts, hipStream_t s) {
     int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
     if (n_elem == 0) return;
-    int blocks = blocks_for(n_elem, g.n_chan);
+    unsigned blocks = (unsigned)((track_threads(g) + kThreads - 1) / kThreads);
     if (f64)
         k_count<true><<<blocks, kThreads, 0, s>>>(g, uvw, wts, mask, st, counts);
     else
@@ -439,7 +561,7 @@ void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const 
                     void *records, hipStream_t s) {
     int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
     if (n_elem == 0) return;
-    int blocks = blocks_for(n_elem, g.n_chan);
+    unsigned blocks = (unsigned)((track_threads(g) + kThreads - 1) / kThreads);
     if (f64)
         k_scatter<double><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor, records);
     else

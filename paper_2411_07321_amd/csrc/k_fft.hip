@@ -22,6 +22,8 @@
 // the strip of the image is written once, with the post factors applied.
 #include "wsg_internal.h"
 
+#include <type_traits>
+
 namespace wsg {
 
 namespace {
@@ -42,6 +44,18 @@ struct Shape {
     static constexpr int NTR = NTR0 > N ? N : NTR0;  // transforms per workgroup
     static constexpr int THREADS = NTR * P;
     static constexpr int NPAD = N + N / 16;           // LDS row length with padding
+};
+
+// pass 2: fewer transforms per workgroup where the FP64 plane sums would not fit in
+// registers next to the points (at most 512 threads for complex64, 256 for complex128)
+template <typename T, int N>
+struct Shape2 {
+    static constexpr int B = BlockRows<T>::value;
+    static constexpr int P = N / E;
+    static constexpr int cap = (sizeof(T) == 4 ? 512 : 256) / P;
+    static constexpr int NTR = Shape<T, N>::NTR < cap ? Shape<T, N>::NTR : (cap > 0 ? cap : 1);
+    static constexpr int THREADS = NTR * P;
+    static constexpr int NPAD = N + N / 16;
 };
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
@@ -205,7 +219,7 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
 // thread -> (t_lo, r, t_hi): reads of 16 consecutive lanes form one 128-byte run
 template <typename T, int N>
 struct P2Index {
-    using SH = Shape<T, N>;
+    using SH = Shape2<T, N>;
     int t, r;
     __device__ __forceinline__ P2Index(int tid) {
         constexpr int TB = SH::B < SH::P ? SH::B : SH::P;
@@ -228,10 +242,10 @@ __device__ __forceinline__ void load_blocked(C2<T> *v, const C2<T> *__restrict__
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_store(const C2<T> *__restrict__ in,
-                                                                       C2<T> *__restrict__ out,
-                                                                       const C2<T> *__restrict__ tw) {
-    using SH = Shape<T, N>;
+__global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C2<T> *__restrict__ in,
+                                                                        C2<T> *__restrict__ out,
+                                                                        const C2<T> *__restrict__ tw) {
+    using SH = Shape2<T, N>;
     constexpr int P = SH::P, NTR = SH::NTR;
     __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
     P2Index<T, N> ix(threadIdx.x);
@@ -256,11 +270,16 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_store(const C2
 }
 
 // phase screen of one pixel for plane w: e^{2 pi i w (n-1)}
-template <bool PH32>
+//   MODE 0 (FP64 mesh):      argument and sin/cos in FP64
+//   MODE 1 (FP32 mesh):      argument w (n-1) in turns formed in FP64 and reduced
+//                            exactly to [-1/2, 1/2]; sin/cos of the reduced angle in
+//                            FP32 (error ~6e-8, below the FP32 mesh rounding)
+//   MODE 2 (FP32 phase):     argument and sin/cos in FP32 (the precision study)
+template <int MODE>
 struct Phase;
 
 template <>
-struct Phase<false> {
+struct Phase<0> {
     using R = double;
     static __device__ __forceinline__ R nm1(double l, double m, int /*naive*/, bool &inside) {
         double eta = l * l + m * m;
@@ -274,7 +293,34 @@ struct Phase<false> {
 };
 
 template <>
-struct Phase<true> {
+struct Phase<1> {
+    using R = double;
+    // -eta/(1 + sqrt(1 - eta)) to ~1e-14 relative: FP32 seeds for the square root
+    // and the reciprocal, each refined by one Newton step in FP64
+    static __device__ __forceinline__ R nm1(double l, double m, int /*naive*/, bool &inside) {
+        double eta = l * l + m * m;
+        inside = eta < 1.0;
+        if (!inside) return 0.0;
+        double x = 1.0 - eta;
+        float yf = sqrtf((float)x);
+        float rf = 1.0f / yf;
+        double y = (double)yf;
+        y = y + (x - y * y) * (0.5 * (double)rf);
+        double d = 1.0 + y;
+        double rd = (double)(1.0f / (float)d);
+        double q = -eta * rd;
+        q = q + (-eta - q * d) * rd;
+        return q;
+    }
+    static __device__ __forceinline__ void screen(R nm1v, double w, float &c, float &s) {
+        double t = w * nm1v;             // turns
+        double r = t - rint(t);          // exact: |r| <= 1/2
+        sincospif(2.0f * (float)r, &s, &c);
+    }
+};
+
+template <>
+struct Phase<2> {
     using R = float;
     static __device__ __forceinline__ R nm1(double l, double m, int naive, bool &inside) {
         float lf = (float)l, mf = (float)m;
@@ -284,21 +330,34 @@ struct Phase<true> {
         if (naive) return sqrtf(1.0f - eta) - 1.0f;
         return -eta / (1.0f + sqrtf(1.0f - eta));
     }
-    static __device__ __forceinline__ void screen(R nm1v, double w, double &c, double &s) {
-        float sf, cf;
-        sincospif(2.0f * ((float)w * nm1v), &sf, &cf);
-        c = cf;
-        s = sf;
+    static __device__ __forceinline__ void screen(R nm1v, double w, float &c, float &s) {
+        sincospif(2.0f * ((float)w * nm1v), &s, &c);
     }
 };
 
+template <typename T, bool PH32>
+struct PhaseMode {
+    static constexpr int value = PH32 ? 2 : (sizeof(T) == 8 ? 0 : 1);
+};
+
+// acc += Re(z * (c + i s)), in the arithmetic of the screen
+template <typename T>
+__device__ __forceinline__ void acc_re(double &acc, C2<T> z, double c, double s) {
+    acc += (double)z.x * c - (double)z.y * s;
+}
+template <typename T>
+__device__ __forceinline__ void acc_re(double &acc, C2<T> z, float c, float s) {
+    acc += (double)(z.x * c - z.y * s);
+}
+
 template <typename T, int N, bool PH32>
-__global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2<T> *__restrict__ stack,
-                                                                       const C2<T> *__restrict__ tw,
-                                                                       WcorrArgs a,
-                                                                       double *__restrict__ image) {
-    using SH = Shape<T, N>;
-    using PR = typename Phase<PH32>::R;
+__global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C2<T> *__restrict__ stack,
+                                                                        const C2<T> *__restrict__ tw,
+                                                                        WcorrArgs a,
+                                                                        double *__restrict__ image) {
+    using SH = Shape2<T, N>;
+    constexpr int PM = PhaseMode<T, PH32>::value;
+    using PR = typename Phase<PM>::R;
     constexpr int P = SH::P, NTR = SH::NTR;
     __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
     P2Index<T, N> ix(threadIdx.x);
@@ -306,14 +365,6 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2
     const int q = blockIdx.x * NTR + ix.r;            // image row handled by this thread
     const ImgState &st = a.st[img];
     const double m = (double)(q - N / 2) * a.cell;
-    PR nm1[E];
-    bool inside[E];
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-        int p = ix.t + s * P;
-        double l = (double)(p - N / 2) * a.cell;
-        nm1[s] = Phase<PH32>::nm1(l, m, a.naive_nm1, inside[s]);
-    }
     double acc[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) acc[s] = 0.0;
@@ -327,11 +378,16 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2
         C2<T> v[E];
         load_blocked<T, N>(v, Y, ix.t, q);
         fft_line<T, N>(v, lre, lim, ix.t, tw);
+        // n - 1 is recomputed per plane: holding it for all E pixels would not fit
+        // in registers next to the points and the FP64 sums
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            double c, sn;
-            Phase<PH32>::screen(nm1[s], wk, c, sn);
-            acc[s] += (double)v[s].x * c - (double)v[s].y * sn;
+            bool in;
+            const double l = (double)(ix.t + s * P - N / 2) * a.cell;
+            PR nm1 = Phase<PM>::nm1(l, m, a.naive_nm1, in);
+            typename std::conditional<PM == 0, double, float>::type c, sn;
+            Phase<PM>::screen(nm1, wk, c, sn);
+            acc_re(acc[s], v[s], c, sn);
         }
     }
     // post factors and the output sign (-1)^(p+q); stage through LDS for
@@ -342,7 +398,9 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         int p = ix.t + s * P;
-        double d = inside[s] ? acc[s] * inv_row * (a.inv_c ? a.inv_c[p] : 1.0) : 0.0;
+        const double l = (double)(p - N / 2) * a.cell;
+        const bool inside = l * l + m * m < 1.0;
+        double d = inside ? acc[s] * inv_row * (a.inv_c ? a.inv_c[p] : 1.0) : 0.0;
         if ((p + q) & 1) d = -d;
         stg[ix.r * N + p] = d;
     }
@@ -355,7 +413,8 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass2_wcorr(const C2
 template <typename T, bool PH32>
 __global__ __launch_bounds__(256) void k_wcorrect(const C2<T> *__restrict__ F, WcorrArgs a,
                                                   double *__restrict__ image) {
-    using PR = typename Phase<PH32>::R;
+    constexpr int PM = PhaseMode<T, PH32>::value;
+    using PR = typename Phase<PM>::R;
     const int N = a.N;
     const size_t n2 = (size_t)N * N;
     size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -363,16 +422,16 @@ __global__ __launch_bounds__(256) void k_wcorrect(const C2<T> *__restrict__ F, W
     const int q = (int)(pix / N), p = (int)(pix % N);
     const ImgState &st = a.st[0];
     bool inside;
-    PR nm1 = Phase<PH32>::nm1((double)(p - N / 2) * a.cell, (double)(q - N / 2) * a.cell,
-                              a.naive_nm1, inside);
+    PR nm1 = Phase<PM>::nm1((double)(p - N / 2) * a.cell, (double)(q - N / 2) * a.cell,
+                            a.naive_nm1, inside);
     double acc = 0.0;
     for (int kl = 0; kl < a.n_pl; ++kl) {
         const int k = a.plane_lo + kl;
         const double wk = (st.dw == 0.0) ? st.w_min : st.w_min + ((double)k + 0.5) * st.dw;
         C2<T> z = F[(size_t)kl * n2 + pix];
-        double c, s;
-        Phase<PH32>::screen(nm1, wk, c, s);
-        acc += (double)z.x * c - (double)z.y * s;
+        typename std::conditional<PM == 0, double, float>::type c, s;
+        Phase<PM>::screen(nm1, wk, c, s);
+        acc_re(acc, z, c, s);
     }
     double d = inside ? acc * st.inv_norm * (a.inv_c ? a.inv_c[p] * a.inv_c[q] : 1.0) : 0.0;
     image[pix] = d;
@@ -402,14 +461,14 @@ void pass1_n(void *planes, int64_t n_planes, const void *tw, hipStream_t s) {
 
 template <typename T, int N>
 void pass2_store_n(const void *in, void *out, int64_t n_planes, const void *tw, hipStream_t s) {
-    using SH = Shape<T, N>;
+    using SH = Shape2<T, N>;
     dim3 grid(N / SH::NTR, (unsigned)n_planes);
     k_pass2_store<T, N><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)in, (C2<T> *)out, (const C2<T> *)tw);
 }
 
 template <typename T, int N>
 void pass2_wcorr_n(const WcorrArgs &a, const void *stack, const void *tw, double *image, hipStream_t s) {
-    using SH = Shape<T, N>;
+    using SH = Shape2<T, N>;
     dim3 grid(N / SH::NTR, (unsigned)a.n_img);
     if (a.phase32)
         k_pass2_wcorr<T, N, true><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)stack, (const C2<T> *)tw, a, image);

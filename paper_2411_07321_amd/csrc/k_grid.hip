@@ -71,7 +71,15 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 }
 
 // LDS tile: TP = T+1 columns per row, separate real / imaginary arrays.
-template <typename T, int TT>
+//
+// Each lane takes a contiguous stretch of the work item's records.  The
+// binning pass keeps the records of one track (one baseline and channel over
+// consecutive times) contiguous inside a bin, and a track moves slowly, so
+// consecutive records of a lane usually have the same nearest cell.  With
+// ACC (complex64 mesh, S <= 7) the lane sums the S x S footprint values of
+// such records in registers and adds them to the LDS tile only when the cell
+// changes; otherwise every record is added to the tile directly.
+template <typename T, int TT, int SS, bool ACC>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,
                                                         const uint32_t *__restrict__ item_off,
@@ -80,6 +88,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                                                         const typename RecTraits<T>::Rec *__restrict__ rec,
                                                         C2<T> *__restrict__ grid, int transposed) {
     constexpr int TP = TT + 1;
+    constexpr int H = (SS - 1) / 2;
     __shared__ T s_re[TT * TP];
     __shared__ T s_im[TT * TP];
     const uint32_t item = blockIdx.x;
@@ -96,34 +105,84 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     }
     __syncthreads();
 
-    const int h = g.h;
-    const int S = g.S;
     const T inv2s2 = (T)g.inv2s2;
-    for (uint32_t ri = r0 + threadIdx.x; ri < r1; ri += blockDim.x) {
+    const uint32_t n = r1 - r0;
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t q0 = r0 + min(n, threadIdx.x * per);
+    const uint32_t q1 = r0 + min(n, (threadIdx.x + 1) * per);
+
+    T ar[ACC ? SS : 1][ACC ? SS : 1], ai[ACC ? SS : 1][ACC ? SS : 1];
+    int cli = INT32_MIN, clj = 0;
+    auto flush = [&](int li, int lj) {
+        if constexpr (ACC) {
+#pragma unroll
+            for (int bb = 0; bb < SS; ++bb) {
+                int j = lj + bb - H;
+#pragma unroll
+                for (int a = 0; a < SS; ++a) {
+                    int i = li + a - H;
+                    if (j >= 0 && j < TT && i >= 0 && i < TT) {
+                        atomicAdd(&s_re[j * TP + i], ar[bb][a]);
+                        atomicAdd(&s_im[j * TP + i], ai[bb][a]);
+                    }
+                    ar[bb][a] = T(0);
+                    ai[bb][a] = T(0);
+                }
+            }
+        }
+    };
+    if constexpr (ACC) {
+#pragma unroll
+        for (int bb = 0; bb < SS; ++bb)
+#pragma unroll
+            for (int a = 0; a < SS; ++a) {
+                ar[bb][a] = T(0);
+                ai[bb][a] = T(0);
+            }
+    }
+    for (uint32_t ri = q0; ri < q1; ++ri) {
         int li, lj;
         T fx, fy, re, im;
-        RecTraits<T>::decode(rec[ri], h, li, lj, fx, fy, re, im);
-        T gx[kMaxSupport], gy[kMaxSupport];
+        RecTraits<T>::decode(rec[ri], H, li, lj, fx, fy, re, im);
+        T gx[SS], gy[SS];
 #pragma unroll
-        for (int a = 0; a < kMaxSupport; ++a) {
-            if (a < S) {
-                gx[a] = RecTraits<T>::gauss((T)(a - h) - fx, inv2s2);
-                gy[a] = RecTraits<T>::gauss((T)(a - h) - fy, inv2s2);
+        for (int a = 0; a < SS; ++a) {
+            gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
+            gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
+        }
+        if constexpr (ACC) {
+            if (li != cli || lj != clj) {
+                if (cli != INT32_MIN) flush(cli, clj);
+                cli = li;
+                clj = lj;
+            }
+#pragma unroll
+            for (int bb = 0; bb < SS; ++bb) {
+                T wr = re * gy[bb], wi = im * gy[bb];
+#pragma unroll
+                for (int a = 0; a < SS; ++a) {
+                    ar[bb][a] += wr * gx[a];
+                    ai[bb][a] += wi * gx[a];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int bb = 0; bb < SS; ++bb) {
+                int j = lj + bb - H;
+                if (j < 0 || j >= TT) continue;
+                T wr = re * gy[bb], wi = im * gy[bb];
+#pragma unroll
+                for (int a = 0; a < SS; ++a) {
+                    int i = li + a - H;
+                    if (i < 0 || i >= TT) continue;
+                    atomicAdd(&s_re[j * TP + i], wr * gx[a]);
+                    atomicAdd(&s_im[j * TP + i], wi * gx[a]);
+                }
             }
         }
-#pragma unroll
-        for (int bb = 0; bb < kMaxSupport; ++bb) {
-            int j = lj + bb - h;
-            if (bb >= S || j < 0 || j >= TT) continue;
-            T wr = re * gy[bb], wi = im * gy[bb];
-#pragma unroll
-            for (int a = 0; a < kMaxSupport; ++a) {
-                int i = li + a - h;
-                if (a >= S || i < 0 || i >= TT) continue;
-                atomicAdd(&s_re[j * TP + i], wr * gx[a]);
-                atomicAdd(&s_im[j * TP + i], wi * gx[a]);
-            }
-        }
+    }
+    if constexpr (ACC) {
+        if (cli != INT32_MIN) flush(cli, clj);
     }
     __syncthreads();
 
@@ -163,6 +222,27 @@ __global__ __launch_bounds__(kGridThreads) void k_zero_split(JobGeom g, const ui
     }
 }
 
+template <typename T, int TT, int SS>
+void launch_tile(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
+                 const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
+                 uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr) {
+    constexpr bool ACC = (sizeof(T) == 4) && SS <= 7;
+    k_grid<T, TT, SS, ACC><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk,
+                                                         r, gp, tr);
+}
+
+template <typename T, int TT>
+void launch_support(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
+                    const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
+                    uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr) {
+    switch (g.S) {
+#define WSG_S(ss) case ss: launch_tile<T, TT, ss>(g, grid, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    WSG_S(1) WSG_S(3) WSG_S(5) WSG_S(7) WSG_S(9) WSG_S(11) WSG_S(13) WSG_S(15)
+#undef WSG_S
+    default: break;
+    }
+}
+
 template <typename T>
 void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
                    const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
@@ -172,13 +252,14 @@ void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *off
     const Rec *r = (const Rec *)records;
     C2<T> *gp = (C2<T> *)grid;
     int tr = transposed ? 1 : 0;
+    dim3 gd(n_items);
     switch (g.T) {
-    case 16: k_grid<T, 16><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
-    case 32: k_grid<T, 32><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
-    case 64: k_grid<T, 64><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 16: launch_support<T, 16>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 32: launch_support<T, 32>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 64: launch_support<T, 64>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
     case 128:
         if constexpr (sizeof(T) == 4)
-            k_grid<T, 128><<<n_items, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk, r, gp, tr);
+            launch_support<T, 128>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr);
         break;
     default: break;
     }

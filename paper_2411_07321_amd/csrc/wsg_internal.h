@@ -80,6 +80,10 @@ struct JobGeom {
     int32_t range_given;
     double w_min_given, w_max_given;
     const double *chan_scale;  // device [n_chan]: f/c or 1
+    // track traversal of the binning passes: rows are viewed as [n_t][P]
+    // (P = row period, the baselines per time slice); a thread follows one
+    // (baseline, channel) track through L consecutive time slices
+    int64_t P, n_t, L, n_tb;
 };
 
 // ----------------------------------------------------------------------------

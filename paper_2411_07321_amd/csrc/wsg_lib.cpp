@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -24,7 +25,7 @@ using namespace wsg;
 
 namespace {
 
-constexpr uint32_t kChunk = 4096;        // records per gridding work item
+constexpr uint32_t kChunk = 32768;       // records per gridding work item
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -59,6 +60,7 @@ struct wsg_ctx {
     // stage timing: events recorded at the stage boundaries of wsg_image
     int timing = 0;
     hipEvent_t tev[8] = {};
+    hipStream_t last_stream = nullptr;   // stream of the previous call (arena users)
 };
 
 namespace {
@@ -228,19 +230,22 @@ size_t dyn_bytes(const Plan &pl, size_t records, size_t items) {
     return align_up(records * rec_size(pl.f64)) + align_up(items * 4);
 }
 
-wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, size_t other_in_use) {
+// Grow an arena (never shrinks here).  The old block is released and the new one
+// allocated in stream order on `s`, so other contexts' work is not waited for;
+// work of this context on other streams is finished first.
+wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, size_t other_in_use, hipStream_t s) {
     if (bytes <= a.size) return WSG_OK;
     if (ctx->budget && bytes + other_in_use > ctx->budget)
         return fail(ctx, WSG_ENOMEM, "workspace of " + std::to_string(bytes + other_in_use) +
                                          " bytes exceeds the context budget");
+    if (ctx->last_stream && ctx->last_stream != s) WSG_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
     if (a.ptr) {
-        WSG_HIP(ctx, hipDeviceSynchronize());
-        WSG_HIP(ctx, hipFree(a.ptr));
+        WSG_HIP(ctx, hipFreeAsync(a.ptr, s));
         a.ptr = nullptr;
         a.size = 0;
     }
     size_t sz = align_up(bytes + bytes / 16);
-    WSG_HIP(ctx, hipMalloc(&a.ptr, sz));
+    WSG_HIP(ctx, hipMallocAsync(&a.ptr, sz, s));
     a.size = sz;
     return WSG_OK;
 }
@@ -373,7 +378,10 @@ void mark(wsg_ctx *ctx, int i, hipStream_t s) {
 }
 
 hipStream_t pick_stream(wsg_ctx *ctx, void *stream) {
-    return stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    if (ctx->last_stream && ctx->last_stream != s) (void)hipStreamSynchronize(ctx->last_stream);
+    ctx->last_stream = s;
+    return s;
 }
 
 // ---------------------------------------------------------------- the binned grid
@@ -403,7 +411,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     if (ctx->budget && pl.fixed_bytes + dyn_est > ctx->budget)
         return fail(ctx, WSG_ENOMEM, "job footprint " + std::to_string(pl.fixed_bytes + dyn_est) +
                                          " bytes exceeds the context budget");
-    wsg_status rc = ensure_arena(ctx, ctx->fixed, pl.fixed_bytes, ctx->dyn.size);
+    wsg_status rc = ensure_arena(ctx, ctx->fixed, pl.fixed_bytes, ctx->dyn.size, s);
     if (rc) return rc;
     char *fx = (char *)ctx->fixed.ptr;
     b.fx = fx;
@@ -447,6 +455,17 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     g.w_min_given = p->w_min;
     g.w_max_given = p->w_max;
     g.chan_scale = (const double *)(fx + pl.o_scale);
+    // track traversal: P = row period (1 without the hint), L time slices per thread,
+    // about 2^20 threads in all
+    g.P = (v->row_period > 1 && v->row_period <= pl.n_rows) ? v->row_period : 1;
+    g.n_t = pl.n_rows > 0 ? (pl.n_rows + g.P - 1) / g.P : 0;
+    {
+        int64_t lanes = g.P * (int64_t)v->n_chan;
+        int64_t want = (int64_t)1 << 20;
+        int64_t L = (g.n_t * lanes + want - 1) / want;
+        g.L = std::max<int64_t>(1, std::min<int64_t>(L, std::max<int64_t>(g.n_t, 1)));
+        g.n_tb = g.n_t > 0 ? (g.n_t + g.L - 1) / g.L : 0;
+    }
 
     b.st = (ImgState *)(fx + pl.o_state);
     b.counts = (uint32_t *)(fx + pl.o_counts);
@@ -502,7 +521,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     b.n_items = htot[1];
 
     size_t need = dyn_bytes(pl, b.n_records, b.n_items);
-    rc = ensure_arena(ctx, ctx->dyn, need, ctx->fixed.size);
+    rc = ensure_arena(ctx, ctx->dyn, need, ctx->fixed.size, s);
     if (rc) return rc;
     char *dy = (char *)ctx->dyn.ptr;
     b.records = dy;
@@ -610,9 +629,10 @@ void wsg_destroy(wsg_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    (void)hipDeviceSynchronize();
-    if (ctx->fixed.ptr) (void)hipFree(ctx->fixed.ptr);
-    if (ctx->dyn.ptr) (void)hipFree(ctx->dyn.ptr);
+    if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
+    if (ctx->fixed.ptr) (void)hipFreeAsync(ctx->fixed.ptr, ctx->stream);
+    if (ctx->dyn.ptr) (void)hipFreeAsync(ctx->dyn.ptr, ctx->stream);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &kv : ctx->twiddles) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->inv_c) (void)hipFree(kv.second.ptr);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
@@ -642,6 +662,19 @@ const char *wsg_last_error(const wsg_ctx *ctx) { return ctx ? ctx->last_error.c_
 wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes) {
     if (!ctx) return WSG_EINVAL;
     ctx->budget = bytes;
+    return WSG_OK;
+}
+
+wsg_status wsg_trim(wsg_ctx *ctx) {
+    if (!ctx) return WSG_EINVAL;
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->last_stream ? ctx->last_stream : ctx->stream;
+    for (Arena *a : {&ctx->fixed, &ctx->dyn}) {
+        if (a->ptr) WSG_HIP(ctx, hipFreeAsync(a->ptr, s));
+        a->ptr = nullptr;
+        a->size = 0;
+    }
+    WSG_HIP(ctx, hipStreamSynchronize(s));
     return WSG_OK;
 }
 
@@ -683,6 +716,10 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
     if (rc) return rc;
     if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
     if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
+    // test hook for failure isolation: jobs of mesh size WSG_FAIL_GRID_N fail on the
+    // host before any device work
+    if (const char *f = std::getenv("WSG_FAIL_GRID_N"))
+        if (std::atoi(f) == p->grid_n) return fail(ctx, WSG_EDEVICE, "failure injected by WSG_FAIL_GRID_N");
     hipStream_t s = pick_stream(ctx, stream);
     bool host_img = image_mem == WSG_MEM_HOST;
     mark(ctx, kMarkStart, s);
@@ -758,7 +795,7 @@ wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_
     bool f64 = f64_mode(p);
     size_t bytes = (size_t)n_planes * N * N * cplx_size(p);
     size_t need = (mem == WSG_MEM_HOST ? 2 : 1) * align_up(bytes);
-    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size);
+    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size, s);
     if (rc) return rc;
     char *fx = (char *)ctx->fixed.ptr;
     void *src = planes;
@@ -797,7 +834,7 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
     size_t pbytes = (size_t)n_planes * N * N * cplx_size(p);
     size_t ibytes = (size_t)N * N * 8;
     size_t need = align_up(sizeof(ImgState)) + (mem == WSG_MEM_HOST ? align_up(pbytes) + align_up(ibytes) : 0);
-    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size);
+    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size, s);
     if (rc) return rc;
     char *fx = (char *)ctx->fixed.ptr;
     ImgState *st = (ImgState *)fx;
@@ -846,7 +883,7 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
                         int32_t *best_tile) {
     wsg_status rc = common_checks(ctx, p, v);
     if (rc) return rc;
-    hipStream_t s = ctx->stream;
+    hipStream_t s = pick_stream(ctx, nullptr);
     const int cands[] = {16, 32, 64, 128};
     float best_ms = 1e30f;
     int best = default_tile(p);
@@ -889,3 +926,11 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
 }
 
 }  // extern "C"
+
+// device bytes held by a context (its arenas and cached tables), for the server
+uint64_t wsg_ctx_device_bytes(const wsg_ctx *ctx) {
+    uint64_t b = ctx->fixed.size + ctx->dyn.size;
+    for (auto &kv : ctx->twiddles) b += kv.second.size;
+    for (auto &kv : ctx->inv_c) b += kv.second.size;
+    return b;
+}

@@ -1,0 +1,151 @@
+"""Serving workload: a Poisson stream of independent imaging jobs through the
+continuous-batching server of libwsg (wsg_server_*).
+
+Jobs are drawn from a pool of pre-generated datasets held in pinned host
+memory (mesh 512^2 .. 4096^2, 8 .. 64 w-planes, 1e5 .. 5e7 complex64
+visibilities, random array layouts); each job's image comes back to pinned
+host memory.  Two schedules are compared on the same trace:
+  * batched:    n_slots concurrent jobs, admitted by device-memory footprint;
+  * sequential: one job at a time (a single slot), in arrival order.
+Latency is arrival -> image on the host.  Run `python -m
+paper_2411_07321_amd.serve --help` for the command-line driver.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from paper_2411_07321_amd import synth, wsg
+
+
+class PinnedJob:
+    """One pooled dataset in pinned host memory plus its imaging parameters."""
+
+    def __init__(self, ds: synth.Dataset):
+        import torch
+        self.ds = ds
+        self.uvw = torch.from_numpy(ds.uvw).pin_memory()
+        self.vis = torch.from_numpy(np.ascontiguousarray(ds.vis)).pin_memory()
+        self.wts = torch.from_numpy(np.ascontiguousarray(ds.weights)).pin_memory()
+        self.params = wsg.params_for(ds)
+        self.vb = wsg.make_vis(self.uvw, self.vis, self.wts, None, ds.freq_hz, ds.row_period)
+        self.n_vis = ds.n_vis
+        self.grid_n = ds.grid_n
+
+
+def make_pool(n_datasets: int, seed: int = synth.CONFIG_SEED0 + 4, device=None,
+              m_cap: float | None = None, log=None) -> list[PinnedJob]:
+    """Pre-generate the pool (job shapes from the seeded job_spec draw)."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_datasets):
+        spec = synth.job_spec(rng)
+        if m_cap is not None and spec["m_target"] > m_cap:
+            n_bl = spec["n_ant"] * (spec["n_ant"] - 1) // 2
+            spec["m_target"] = m_cap
+            spec["n_times"] = max(1, int(round(m_cap / n_bl)))
+        ds = synth.make_job(spec, seed * 1000 + i, device=device)
+        pool.append(PinnedJob(ds))
+        if log:
+            log(f"pool {i + 1}/{n_datasets}: N={ds.grid_n} Nw={ds.n_wplanes} M={ds.n_vis:,}")
+    return pool
+
+
+class OutputBuffers:
+    """Pinned host images, recycled by size."""
+
+    def __init__(self):
+        self.free = {}
+
+    def take(self, n: int):
+        import torch
+        lst = self.free.setdefault(n, [])
+        return lst.pop() if lst else torch.empty((1, n, n), dtype=torch.float64).pin_memory()
+
+    def give(self, n: int, buf):
+        self.free.setdefault(n, []).append(buf)
+
+
+def replay(pool, order, arrivals, n_slots: int, hbm_budget: int = 0, device: int = 0,
+           keep_images: set | None = None, log=None) -> dict:
+    """Submit job k (pool index order[k]) at time arrivals[k] (s after start) to a server
+    with n_slots slots; returns per-job latency and the throughput of the run."""
+    srv = wsg.Server(device, n_slots, hbm_budget)
+    outs = OutputBuffers()
+    pending = {}
+    lat, infos, kept = [], [], {}
+    t0 = time.perf_counter()
+    k = 0
+    n = len(order)
+    try:
+        while k < n or pending:
+            now = time.perf_counter() - t0
+            while k < n and arrivals[k] <= now:
+                job = pool[order[k]]
+                buf = outs.take(job.grid_n)
+                t = srv.submit(job.params, job.vb, buf)
+                pending[t] = (k, job, buf)
+                k += 1
+            done_any = False
+            for t in list(pending):
+                ok, info = srv.poll(t)
+                if ok:
+                    kk, job, buf = pending.pop(t)
+                    if info["status"] != wsg.OK:
+                        raise wsg.WsgError(info["status"], f"job {kk} failed")
+                    lat.append(info["t_end"] - info["t_submit"])
+                    infos.append(info)
+                    if keep_images is not None and kk in keep_images:
+                        kept[kk] = buf.numpy().copy()
+                    outs.give(job.grid_n, buf)
+                    done_any = True
+            if not done_any:
+                nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 0.0005
+                time.sleep(max(0.0, min(0.0005, nxt)))
+        wall = time.perf_counter() - t0
+        held, peak = srv.memory()
+    finally:
+        srv.close()
+    lat = np.array(lat)
+    t_first = min(i["t_submit"] for i in infos)
+    t_last = max(i["t_end"] for i in infos)
+    return {"jobs": n, "wall_s": wall, "jobs_per_s": n / (t_last - t_first),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "peak_device_bytes": peak,
+            "visibilities_per_s": sum(pool[i].n_vis for i in order) / (t_last - t_first),
+            "images": kept}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--pool", type=int, default=24)
+    ap.add_argument("--jobs", type=int, default=600)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=96.0)
+    ap.add_argument("--backlog", action="store_true", help="all jobs arrive at t=0")
+    ap.add_argument("--m-cap", type=float, default=None, help="cap visibilities per job")
+    args = ap.parse_args()
+    log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)
+    pool = make_pool(args.pool, device="cuda", m_cap=args.m_cap, log=log)
+    rng = np.random.default_rng(synth.CONFIG_SEED0 + 40)
+    order = rng.integers(0, len(pool), args.jobs)
+    arr = np.zeros(args.jobs) if args.backlog else synth.poisson_arrivals(args.jobs, args.rate, rng)
+    res = {}
+    for name, slots in (("batched", args.slots), ("sequential", 1)):
+        log(f"replaying {args.jobs} jobs, {name}")
+        r = replay(pool, order, arr, slots, int(args.budget_gb * 2**30), log=log)
+        r.pop("images")
+        res[name] = r
+        log(f"{name}: {r['jobs_per_s']:.2f} jobs/s p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms")
+    print(json.dumps({"workload": "config4_serving", "rate_hz": None if args.backlog else args.rate,
+                      "backlog": args.backlog, "pool": args.pool, **res}))
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,7 @@ class Dataset:
     precision: str                  # "f64" | "f32_phase64" | "f32_phase32"
     kernel_sigma: float = 0.9
     per_channel: bool = False       # one image per channel (cube) instead of one image
+    row_period: int = 0             # baselines per time slice (rows are time-major)
     sky: Sky | None = None
     meta: dict = field(default_factory=dict)
 
@@ -197,7 +198,8 @@ def config0(seed: int = CONFIG_SEED0 + 0, device=None) -> Dataset:
     sky = point_sources(5, math.radians(1.0), n, cell, rng)
     vis = visibilities(uvw, np.array([1.0]), sky, device=device)
     w = np.ones(vis.shape, dtype=np.float64)
-    return Dataset("config0", uvw, None, vis, w, None, n, 8, 7, cell, "f64", sky=sky)
+    return Dataset("config0", uvw, None, vis, w, None, n, 8, 7, cell, "f64", sky=sky,
+                   row_period=32 * 31 // 2)
 
 
 def _config1_inputs(seed: int, device, rows_stride: int = 1):
@@ -224,7 +226,7 @@ def config1(seed: int = CONFIG_SEED0 + 1, device=None, rows_stride: int = 1) -> 
     vis = vis.astype(np.complex64)
     w = np.ones(vis.shape, dtype=np.float32)
     return Dataset("config1", uvw, freq, vis, w, None, 4096, 64, 7, 0.2 / 4096,
-                   "f32_phase64", sky=sky)
+                   "f32_phase64", sky=sky, row_period=0 if rows_stride > 1 else 256 * 255 // 2)
 
 
 def config2(precision: str = "f32_phase64", seed: int = CONFIG_SEED0 + 1, device=None,
@@ -238,7 +240,7 @@ def config2(precision: str = "f32_phase64", seed: int = CONFIG_SEED0 + 1, device
         vis = vis.astype(np.complex64)
         w = np.ones(vis.shape, dtype=np.float32)
     return Dataset("config2", uvw, freq, vis, w, None, 2048, 32, 7, 0.2 / 2048,
-                   precision, sky=sky)
+                   precision, sky=sky, row_period=0 if rows_stride > 1 else 256 * 255 // 2)
 
 
 def config3(seed: int = CONFIG_SEED0 + 3, device=None, n_times: int = 512) -> Dataset:
@@ -258,7 +260,8 @@ def config3(seed: int = CONFIG_SEED0 + 3, device=None, n_times: int = 512) -> Da
         flags[:, c] = (rng.random(vis.shape[0]) < p[c]).astype(np.uint8)
     w = np.ones(vis.shape, dtype=np.float32)
     return Dataset("config3", uvw, freq, vis, w, flags, n, 16, 7, cell, "f32_phase64",
-                   per_channel=True, sky=sky, meta={"flag_fraction": p})
+                   per_channel=True, sky=sky, meta={"flag_fraction": p},
+                   row_period=128 * 127 // 2)
 
 
 # ----------------------------------------------------------------------------
@@ -293,7 +296,8 @@ def make_job(spec: dict, seed: int, device=None) -> Dataset:
     vis = visibilities(uvw, np.array([1.0]), sky, device=device).astype(np.complex64)
     w = np.ones(vis.shape, dtype=np.float32)
     return Dataset(f"job{seed}", uvw, None, vis, w, None, n, spec["n_wplanes"], 7, cell,
-                   "f32_phase64", sky=sky, meta=dict(spec))
+                   "f32_phase64", sky=sky, meta=dict(spec),
+                   row_period=spec["n_ant"] * (spec["n_ant"] - 1) // 2)
 
 
 def poisson_arrivals(n_jobs: int, rate_hz: float, rng: np.random.Generator) -> np.ndarray:
@@ -382,5 +386,6 @@ def config1_device(device="cuda", seed: int = CONFIG_SEED0 + 1, grid_n: int = 40
                               dtype=torch.complex128 if f64 else torch.complex64)
     wts = torch.ones(vis.shape, dtype=torch.float64 if f64 else torch.float32, device=device)
     return {"uvw": uvw_d, "vis": vis, "weights": wts, "freq_hz": freq, "sky": sky,
+            "row_period": 0 if rows_stride > 1 else 256 * 255 // 2,
             "params": dict(grid_n=grid_n, n_wplanes=n_wplanes, support=7,
                            cell_rad=0.2 / grid_n, precision=precision, kernel_sigma=0.9)}

@@ -24,9 +24,10 @@ GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1 = 1, 2, 4, 8
 
 # symbols declared in include/wsg.h
 SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_set_budget",
-           "wsg_set_timing",
-           "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image", "wsg_stage_grid",
-           "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune")
+           "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image",
+           "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune",
+           "wsg_server_create", "wsg_server_destroy", "wsg_server_submit", "wsg_server_poll",
+           "wsg_server_wait", "wsg_server_memory", "wsg_trim")
 
 
 class WsgError(RuntimeError):
@@ -46,7 +47,7 @@ class Params(ctypes.Structure):
 
 class Vis(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_chan", ctypes.c_int32), ("mem", ctypes.c_int32),
-                ("uvw", ctypes.c_void_p), ("freq_hz", ctypes.c_void_p), ("vis", ctypes.c_void_p),
+                ("row_period", ctypes.c_int64), ("uvw", ctypes.c_void_p), ("freq_hz", ctypes.c_void_p), ("vis", ctypes.c_void_p),
                 ("weights", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
 
@@ -62,6 +63,17 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("footprint", ctypes.c_uint64), ("stats", Stats)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        return d
 
 
 _lib = None
@@ -99,8 +111,22 @@ def load() -> ctypes.CDLL:
                                            P, S, P]
         lib.wsg_autotune.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis),
                                      ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
-        for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_image",
-                     "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune"):
+        lib.wsg_server_create.argtypes = [ctypes.c_int, S, ctypes.c_uint64, ctypes.POINTER(P)]
+        lib.wsg_server_destroy.argtypes = [P]
+        lib.wsg_server_destroy.restype = None
+        lib.wsg_server_submit.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S,
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        lib.wsg_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(S),
+                                        ctypes.POINTER(JobInfo)]
+        lib.wsg_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(JobInfo)]
+        lib.wsg_server_memory.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        lib.wsg_trim.argtypes = [P]
+        for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check",
+                     "wsg_footprint", "wsg_image", "wsg_stage_grid", "wsg_stage_fft",
+                     "wsg_stage_wcorrect", "wsg_autotune", "wsg_server_create",
+                     "wsg_server_submit", "wsg_server_poll", "wsg_server_wait",
+                     "wsg_server_memory", "wsg_trim"):
             getattr(lib, name).restype = S
         lib.wsg_n_images.restype = S
         _lib = lib
@@ -151,9 +177,10 @@ class VisBuffers:
     keep: tuple
 
 
-def make_vis(uvw, vis, weights=None, flags=None, freq_hz=None) -> VisBuffers:
+def make_vis(uvw, vis, weights=None, flags=None, freq_hz=None, row_period=0) -> VisBuffers:
     """Describe measurements: uvw [rows,3] f64, vis [rows,n_chan] complex, weights and flags
-    [rows,n_chan] or None, freq_hz (host) or None.  All buffers in one memory space."""
+    [rows,n_chan] or None, freq_hz (host) or None.  All buffers in one memory space.
+    row_period: baselines per time slice of time-major data (a performance hint)."""
     pu, mu = _ptr_mem(uvw)
     pv, mv = _ptr_mem(vis)
     pw, mw = _ptr_mem(weights)
@@ -166,8 +193,8 @@ def make_vis(uvw, vis, weights=None, flags=None, freq_hz=None) -> VisBuffers:
     fq = None
     if freq_hz is not None:
         fq = np.ascontiguousarray(freq_hz, dtype=np.float64)
-    d = Vis(int(n_rows), int(n_chan), spaces.pop() if spaces else MEM_HOST, pu, None if fq is None
-            else fq.ctypes.data, pv, pw, pf)
+    d = Vis(int(n_rows), int(n_chan), spaces.pop() if spaces else MEM_HOST, int(row_period), pu,
+            None if fq is None else fq.ctypes.data, pv, pw, pf)
     return VisBuffers(d, (uvw, vis, weights, flags, fq))
 
 
@@ -266,6 +293,71 @@ class Context:
                                  ctypes.byref(best))
         self._check(rc, "wsg_autotune")
         return int(best.value)
+
+
+class Server:
+    """Continuous-batching imaging server (n_slots concurrent jobs, device-memory budget)."""
+
+    def __init__(self, device: int = 0, n_slots: int = 4, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        st = load().wsg_server_create(int(device), int(n_slots), int(hbm_budget), ctypes.byref(h))
+        if st != OK:
+            raise WsgError(st, f"wsg_server_create: {strerror(st)}")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, params: Params, vb: VisBuffers, out) -> int:
+        """Queue a job; `out` must stay valid until the job is reported done."""
+        po, mo = _ptr_mem(out)
+        t = ctypes.c_uint64(0)
+        st = load().wsg_server_submit(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po,
+                                      mo, ctypes.byref(t))
+        if st != OK:
+            raise WsgError(st, f"wsg_server_submit: {strerror(st)}")
+        self._keep[t.value] = (params, vb, out)
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int32(0)
+        info = JobInfo()
+        st = load().wsg_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(info))
+        if st != OK:
+            raise WsgError(st, "wsg_server_poll: unknown ticket")
+        if done.value:
+            self._keep.pop(ticket, None)
+            return True, info.as_dict()
+        return False, None
+
+    def wait(self, ticket: int) -> dict:
+        info = JobInfo()
+        st = load().wsg_server_wait(self._h, int(ticket), ctypes.byref(info))
+        if st != OK:
+            raise WsgError(st, "wsg_server_wait: unknown ticket")
+        self._keep.pop(ticket, None)
+        return info.as_dict()
+
+    def memory(self):
+        held, peak = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        load().wsg_server_memory(self._h, ctypes.byref(held), ctypes.byref(peak))
+        return int(held.value), int(peak.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wsg_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def check(params: Params, vb: VisBuffers | None = None) -> int:

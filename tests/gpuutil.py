@@ -46,21 +46,21 @@ def both_params(grid_n, n_wplanes, support, cell_rad, precision="f64", kernel_si
     return wp, op
 
 
-def gpu_image(ctx, wp, uvw, vis, wts=None, flags=None, freq=None, on_device=True):
+def gpu_image(ctx, wp, uvw, vis, wts=None, flags=None, freq=None, on_device=True, row_period=0):
     """Image through the C ABI; returns (image [n_img,N,N] numpy, stats list)."""
     import torch
     n_img = wsg.n_images(wp, wsg.make_vis(uvw, vis, wts, flags, freq))
     n = wp.grid_n
     if on_device:
         vb = wsg.make_vis(dev(uvw), dev(vis), None if wts is None else dev(wts),
-                          None if flags is None else dev(flags), freq)
+                          None if flags is None else dev(flags), freq, row_period)
         out = torch.full((n_img, n, n), float("nan"), dtype=torch.float64, device=DEV)
         st = ctx.image(wp, vb, out)
         torch.cuda.synchronize()
         return out.cpu().numpy(), st
     vb = wsg.make_vis(np.ascontiguousarray(uvw), np.ascontiguousarray(vis),
                       None if wts is None else np.ascontiguousarray(wts),
-                      None if flags is None else np.ascontiguousarray(flags), freq)
+                      None if flags is None else np.ascontiguousarray(flags), freq, row_period)
     out = np.full((n_img, n, n), np.nan)
     st = ctx.image(wp, vb, out)
     return out, st

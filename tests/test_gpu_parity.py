@@ -27,12 +27,15 @@ def ctx():
 
 
 # ---------------------------------------------------------------- end to end, config 0
-@pytest.mark.parametrize("on_device", [True, False])
-def test_config0_f64_image(ctx, config0, on_device):
+@pytest.mark.parametrize("on_device,row_period", [(True, 496), (False, 496), (True, 0), (True, 37)])
+def test_config0_f64_image(ctx, config0, on_device, row_period):
+    # row_period: the baselines per time slice (496), no hint, and a wrong hint; the
+    # hint only changes the traversal order of the binning passes
     ds = config0
-    log(f"config0 f64 image on_device={on_device}")
+    log(f"config0 f64 image on_device={on_device} row_period={row_period}")
     wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, "f64")
-    img, st = gpu_image(ctx, wp, ds.uvw, ds.vis, ds.weights, on_device=on_device)
+    img, st = gpu_image(ctx, wp, ds.uvw, ds.vis, ds.weights, on_device=on_device,
+                        row_period=row_period)
     ref = oracle_image(op, ds.uvw, ds.vis, ds.weights)
     assert_stats(st, ref["stats"])
     assert rel(img[0], ref["image"][0]) <= TOL64
@@ -42,7 +45,7 @@ def test_config0_f64_raw(ctx, config0):
     ds = config0
     wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, "f64",
                          grid_correct=False, normalize=False)
-    img, st = gpu_image(ctx, wp, ds.uvw, ds.vis, ds.weights)
+    img, st = gpu_image(ctx, wp, ds.uvw, ds.vis, ds.weights, row_period=ds.row_period)
     ref = oracle_image(op, ds.uvw, ds.vis, ds.weights)
     assert rel(img[0], ref["raw"][0].real) <= TOL64
 
@@ -53,7 +56,7 @@ def test_config0_f32_paths(ctx, config0, precision):
     vis, wts = cast_inputs(precision, ds.vis, ds.weights)
     wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, precision,
                          grid_correct=False, normalize=False)
-    img, st = gpu_image(ctx, wp, ds.uvw, vis, wts)
+    img, st = gpu_image(ctx, wp, ds.uvw, vis, wts, row_period=ds.row_period)
     ref = oracle_image(op, ds.uvw, vis, wts)
     assert_stats(st, ref["stats"], sum_w_rel=1e-12)
     e = rel(img[0], ref["raw"][0].real)
@@ -70,7 +73,8 @@ def test_stage_grid(ctx, config0, precision):
     wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, precision)
     ctype = torch.complex128 if precision == "f64" else torch.complex64
     out = torch.zeros((ds.n_wplanes, ds.grid_n, ds.grid_n), dtype=ctype, device=DEV)
-    st = ctx.stage_grid(wp, wsg.make_vis(dev(ds.uvw), dev(vis), dev(wts)), out)
+    st = ctx.stage_grid(wp, wsg.make_vis(dev(ds.uvw), dev(vis), dev(wts), row_period=ds.row_period),
+                        out)
     inp = oracle.Inputs.make(ds.uvw, None, vis, wts)
     wmin, wmax = oracle.w_range(inp, op)
     g, cnt = oracle.grid(inp, op, wmin, wmax)
@@ -126,7 +130,8 @@ def test_stage_wcorrect(ctx, precision):
     ref = oracle.post(A, sum_w, op)
     e = rel(out.cpu().numpy(), ref)
     log(f"stage wcorrect {precision}: rel err {e:.3e}")
-    tol = {"f64": TOL64, "f32_phase64": 1e-12, "f32_phase32": 1e-3}[precision]
+    # f32_phase64: FP64 argument reduced exactly, FP32 sin/cos of the reduced angle
+    tol = {"f64": TOL64, "f32_phase64": 1e-6, "f32_phase32": 1e-3}[precision]
     assert e <= tol
 
 
@@ -136,7 +141,8 @@ def test_f32_random_1024_ragged(ctx):
     uvw, vis, wts = synth.random_visibilities(300_001, 1, n, 0.2 / n, seed=31, w_extent=800.0)
     vis, wts = cast_inputs("f32_phase64", vis, wts)
     wp, op = both_params(n, nw, 7, 0.2 / n, "f32_phase64", grid_correct=False, normalize=False)
-    img, st = gpu_image(ctx, wp, uvw, vis, wts)
+    # row period 1000: 301 time slices, the last one ragged
+    img, st = gpu_image(ctx, wp, uvw, vis, wts, row_period=1000)
     ref = oracle_image(op, uvw, vis, wts)
     assert_stats(st, ref["stats"])
     e = rel(img[0], ref["raw"][0].real)
@@ -280,7 +286,7 @@ def test_channels_metres_mfs_and_cube(ctx):
     flags = (rng.random((rows, nch)) < 0.2).astype(np.uint8)
     for per_channel in (False, True):
         wp, op = both_params(n, 4, 7, 0.2 / n, "f64", per_channel=per_channel)
-        img, st = gpu_image(ctx, wp, uvw, vis, wts, flags, freq)
+        img, st = gpu_image(ctx, wp, uvw, vis, wts, flags, freq, row_period=50)
         ref = oracle_image(op, uvw, vis, wts, flags, freq)
         assert_stats(st, ref["stats"])
         assert img.shape[0] == (nch if per_channel else 1)

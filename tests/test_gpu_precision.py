@@ -1,0 +1,80 @@
+"""Precision study on the config-1 inputs at 2048^2 x 32 planes (field edges at
+l, m = +-0.1): complex128 vs complex64 mesh and transform, FP64 vs FP32 w-phase,
+and the naive FP32 n - 1, each against the FP64 oracle on the same inputs.
+Errors are relative L2 over the raw image (Re A), the bar of the plain path."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_07321_amd import synth, wsg
+from tests.gpuutil import DEV, log, rel
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    import torch
+    d64 = synth.config1_device(DEV, grid_n=2048, n_wplanes=32, precision="f64")
+    torch.cuda.synchronize()
+    host = {"uvw": d64["uvw"].cpu().numpy(), "freq": d64["freq_hz"],
+            "vis128": d64["vis"].cpu().numpy()}
+    host["vis64"] = host["vis128"].astype(np.complex64)
+    log(f"config 2 inputs: {host['vis128'].shape}")
+    return d64, host
+
+
+def _run(d, host, precision, naive=False):
+    import torch
+    v = d["vis"] if precision == "f64" else d["vis"].to(torch.complex64)
+    w = d["weights"] if precision == "f64" else d["weights"].to(torch.float32)
+    prm = wsg.make_params(2048, 32, 7, 0.2 / 2048, precision, grid_correct=False,
+                          normalize=False, naive_nm1=naive)
+    vb = wsg.make_vis(d["uvw"], v, w, None, host["freq"], d["row_period"])
+    out = torch.empty((1, 2048, 2048), dtype=torch.float64, device=DEV)
+    with wsg.Context(0) as ctx:
+        st = ctx.image(prm, vb, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[0], st[0]
+
+
+def test_precision_study(c2):
+    d, host = c2
+    op = oracle.Params(2048, 32, 7, 0.2 / 2048, 0.9, grid_correct=False, normalize=False)
+    log("oracle on complex128 inputs")
+    ref128 = oracle.image(oracle.Inputs.make(host["uvw"], host["freq"], host["vis128"]), op,
+                          plane_chunk=8)
+    log("oracle on complex64 inputs")
+    ref64 = oracle.image(oracle.Inputs.make(host["uvw"], host["freq"],
+                                            host["vis64"].astype(np.complex128)), op,
+                         plane_chunk=8)
+    sky = d["sky"]
+    pq = np.round(sky.m / (0.2 / 2048)).astype(int) + 1024
+    pp = np.round(sky.l / (0.2 / 2048)).astype(int) + 1024
+    rows = {}
+    for name, prec, naive, ref in (("f64", "f64", False, ref128),
+                                   ("f32_phase64", "f32_phase64", False, ref64),
+                                   ("f32_phase32", "f32_phase32", False, ref64),
+                                   ("f32_phase32_naive", "f32_phase32", True, ref64)):
+        img, st = _run(d, host, prec, naive)
+        A = ref["raw"][0].real
+        e = rel(img, A)
+        peak = float(np.abs(img - A).max() / np.abs(A).max())
+        src = float(np.abs(img[pq, pp] - A[pq, pp]).max() / np.abs(A[pq, pp]).max())
+        rows[name] = {"rel_l2": e, "peak": peak, "source_max": src, "n_used": st["n_used"],
+                      "n_dropped": st["n_dropped"]}
+        log(f"{name:18s} rel-L2 {e:.3e}  peak {peak:.3e}  sources {src:.3e}")
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "precision_study.json"), "w") as f:
+        json.dump(rows, f, indent=1)
+    assert rows["f64"]["rel_l2"] <= 1e-12
+    assert rows["f32_phase64"]["rel_l2"] <= 1e-5
+    # the FP32 phase loses accuracy at large w and the field edge; the naive n - 1
+    # loses more (it cancels near the phase centre)
+    assert rows["f32_phase32"]["rel_l2"] > rows["f32_phase64"]["rel_l2"]
+    assert rows["f32_phase32_naive"]["rel_l2"] >= rows["f32_phase32"]["rel_l2"]
