@@ -123,7 +123,20 @@ def main():
                     help="keep every k-th row (quick runs only; not the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=400_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a reference elementwise pass of known traffic (2 GiB read, "
+                         "2 GiB written per launch) for calibrating rocprofv3 byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 2 ** 29
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.add(x, 0.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": n * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build images on one GPU; multi-GPU runs (w-plane "
                                    "sharding) are not implemented", "n_gpus": args.gpus}))

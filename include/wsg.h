@@ -96,7 +96,7 @@ typedef struct {
     int32_t plane_lo;      /* image only planes [plane_lo, plane_hi) of N_w (both 0: all);    */
     int32_t plane_hi;      /*   needs a given w range, so that every shard agrees             */
     uint32_t flags;        /* WSG_GRID_CORRECT | WSG_NORMALIZE | ...                           */
-    int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64/128 */
+    int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64     */
 } wsg_params;
 
 typedef struct {

@@ -22,8 +22,8 @@
 // slowly across the mesh, so consecutive elements of a thread mostly fall in
 // the same bins: a "run" is a maximal stretch of consecutive elements whose
 // footprints all touch one bin, and each run costs one global atomic instead
-// of one per element (the scatter looks ahead to size the run before it
-// reserves its slots).  This matters because the uv coverage is extremely
+// of one per element (the scatter first sizes the runs of a block of time
+// slices, then reserves their slots).  This matters because the uv coverage is extremely
 // uneven: the short baselines of a dense core all land in the few central
 // tiles, and per-element atomics there serialise.  Records of one run stay
 // contiguous inside their bin.
@@ -405,30 +405,130 @@ __device__ __forceinline__ void write_record(void *records, uint32_t slot, const
     }
 }
 
+// The scatter walks the same tracks in blocks of kScatL time slices, in three
+// phases with the same trip count on every lane (so no lane waits on another's
+// inner loop):
+//   1. the bins of each element, packed into one word, into LDS;
+//   2. backwards through the block, the length of the run that starts at each
+//      (element, bin);
+//   3. forwards, one slot reservation per run (an atomic on the bin's cursor),
+//      then the records.
+constexpr int kScatThreads = 128;
+constexpr int kScatL = 64;
+constexpr uint32_t kNoKey = 0xffffffffu;
+
+// base bin (lowest tile) in bits 0..26, bit 27: also the tile to the right, bit 28:
+// also the tile above
+__device__ __forceinline__ uint32_t pack_keys(const JobGeom &g, const ImgState &s,
+                                              const double *uvw, const uint8_t *mask, int64_t r,
+                                              int c, int img) {
+    int64_t e = r * g.n_chan + c;
+    if (!mask[e]) return kNoKey;
+    Placed pl;
+    if (!place(g, s, uvw, r, c, pl)) return kNoKey;
+    int kl = pl.k - g.plane_lo;
+    if (kl < 0 || kl >= g.n_pl) return kNoKey;
+    int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
+    int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
+    uint32_t base = (uint32_t)(bin_base(g, img, kl) + (int64_t)ty0 * g.NT + tx0);
+    return base | ((uint32_t)(tx1 > tx0) << 27) | ((uint32_t)(ty1 > ty0) << 28);
+}
+
+__device__ __forceinline__ void unpack_keys(uint32_t pk, int NT, Keys &ks) {
+    ks.n = 0;
+    if (pk == kNoKey) return;
+    uint32_t b = pk & 0x7ffffffu;
+    bool cx = (pk >> 27) & 1u, cy = (pk >> 28) & 1u;
+    ks.k[ks.n++] = b;
+    if (cx) ks.k[ks.n++] = b + 1;
+    if (cy) ks.k[ks.n++] = b + (uint32_t)NT;
+    if (cx && cy) ks.k[ks.n++] = b + (uint32_t)NT + 1;
+}
+
 template <typename VT>
-__global__ __launch_bounds__(kThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
-                                                      const void *__restrict__ vis,
-                                                      const void *__restrict__ wts,
-                                                      const uint8_t *__restrict__ mask,
-                                                      const ImgState *st, uint32_t *cursor,
-                                                      void *__restrict__ records) {
-    const Track tr = track_of(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (!tr.ok) return;
-    const int img = (g.n_img > 1) ? tr.c : 0;
-    const ImgState s = st[img];
-    uint32_t okey[4] = {0, 0, 0, 0};
+__global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
+                                                          const void *__restrict__ vis,
+                                                          const void *__restrict__ wts,
+                                                          const uint8_t *__restrict__ mask,
+                                                          const ImgState *st, uint32_t *cursor,
+                                                          void *__restrict__ records, uint32_t capacity,
+                                                          uint32_t *overflow) {
+    __shared__ uint32_t s_key[kScatL][kScatThreads];
+    __shared__ uint32_t s_len[kScatL][kScatThreads];   // 4 x 8-bit run lengths
+    const int lane = threadIdx.x;
+    // track of this thread: blocks of kScatL time slices
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
+    const int c = (int)(idx % g.n_chan);
+    const int64_t rest = idx / g.n_chan;
+    const int64_t b = rest % g.P;
+    const int64_t tb = rest / g.P;
+    const int64_t t0 = tb * kScatL;
+    const bool ok = t0 < g.n_t;
+    const int img = (g.n_img > 1) ? c : 0;
+    const ImgState s = st[ok ? img : 0];
+    int nt = 0;
+    if (ok) {
+        int64_t t1 = min(g.n_t, t0 + kScatL);
+        for (int64_t t = t0; t < t1; ++t) {
+            if (t * g.P + b >= g.n_rows) break;
+            ++nt;
+        }
+    }
+    // phase 1: packed bins
+    for (int k = 0; k < kScatL; ++k) {
+        uint32_t pk = kNoKey;
+        if (k < nt) pk = pack_keys(g, s, uvw, mask, (t0 + k) * g.P + b, c, img);
+        s_key[k][lane] = pk;
+    }
+    // phase 2: run lengths, backwards; `open` holds the bins of element k+1 with the
+    // length of their run from k+1 on
+    {
+        uint32_t okey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
+        uint32_t olen[4] = {0, 0, 0, 0};
+        for (int k = kScatL - 1; k >= 0; --k) {
+            Keys ks;
+            unpack_keys(s_key[k][lane], g.NT, ks);
+            uint32_t nkey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
+            uint32_t nlen[4] = {0, 0, 0, 0};
+            uint32_t packed = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i >= ks.n) continue;
+                uint32_t len = 1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (okey[j] == ks.k[i]) len = olen[j] + 1;
+                nkey[i] = ks.k[i];
+                nlen[i] = len;
+                packed |= min(len, 255u) << (8 * i);
+            }
+            s_len[k][lane] = packed;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                okey[i] = nkey[i];
+                olen[i] = nlen[i];
+            }
+        }
+    }
+    // phase 3: forwards, one reservation per run
+    uint32_t okey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
     uint32_t onext[4] = {0, 0, 0, 0};
     uint32_t orem[4] = {0, 0, 0, 0};
-    for (int64_t t = tr.t0; t < tr.t1; ++t) {
-        int64_t r = t * g.P + tr.b;
-        if (r >= g.n_rows) break;
-        Placed pl;
+    for (int k = 0; k < nt; ++k) {
+        uint32_t pk = s_key[k][lane];
+        if (pk == kNoKey) continue;
         Keys ks;
-        if (!element_keys(g, s, uvw, mask, r, tr.c, img, pl, ks)) continue;
-        int64_t e = r * g.n_chan + tr.c;
+        unpack_keys(pk, g.NT, ks);
+        const uint32_t lens = s_len[k][lane];
+        const int64_t r = (t0 + k) * g.P + b;
+        Placed pl;
+        place(g, s, uvw, r, c, pl);
+        const int64_t e = r * g.n_chan + c;
         double vr, vi, wt;
         ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
-        for (int i = 0; i < ks.n; ++i) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= ks.n) continue;
             const uint32_t key = ks.k[i];
             uint32_t slot = 0;
             bool have = false;
@@ -440,19 +540,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(JobGeom g, const double *_
                     have = true;
                 }
             if (!have) {
-                // a new run: its length is the number of consecutive elements of
-                // this track, from this one on, whose footprint touches `key`
-                uint32_t len = 1;
-                for (int64_t t2 = t + 1; t2 < tr.t1; ++t2) {
-                    int64_t r2 = t2 * g.P + tr.b;
-                    if (r2 >= g.n_rows) break;
-                    Placed pl2;
-                    Keys ks2;
-                    element_keys(g, s, uvw, mask, r2, tr.c, img, pl2, ks2);
-                    if (!has_key(ks2, key)) break;
-                    ++len;
-                }
-                uint32_t base = atomicAdd(&cursor[key], len);
+                const uint32_t len = (lens >> (8 * i)) & 0xffu;
+                const uint32_t base = atomicAdd(&cursor[key], len);
                 slot = base;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -463,7 +552,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(JobGeom g, const double *_
                         have = true;
                     }
             }
-            write_record<VT>(records, slot, g, pl, key, vr, vi, wt);
+            // the counting pass sized the buffer; a slot beyond it would mean the two
+            // passes disagree: never write there, report it instead
+            if (slot < capacity)
+                write_record<VT>(records, slot, g, pl, key, vr, vi, wt);
+            else
+                atomicAdd(overflow, 1u);
         }
     }
 }
@@ -558,14 +652,17 @@ void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64
 
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
                     bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
-                    void *records, hipStream_t s) {
+                    void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s) {
     int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
     if (n_elem == 0) return;
-    unsigned blocks = (unsigned)((track_threads(g) + kThreads - 1) / kThreads);
+    int64_t threads = (int64_t)g.n_chan * g.P * ((g.n_t + kScatL - 1) / kScatL);
+    unsigned blocks = (unsigned)((threads + kScatThreads - 1) / kScatThreads);
     if (f64)
-        k_scatter<double><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor, records);
+        k_scatter<double><<<blocks, kScatThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor,
+                                                          records, capacity, overflow);
     else
-        k_scatter<float><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor, records);
+        k_scatter<float><<<blocks, kScatThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor,
+                                                         records, capacity, overflow);
 }
 
 size_t scan_tmp_elems(size_t n) {

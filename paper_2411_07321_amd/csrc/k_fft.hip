@@ -360,11 +360,19 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
     using PR = typename Phase<PM>::R;
     constexpr int P = SH::P, NTR = SH::NTR;
     __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    // n - 1 of this workgroup's pixels, computed once and read for every plane
+    __shared__ PR s_nm1[NTR * N];
     P2Index<T, N> ix(threadIdx.x);
     const int img = blockIdx.y;
     const int q = blockIdx.x * NTR + ix.r;            // image row handled by this thread
     const ImgState &st = a.st[img];
     const double m = (double)(q - N / 2) * a.cell;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        bool in;
+        const double l = (double)(ix.t + s * P - N / 2) * a.cell;
+        s_nm1[ix.r * N + ix.t + s * P] = Phase<PM>::nm1(l, m, a.naive_nm1, in);
+    }
     double acc[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) acc[s] = 0.0;
@@ -378,13 +386,11 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
         C2<T> v[E];
         load_blocked<T, N>(v, Y, ix.t, q);
         fft_line<T, N>(v, lre, lim, ix.t, tw);
-        // n - 1 is recomputed per plane: holding it for all E pixels would not fit
-        // in registers next to the points and the FP64 sums
+        // (n - 1 comes from LDS: holding it for all E pixels in registers would not
+        // fit next to the points and the FP64 sums)
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            bool in;
-            const double l = (double)(ix.t + s * P - N / 2) * a.cell;
-            PR nm1 = Phase<PM>::nm1(l, m, a.naive_nm1, in);
+            const PR nm1 = s_nm1[ix.r * N + ix.t + s * P];
             typename std::conditional<PM == 0, double, float>::type c, sn;
             Phase<PM>::screen(nm1, wk, c, sn);
             acc_re(acc[s], v[s], c, sn);

@@ -18,6 +18,7 @@ namespace wsg {
 namespace {
 
 constexpr int kGridThreads = 256;
+constexpr int kRunCap = 8;
 
 template <typename T>
 struct RecTraits;
@@ -78,7 +79,8 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // consecutive records of a lane usually have the same nearest cell.  With
 // ACC (complex64 mesh, S <= 7) the lane sums the S x S footprint values of
 // such records in registers and adds them to the LDS tile only when the cell
-// changes; otherwise every record is added to the tile directly.
+// changes, or after kRunCap records (so an FP32 register sum never holds more
+// than kRunCap terms); otherwise every record is added to the tile directly.
 template <typename T, int TT, int SS, bool ACC>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,
@@ -89,8 +91,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                                                         C2<T> *__restrict__ grid, int transposed) {
     constexpr int TP = TT + 1;
     constexpr int H = (SS - 1) / 2;
-    __shared__ T s_re[TT * TP];
-    __shared__ T s_im[TT * TP];
+    // the tile sums many contributions per cell: kept in FP64 for every mesh type,
+    // rounded once when the cell is stored
+    __shared__ double s_re[TT * TP];
+    __shared__ double s_im[TT * TP];
     const uint32_t item = blockIdx.x;
     const uint32_t b = item_bin[item];
     const uint32_t c = item - item_off[b];
@@ -100,8 +104,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t r1 = offsets[b] + min(cnt, (c + 1) * chunk);
 
     for (int i = threadIdx.x; i < TT * TP; i += blockDim.x) {
-        s_re[i] = T(0);
-        s_im[i] = T(0);
+        s_re[i] = 0.0;
+        s_im[i] = 0.0;
     }
     __syncthreads();
 
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t q1 = r0 + min(n, (threadIdx.x + 1) * per);
 
     T ar[ACC ? SS : 1][ACC ? SS : 1], ai[ACC ? SS : 1][ACC ? SS : 1];
-    int cli = INT32_MIN, clj = 0;
+    int cli = INT32_MIN, clj = 0, run = 0;
     auto flush = [&](int li, int lj) {
         if constexpr (ACC) {
 #pragma unroll
@@ -122,8 +126,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 for (int a = 0; a < SS; ++a) {
                     int i = li + a - H;
                     if (j >= 0 && j < TT && i >= 0 && i < TT) {
-                        atomicAdd(&s_re[j * TP + i], ar[bb][a]);
-                        atomicAdd(&s_im[j * TP + i], ai[bb][a]);
+                        atomicAdd(&s_re[j * TP + i], (double)ar[bb][a]);
+                        atomicAdd(&s_im[j * TP + i], (double)ai[bb][a]);
                     }
                     ar[bb][a] = T(0);
                     ai[bb][a] = T(0);
@@ -151,11 +155,13 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
         }
         if constexpr (ACC) {
-            if (li != cli || lj != clj) {
+            if (li != cli || lj != clj || run == kRunCap) {
                 if (cli != INT32_MIN) flush(cli, clj);
                 cli = li;
                 clj = lj;
+                run = 0;
             }
+            ++run;
 #pragma unroll
             for (int bb = 0; bb < SS; ++bb) {
                 T wr = re * gy[bb], wi = im * gy[bb];
@@ -175,8 +181,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 for (int a = 0; a < SS; ++a) {
                     int i = li + a - H;
                     if (i < 0 || i >= TT) continue;
-                    atomicAdd(&s_re[j * TP + i], wr * gx[a]);
-                    atomicAdd(&s_im[j * TP + i], wi * gx[a]);
+                    atomicAdd(&s_re[j * TP + i], (double)(wr * gx[a]));
+                    atomicAdd(&s_im[j * TP + i], (double)(wi * gx[a]));
                 }
             }
         }
@@ -194,7 +200,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         int fast = t % TT, slow = t / TT;
         int i, j;
         if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
-        T vr = s_re[j * TP + i], vi = s_im[j * TP + i];
+        T vr = (T)s_re[j * TP + i], vi = (T)s_im[j * TP + i];
         size_t idx = cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0);
         if (split) {
             atomicAdd(&grid[idx].x, vr);
@@ -257,10 +263,6 @@ void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *off
     case 16: launch_support<T, 16>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
     case 32: launch_support<T, 32>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
     case 64: launch_support<T, 64>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
-    case 128:
-        if constexpr (sizeof(T) == 4)
-            launch_support<T, 128>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr);
-        break;
     default: break;
     }
 }
@@ -275,7 +277,6 @@ void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, voi
     case 16: k_zero_split<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
     case 32: k_zero_split<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
     case 64: k_zero_split<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
-    case 128: k_zero_split<T, 128><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
     default: break;
     }
 }

@@ -105,9 +105,10 @@ void launch_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n_bins, uint
                    hipStream_t s);
 void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
                      size_t n_bins, hipStream_t s);
+// records beyond `capacity` are not written; each such slot increments *overflow
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
                     bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
-                    void *records, hipStream_t s);
+                    void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s);
 void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]

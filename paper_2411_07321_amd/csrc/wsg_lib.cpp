@@ -101,6 +101,8 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
         return WSG_EINVAL;
     }
     if (p->support > kMaxSupport) { why = "support above 15"; return WSG_EUNSUPPORTED; }
+    // (every tile size here is >= 16 >= S - 1, so a footprint touches at most two
+    // tiles per axis, which the binning passes rely on)
     if (p->precision < WSG_PREC_F64 || p->precision > WSG_PREC_F32_PHASE32) { why = "bad precision"; return WSG_EINVAL; }
     if (!(p->cell_rad > 0.0) || !std::isfinite(p->cell_rad)) { why = "cell_rad must be finite and > 0"; return WSG_EINVAL; }
     if (!(p->kernel_sigma > 0.0) || !std::isfinite(p->kernel_sigma)) { why = "kernel_sigma must be finite and > 0"; return WSG_EINVAL; }
@@ -127,7 +129,8 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
             why = "tile must be 16, 32, 64 or 128 and <= grid_n";
             return WSG_EINVAL;
         }
-        if (p->tile == 128 && p->precision == WSG_PREC_F64) { why = "tile 128 needs a complex64 mesh"; return WSG_EUNSUPPORTED; }
+        // the LDS tile holds FP64 sums: 64 x 64 cells is the largest that fits
+        if (p->tile == 128) { why = "tile 128 does not fit the FP64 LDS tile"; return WSG_EUNSUPPORTED; }
     }
     return WSG_OK;
 }
@@ -397,6 +400,7 @@ struct Binned {
     void *records;
     uint32_t n_items;
     uint32_t n_records;
+    uint32_t *overflow;    // device counter of records the scatter could not place
 };
 
 // Stage inputs, validity pass, counting sort and record scatter.  Ends with
@@ -528,7 +532,10 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     b.item_bin = (uint32_t *)(dy + align_up((size_t)b.n_records * rec_size(pl.f64)));
     mark(ctx, kMarkScatterStart, s);
     launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
-    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, b.records, s);
+    b.overflow = tot + 2;
+    WSG_HIP(ctx, hipMemsetAsync(b.overflow, 0, 4, s));
+    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, b.records, b.n_records,
+                   b.overflow, s);
     mark(ctx, kMarkScatter, s);
     return WSG_OK;
 }
@@ -544,6 +551,14 @@ wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, hip
 wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream_t s,
                       wsg_stats *stats, bool timed) {
     if (!stats) return WSG_OK;
+    {
+        wsg_status rc = ensure_pin(ctx, 64);
+        if (rc) return rc;
+        WSG_HIP(ctx, hipMemcpyAsync(ctx->pin, b.overflow, 4, hipMemcpyDeviceToHost, s));
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+        if (*(const uint32_t *)ctx->pin != 0)
+            return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
+    }
     float t[7] = {0, 0, 0, 0, 0, 0, 0};
     if (timed) {
         WSG_HIP(ctx, hipEventSynchronize(ctx->tev[kMarkEnd]));
@@ -884,11 +899,11 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
     wsg_status rc = common_checks(ctx, p, v);
     if (rc) return rc;
     hipStream_t s = pick_stream(ctx, nullptr);
-    const int cands[] = {16, 32, 64, 128};
+    const int cands[] = {16, 32, 64};
     float best_ms = 1e30f;
     int best = default_tile(p);
     for (int t : cands) {
-        if (t > p->grid_n || (t == 128 && f64_mode(p))) continue;
+        if (t > p->grid_n) continue;
         wsg_params q = *p;
         q.tile = t;
         float acc = 0.f;

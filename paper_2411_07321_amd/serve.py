@@ -25,13 +25,13 @@ from paper_2411_07321_amd import synth, wsg
 class PinnedJob:
     """One pooled dataset in pinned host memory plus its imaging parameters."""
 
-    def __init__(self, ds: synth.Dataset):
+    def __init__(self, ds: synth.Dataset, **param_overrides):
         import torch
         self.ds = ds
         self.uvw = torch.from_numpy(ds.uvw).pin_memory()
         self.vis = torch.from_numpy(np.ascontiguousarray(ds.vis)).pin_memory()
         self.wts = torch.from_numpy(np.ascontiguousarray(ds.weights)).pin_memory()
-        self.params = wsg.params_for(ds)
+        self.params = wsg.params_for(ds, **param_overrides)
         self.vb = wsg.make_vis(self.uvw, self.vis, self.wts, None, ds.freq_hz, ds.row_period)
         self.n_vis = ds.n_vis
         self.grid_n = ds.grid_n

@@ -59,8 +59,9 @@ def _v(n_rows=10, n_chan=1, **kw):
     (dict(plane_lo=4, plane_hi=4, w_min=0.0, w_max=1.0), wsg.EINVAL),
     (dict(plane_lo=0, plane_hi=9, w_min=0.0, w_max=1.0), wsg.EINVAL),
     (dict(tile=48), wsg.EINVAL),
-    (dict(tile=128), wsg.EUNSUPPORTED),                  # FP64 mesh tile limit
-    (dict(tile=128, precision="f32_phase64"), wsg.OK),
+    (dict(tile=128), wsg.EUNSUPPORTED),                  # FP64 LDS tile limit
+    (dict(tile=128, precision="f32_phase64"), wsg.EUNSUPPORTED),
+    (dict(tile=16, precision="f32_phase64"), wsg.OK),
 ])
 def test_parameter_validation(kw, code):
     assert wsg.check(_p(**kw), _v()) == code

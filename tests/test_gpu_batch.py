@@ -63,5 +63,5 @@ def test_autotune_picks_a_tile(c3):
                       ds.row_period)
     with wsg.Context(0) as ctx:
         best = ctx.autotune(prm, vb)
-        assert best in (16, 32, 64, 128)
+        assert best in (16, 32, 64)
         log(f"autotuned tile: {best}")

@@ -220,7 +220,7 @@ def test_tiny_meshes(ctx, n):
     assert rel(img[0], ref["image"][0]) <= TOL64
 
 
-@pytest.mark.parametrize("tile", [16, 32, 64, 128])
+@pytest.mark.parametrize("tile", [16, 32, 64])
 def test_tiles_f32(ctx, tile):
     n = 256
     uvw, vis, wts = _small(20_000, n=n, prec="f32_phase64", seed=8)
