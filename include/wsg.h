@@ -137,6 +137,10 @@ void wsg_destroy(wsg_ctx *ctx);
 const char *wsg_strerror(wsg_status s);
 /* Detail of the last failure on this context (never NULL). */
 const char *wsg_last_error(const wsg_ctx *ctx);
+/* The context's own hipStream_t (non-blocking, default priority), for callers that
+ * want the library's work off the null stream; NULL for a NULL context.  Valid
+ * until wsg_destroy. */
+void *wsg_context_stream(const wsg_ctx *ctx);
 /* Limit the context's workspace to `bytes` (0 = no limit); larger jobs fail with ENOMEM. */
 wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes);
 /* Record hipEvents between the stages of wsg_image and report their durations in
@@ -160,7 +164,10 @@ int32_t wsg_n_images(const wsg_params *p, const wsg_vis *v);
 /*
  * image: [n_images][N][N] double, row-major (p fastest), in memory space
  *        image_mem; written completely.
- * stream: hipStream_t to run on (NULL: the context's own stream).
+ * stream: hipStream_t to run on; NULL is HIP's null stream, which is ordered
+ *         after the work of every blocking stream of the device (torch's default
+ *         stream is this stream).  The calls on one context must not overlap:
+ *         switching streams waits for the previous stream.
  * stats:  NULL, or an array of n_images entries; when given, the call waits
  *         for the device and fills it.  With stats NULL and a device image the
  *         call may return before the work is done; synchronise `stream`.

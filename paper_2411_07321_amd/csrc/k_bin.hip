@@ -36,6 +36,7 @@ namespace wsg {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kBatch = 4;          // elements of a track whose loads are issued together
 
 __device__ __forceinline__ unsigned long long order_key(double d) {
     unsigned long long b = (unsigned long long)__double_as_longlong(d);
@@ -209,12 +210,20 @@ __global__ void k_finalize(JobGeom g, ImgState *st) {
     s.w_min = lo;
     s.w_max = hi;
     s.dw = (hi - lo) / (double)g.n_w;
+    s.inv_dw = s.dw > 0.0 ? 1.0 / s.dw : 0.0;
 }
 
-__device__ __forceinline__ int plane_of(double w, double w_min, double dw, int n_w) {
+// Nearest plane: k = min(n_w - 1, floor((w - w_min) / dw)) with the IEEE quotient.
+// The quotient is first formed with the reciprocal; the two can floor differently
+// only when it lies within a few ulps (< 1e-9 here, as it is below 65536) of an
+// integer, and only then is the division done.
+__device__ __forceinline__ int plane_of(double w, double w_min, double dw, double inv_dw, int n_w) {
     if (dw == 0.0) return 0;
-    double t = floor((w - w_min) / dw);
-    int k = (int)t;
+    const double d = w - w_min;
+    double q = d * inv_dw;
+    double f = q - floor(q);
+    if (f < 1e-9 || f > 1.0 - 1e-9) q = d / dw;
+    int k = (int)floor(q);
     return k > n_w - 1 ? n_w - 1 : k;
 }
 
@@ -224,23 +233,28 @@ struct Placed {
     double x, y;
 };
 
-// A valid element inside the w range: its plane, nearest cell and position.
-__device__ __forceinline__ bool place(const JobGeom &g, const ImgState &s, const double *uvw,
-                                      int64_t r, int c, Placed &pl) {
-    double sc = g.chan_scale[c];
-    double w = uvw[3 * r + 2] * sc;
+// A valid element inside the w range: its plane, nearest cell and position, from
+// the row's (u, v, w) as stored and the channel's scale.
+__device__ __forceinline__ bool place_vals(const JobGeom &g, const ImgState &s, double um,
+                                           double vm, double wm, double sc, Placed &pl) {
+    double w = wm * sc;
     if (!(w >= s.w_min && w <= s.w_max)) return false;
-    double u = uvw[3 * r] * sc, v = uvw[3 * r + 1] * sc;
+    double u = um * sc, v = vm * sc;
     pl.x = mesh_coord(u, g.scale, g.half);
     pl.y = mesh_coord(v, g.scale, g.half);
     pl.i0 = (int)floor(pl.x + 0.5);
     pl.j0 = (int)floor(pl.y + 0.5);
-    pl.k = plane_of(w, s.w_min, s.dw, g.n_w);
+    pl.k = plane_of(w, s.w_min, s.dw, s.inv_dw, g.n_w);
     return true;
 }
 
+__device__ __forceinline__ bool place(const JobGeom &g, const ImgState &s, const double *uvw,
+                                      int64_t r, int c, Placed &pl) {
+    return place_vals(g, s, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], g.chan_scale[c], pl);
+}
+
 __device__ __forceinline__ int64_t bin_base(const JobGeom &g, int img, int kl) {
-    return ((int64_t)img * g.n_pl + kl) * (int64_t)g.NT * g.NT;
+    return ((int64_t)img * g.n_pl + kl) << (2 * g.logNT);
 }
 
 // Bins touched by one element's footprint (0, 1, 2 or 4), in a fixed order.
@@ -254,24 +268,6 @@ __device__ __forceinline__ bool has_key(const Keys &ks, uint32_t key) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) f |= (i < ks.n) && ks.k[i] == key;
     return f;
-}
-
-// keys of element (row r, channel c); false if the element is not gridded
-__device__ __forceinline__ bool element_keys(const JobGeom &g, const ImgState &s, const double *uvw,
-                                             const uint8_t *mask, int64_t r, int c, int img,
-                                             Placed &pl, Keys &ks) {
-    ks.n = 0;
-    int64_t e = r * g.n_chan + c;
-    if (!mask[e]) return false;
-    if (!place(g, s, uvw, r, c, pl)) return false;
-    int kl = pl.k - g.plane_lo;
-    if (kl < 0 || kl >= g.n_pl) return false;
-    int64_t base = bin_base(g, img, kl);
-    int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
-    int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) ks.k[ks.n++] = (uint32_t)(base + (int64_t)ty * g.NT + tx);
-    return true;
 }
 
 // (channel, baseline, time block) of a track thread
@@ -314,41 +310,67 @@ __global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__r
         const ImgState s = st[img];
         uint32_t okey[4] = {0, 0, 0, 0};
         uint32_t ocnt[4] = {0, 0, 0, 0};
-        for (int64_t t = tr.t0; t < tr.t1; ++t) {
-            int64_t r = t * g.P + tr.b;
-            if (r >= g.n_rows) break;
+        const double sc = g.chan_scale[tr.c];
+        int64_t t_end = tr.t1;
+        if (t_end > tr.t0 && (t_end - 1) * g.P + tr.b >= g.n_rows) t_end = (g.n_rows - 1 - tr.b) / g.P + 1;
+        for (int64_t t0b = tr.t0; t0b < t_end; t0b += kBatch) {
+        // the loads of kBatch elements are issued together
+        uint8_t mb[kBatch];
+        double ub[kBatch], vb[kBatch], wb[kBatch], wtb[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int64_t t = min(t0b + j, t_end - 1);
+            const int64_t r = t * g.P + tr.b;
+            const int64_t e = r * g.n_chan + tr.c;
+            mb[j] = (t0b + j < t_end) ? mask[e] : 0;
+            ub[j] = uvw[3 * r];
+            vb[j] = uvw[3 * r + 1];
+            wb[j] = uvw[3 * r + 2];
+            wtb[j] = wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
+        }
+        for (int j = 0; j < kBatch && t0b + j < t_end; ++j) {
             Placed pl;
             Keys ks;
-            int64_t e = r * g.n_chan + tr.c;
-            if (mask[e] && place(g, s, uvw, r, tr.c, pl)) {
+            ks.n = 0;
+            const bool in_range = place_vals(g, s, ub[j], vb[j], wb[j], sc, pl);
+            if (mb[j] && in_range) {
                 ++nu;
-                sw += wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
+                sw += wtb[j];
+                int kl = pl.k - g.plane_lo;
+                if (kl >= 0 && kl < g.n_pl) {
+                    int64_t base = bin_base(g, img, kl);
+                    int tx0 = (pl.i0 - g.h) >> g.logT, tx1 = (pl.i0 + g.h) >> g.logT;
+                    int ty0 = (pl.j0 - g.h) >> g.logT, ty1 = (pl.j0 + g.h) >> g.logT;
+                    for (int ty = ty0; ty <= ty1; ++ty)
+                        for (int tx = tx0; tx <= tx1; ++tx)
+                            ks.k[ks.n++] = (uint32_t)(base + (int64_t)ty * g.NT + tx);
+                }
             }
-            element_keys(g, s, uvw, mask, r, tr.c, img, pl, ks);
             // close runs whose bin this element does not touch
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (ocnt[j] && !has_key(ks, okey[j])) {
-                    atomicAdd(&counts[okey[j]], ocnt[j]);
-                    ocnt[j] = 0;
+            for (int q = 0; q < 4; ++q)
+                if (ocnt[q] && !has_key(ks, okey[q])) {
+                    atomicAdd(&counts[okey[q]], ocnt[q]);
+                    ocnt[q] = 0;
                 }
             // extend or open runs
             for (int i = 0; i < ks.n; ++i) {
                 bool done = false;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (!done && ocnt[j] && okey[j] == ks.k[i]) {
-                        ++ocnt[j];
+                for (int q = 0; q < 4; ++q)
+                    if (!done && ocnt[q] && okey[q] == ks.k[i]) {
+                        ++ocnt[q];
                         done = true;
                     }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (!done && ocnt[j] == 0) {
-                        okey[j] = ks.k[i];
-                        ocnt[j] = 1;
+                for (int q = 0; q < 4; ++q)
+                    if (!done && ocnt[q] == 0) {
+                        okey[q] = ks.k[i];
+                        ocnt[q] = 1;
                         done = true;
                     }
             }
+        }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -380,8 +402,8 @@ template <typename VT>
 __device__ __forceinline__ void write_record(void *records, uint32_t slot, const JobGeom &g,
                                              const Placed &pl, uint32_t key, double vr, double vi,
                                              double wt) {
-    uint32_t t = key % (uint32_t)(g.NT * g.NT);
-    int ty = (int)(t / g.NT), tx = (int)(t % g.NT);
+    uint32_t t = key & ((1u << (2 * g.logNT)) - 1u);
+    int ty = (int)(t >> g.logNT), tx = (int)(t & (uint32_t)(g.NT - 1));
     double fx = pl.x - (double)pl.i0;
     double fy = pl.y - (double)pl.j0;
     if constexpr (sizeof(VT) == 8) {
@@ -390,15 +412,15 @@ __device__ __forceinline__ void write_record(void *records, uint32_t slot, const
         rec.fy = fy;
         rec.re = wt * vr;
         rec.im = wt * vi;
-        rec.li = pl.i0 - tx * g.T;
-        rec.lj = pl.j0 - ty * g.T;
+        rec.li = pl.i0 - (tx << g.logT);
+        rec.lj = pl.j0 - (ty << g.logT);
         ((RecF64 *)records)[slot] = rec;
     } else {
         uint32_t qx = (uint32_t)fmin((fx + 0.5) * 16777216.0 + 0.5, 16777215.0);
         uint32_t qy = (uint32_t)fmin((fy + 0.5) * 16777216.0 + 0.5, 16777215.0);
         RecF32 rec;
-        rec.px = ((uint32_t)(pl.i0 - tx * g.T + g.h) << kFracBits) | qx;
-        rec.py = ((uint32_t)(pl.j0 - ty * g.T + g.h) << kFracBits) | qy;
+        rec.px = ((uint32_t)(pl.i0 - (tx << g.logT) + g.h) << kFracBits) | qx;
+        rec.py = ((uint32_t)(pl.j0 - (ty << g.logT) + g.h) << kFracBits) | qy;
         rec.re = (float)wt * (float)vr;
         rec.im = (float)wt * (float)vi;
         ((RecF32 *)records)[slot] = rec;
@@ -419,18 +441,12 @@ constexpr uint32_t kNoKey = 0xffffffffu;
 
 // base bin (lowest tile) in bits 0..26, bit 27: also the tile to the right, bit 28:
 // also the tile above
-__device__ __forceinline__ uint32_t pack_keys(const JobGeom &g, const ImgState &s,
-                                              const double *uvw, const uint8_t *mask, int64_t r,
-                                              int c, int img) {
-    int64_t e = r * g.n_chan + c;
-    if (!mask[e]) return kNoKey;
-    Placed pl;
-    if (!place(g, s, uvw, r, c, pl)) return kNoKey;
+__device__ __forceinline__ uint32_t pack_placed(const JobGeom &g, int img, const Placed &pl) {
     int kl = pl.k - g.plane_lo;
     if (kl < 0 || kl >= g.n_pl) return kNoKey;
-    int tx0 = (pl.i0 - g.h) / g.T, tx1 = (pl.i0 + g.h) / g.T;
-    int ty0 = (pl.j0 - g.h) / g.T, ty1 = (pl.j0 + g.h) / g.T;
-    uint32_t base = (uint32_t)(bin_base(g, img, kl) + (int64_t)ty0 * g.NT + tx0);
+    int tx0 = (pl.i0 - g.h) >> g.logT, tx1 = (pl.i0 + g.h) >> g.logT;
+    int ty0 = (pl.j0 - g.h) >> g.logT, ty1 = (pl.j0 + g.h) >> g.logT;
+    uint32_t base = (uint32_t)(bin_base(g, img, kl) + ((int64_t)ty0 << g.logNT) + tx0);
     return base | ((uint32_t)(tx1 > tx0) << 27) | ((uint32_t)(ty1 > ty0) << 28);
 }
 
@@ -453,8 +469,9 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
                                                           const ImgState *st, uint32_t *cursor,
                                                           void *__restrict__ records, uint32_t capacity,
                                                           uint32_t *overflow) {
+    // one word per element: the packed bins (phase 1), then, in place, the 4 x
+    // 8-bit run lengths (phase 2); phase 3 recomputes the bins
     __shared__ uint32_t s_key[kScatL][kScatThreads];
-    __shared__ uint32_t s_len[kScatL][kScatThreads];   // 4 x 8-bit run lengths
     const int lane = threadIdx.x;
     // track of this thread: blocks of kScatL time slices
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
@@ -474,11 +491,29 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
             ++nt;
         }
     }
-    // phase 1: packed bins
-    for (int k = 0; k < kScatL; ++k) {
-        uint32_t pk = kNoKey;
-        if (k < nt) pk = pack_keys(g, s, uvw, mask, (t0 + k) * g.P + b, c, img);
-        s_key[k][lane] = pk;
+    const double sc = g.chan_scale[c];
+    // phase 1: packed bins (the loads of kBatch elements are issued together)
+    for (int k0 = 0; k0 < kScatL; k0 += kBatch) {
+        uint8_t m[kBatch];
+        double u[kBatch], v[kBatch], w[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int k = k0 + j;
+            const bool in = k < nt;
+            // clamped to a real row so that no load can leave the buffers
+            const int64_t r = min((t0 + min(k, max(nt - 1, 0))) * g.P + b, g.n_rows - 1);
+            m[j] = in ? mask[r * g.n_chan + c] : 0;
+            u[j] = in ? uvw[3 * r] : 0.0;
+            v[j] = in ? uvw[3 * r + 1] : 0.0;
+            w[j] = in ? uvw[3 * r + 2] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            Placed pl;
+            uint32_t pk = kNoKey;
+            if (m[j] && place_vals(g, s, u[j], v[j], w[j], sc, pl)) pk = pack_placed(g, img, pl);
+            s_key[k0 + j][lane] = pk;
+        }
     }
     // phase 2: run lengths, backwards; `open` holds the bins of element k+1 with the
     // length of their run from k+1 on
@@ -502,7 +537,7 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
                 nlen[i] = len;
                 packed |= min(len, 255u) << (8 * i);
             }
-            s_len[k][lane] = packed;
+            s_key[k][lane] = packed;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 okey[i] = nkey[i];
@@ -514,18 +549,29 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
     uint32_t okey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
     uint32_t onext[4] = {0, 0, 0, 0};
     uint32_t orem[4] = {0, 0, 0, 0};
-    for (int k = 0; k < nt; ++k) {
-        uint32_t pk = s_key[k][lane];
+    for (int k0 = 0; k0 < nt; k0 += kBatch) {
+        uint8_t m[kBatch];
+        double u[kBatch], v[kBatch], w[kBatch], vr[kBatch], vi[kBatch], wt[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int k = min(k0 + j, nt - 1);
+            const int64_t r = (t0 + k) * g.P + b;
+            const int64_t e = r * g.n_chan + c;
+            m[j] = (k0 + j < nt) ? mask[e] : 0;
+            u[j] = uvw[3 * r];
+            v[j] = uvw[3 * r + 1];
+            w[j] = uvw[3 * r + 2];
+            ElemIO<VT, VT>::load(vis, wts, e, vr[j], vi[j], wt[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+        Placed pl;
+        if (!m[j] || !place_vals(g, s, u[j], v[j], w[j], sc, pl)) continue;
+        const uint32_t pk = pack_placed(g, img, pl);
         if (pk == kNoKey) continue;
         Keys ks;
         unpack_keys(pk, g.NT, ks);
-        const uint32_t lens = s_len[k][lane];
-        const int64_t r = (t0 + k) * g.P + b;
-        Placed pl;
-        place(g, s, uvw, r, c, pl);
-        const int64_t e = r * g.n_chan + c;
-        double vr, vi, wt;
-        ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
+        const uint32_t lens = s_key[k0 + j][lane];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (i >= ks.n) continue;
@@ -555,9 +601,10 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
             // the counting pass sized the buffer; a slot beyond it would mean the two
             // passes disagree: never write there, report it instead
             if (slot < capacity)
-                write_record<VT>(records, slot, g, pl, key, vr, vi, wt);
+                write_record<VT>(records, slot, g, pl, key, vr[j], vi[j], wt[j]);
             else
                 atomicAdd(overflow, 1u);
+        }
         }
     }
 }

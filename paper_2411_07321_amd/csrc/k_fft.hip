@@ -216,6 +216,16 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
 }
 
 // ---------------------------------------------------------------- pass 2
+// Workgroups are dealt to the 8 XCDs round robin.  Strip s of pass 2 goes to the
+// workgroup that makes consecutive strips run side by side on one XCD, so two
+// strips whose reads share 128-byte lines (B x NTR elements of 8 bytes = 64 bytes
+// each) meet in that XCD's L2 and every line is fetched from HBM once.
+__device__ __forceinline__ int xcd_strip(int bid, int n_strips) {
+    constexpr int kXcd = 8;
+    if (n_strips % kXcd) return bid;
+    return (bid % kXcd) * (n_strips / kXcd) + bid / kXcd;
+}
+
 // thread -> (t_lo, r, t_hi): reads of 16 consecutive lanes form one 128-byte run
 template <typename T, int N>
 struct P2Index {
@@ -249,7 +259,8 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C
     constexpr int P = SH::P, NTR = SH::NTR;
     __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
     P2Index<T, N> ix(threadIdx.x);
-    const int bcol = blockIdx.x * NTR + ix.r;
+    const int strip = xcd_strip(blockIdx.x, N / NTR);
+    const int bcol = strip * NTR + ix.r;
     const C2<T> *Y = in + (size_t)blockIdx.y * N * N;
     C2<T> v[E];
     load_blocked<T, N>(v, Y, ix.t, bcol);
@@ -265,7 +276,7 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C
         st[ix.r * N + ap] = z;
     }
     __syncthreads();
-    C2<T> *Z = out + (size_t)blockIdx.y * N * N + (size_t)blockIdx.x * NTR * N;
+    C2<T> *Z = out + (size_t)blockIdx.y * N * N + (size_t)strip * NTR * N;
     for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) Z[i] = st[i];
 }
 
@@ -364,7 +375,8 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
     __shared__ PR s_nm1[NTR * N];
     P2Index<T, N> ix(threadIdx.x);
     const int img = blockIdx.y;
-    const int q = blockIdx.x * NTR + ix.r;            // image row handled by this thread
+    const int strip = xcd_strip(blockIdx.x, N / NTR);
+    const int q = strip * NTR + ix.r;                 // image row handled by this thread
     const ImgState &st = a.st[img];
     const double m = (double)(q - N / 2) * a.cell;
 #pragma unroll
@@ -411,7 +423,7 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
         stg[ix.r * N + p] = d;
     }
     __syncthreads();
-    double *D = image + (size_t)img * N * N + (size_t)blockIdx.x * NTR * N;
+    double *D = image + (size_t)img * N * N + (size_t)strip * NTR * N;
     for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = stg[i];
 }
 

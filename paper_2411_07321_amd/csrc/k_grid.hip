@@ -18,7 +18,7 @@ namespace wsg {
 namespace {
 
 constexpr int kGridThreads = 256;
-constexpr int kRunCap = 8;
+constexpr int kRunCap = 16;
 
 template <typename T>
 struct RecTraits;
@@ -35,7 +35,12 @@ struct RecTraits<float> {
         re = r.re;
         im = r.im;
     }
-    static __device__ __forceinline__ float gauss(float d, float inv2s2) { return expf(-d * d * inv2s2); }
+    // exp(-d^2/(2 sigma^2)) as one hardware exp2 of -(d^2) * log2(e)/(2 sigma^2); the
+    // argument's rounding gives a relative error of ~3e-7, far below the tolerance of
+    // the FP32 mesh
+    static __device__ __forceinline__ float gauss(float d, float inv2s2) {
+        return __builtin_amdgcn_exp2f(-(d * d) * (inv2s2 * 1.4426950408889634f));
+    }
 };
 
 template <>
@@ -81,6 +86,8 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // such records in registers and adds them to the LDS tile only when the cell
 // changes, or after kRunCap records (so an FP32 register sum never holds more
 // than kRunCap terms); otherwise every record is added to the tile directly.
+// (A variant that adds the footprint with one base address when it lies inside
+// the tile measured slower: the burst of 98 back-to-back FP64 LDS atomics.)
 template <typename T, int TT, int SS, bool ACC>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,

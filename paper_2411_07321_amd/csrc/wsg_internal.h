@@ -59,8 +59,8 @@ struct ImgState {
     unsigned long long n_used;
     double sum_w;
     double w_min, w_max, dw;                 // plane geometry used by the job
+    double inv_dw;                           // 1/dw (0 when dw = 0)
     double inv_norm;                         // 1/sum_w (or 1, or 0 for an empty image)
-    int32_t pad[2];
 };
 
 // Everything the binning and gridding kernels need about one job.
@@ -72,7 +72,8 @@ struct JobGeom {
     int32_t n_w;            // planes over [w_min, w_max]
     int32_t plane_lo, n_pl; // planes imaged: [plane_lo, plane_lo + n_pl)
     int32_t S, h;
-    int32_t T, NT;          // tile edge and tiles per axis
+    int32_t T, NT;          // tile edge and tiles per axis (powers of two)
+    int32_t logT, logNT;
     double scale;           // N * cell_rad
     double half;            // N / 2
     double sigma;

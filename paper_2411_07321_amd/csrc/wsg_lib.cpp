@@ -60,7 +60,8 @@ struct wsg_ctx {
     // stage timing: events recorded at the stage boundaries of wsg_image
     int timing = 0;
     hipEvent_t tev[8] = {};
-    hipStream_t last_stream = nullptr;   // stream of the previous call (arena users)
+    hipStream_t last_stream = nullptr;   // stream of the previous call (arena users);
+    bool has_last = false;               // NULL is a real stream (the null stream)
 };
 
 namespace {
@@ -241,7 +242,7 @@ wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, size_t other_in_us
     if (ctx->budget && bytes + other_in_use > ctx->budget)
         return fail(ctx, WSG_ENOMEM, "workspace of " + std::to_string(bytes + other_in_use) +
                                          " bytes exceeds the context budget");
-    if (ctx->last_stream && ctx->last_stream != s) WSG_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+    if (ctx->has_last && ctx->last_stream != s) WSG_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
     if (a.ptr) {
         WSG_HIP(ctx, hipFreeAsync(a.ptr, s));
         a.ptr = nullptr;
@@ -381,9 +382,12 @@ void mark(wsg_ctx *ctx, int i, hipStream_t s) {
 }
 
 hipStream_t pick_stream(wsg_ctx *ctx, void *stream) {
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-    if (ctx->last_stream && ctx->last_stream != s) (void)hipStreamSynchronize(ctx->last_stream);
+    // NULL is HIP's null stream, as everywhere in HIP; the context's own stream is
+    // passed explicitly (wsg_context_stream)
+    hipStream_t s = (hipStream_t)stream;
+    if (ctx->has_last && ctx->last_stream != s) (void)hipStreamSynchronize(ctx->last_stream);
     ctx->last_stream = s;
+    ctx->has_last = true;
     return s;
 }
 
@@ -451,6 +455,10 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     g.h = (pl.S - 1) / 2;
     g.T = pl.T;
     g.NT = pl.NT;
+    g.logT = 0;
+    while ((1 << g.logT) < g.T) ++g.logT;
+    g.logNT = 0;
+    while ((1 << g.logNT) < g.NT) ++g.logNT;
     g.scale = (double)pl.N * p->cell_rad;
     g.half = 0.5 * (double)pl.N;
     g.sigma = p->kernel_sigma;
@@ -644,7 +652,7 @@ void wsg_destroy(wsg_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
+    if (ctx->has_last && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
     if (ctx->fixed.ptr) (void)hipFreeAsync(ctx->fixed.ptr, ctx->stream);
     if (ctx->dyn.ptr) (void)hipFreeAsync(ctx->dyn.ptr, ctx->stream);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
@@ -672,6 +680,8 @@ const char *wsg_strerror(wsg_status s) {
     }
 }
 
+void *wsg_context_stream(const wsg_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
 const char *wsg_last_error(const wsg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
 
 wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes) {
@@ -683,7 +693,7 @@ wsg_status wsg_set_budget(wsg_ctx *ctx, uint64_t bytes) {
 wsg_status wsg_trim(wsg_ctx *ctx) {
     if (!ctx) return WSG_EINVAL;
     WSG_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = ctx->last_stream ? ctx->last_stream : ctx->stream;
+    hipStream_t s = ctx->has_last ? ctx->last_stream : ctx->stream;
     for (Arena *a : {&ctx->fixed, &ctx->dyn}) {
         if (a->ptr) WSG_HIP(ctx, hipFreeAsync(a->ptr, s));
         a->ptr = nullptr;

@@ -131,7 +131,7 @@ struct wsg_server {
             wsg_stats st{};
             int n_img = wsg_n_images(&j->p, &j->v);
             std::vector<wsg_stats> all((size_t)std::max(1, n_img));
-            wsg_status rc = wsg_image(s.ctx, &j->p, &j->v, j->image, j->image_mem, nullptr, all.data());
+            wsg_status rc = wsg_image(s.ctx, &j->p, &j->v, j->image, j->image_mem, wsg_context_stream(s.ctx), all.data());
             if (rc == WSG_OK) st = all[0];
             double t_end = now_s();
             {

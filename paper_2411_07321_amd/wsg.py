@@ -27,7 +27,7 @@ SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_s
            "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image",
            "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune",
            "wsg_server_create", "wsg_server_destroy", "wsg_server_submit", "wsg_server_poll",
-           "wsg_server_wait", "wsg_server_memory", "wsg_trim")
+           "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream")
 
 
 class WsgError(RuntimeError):
@@ -122,6 +122,8 @@ def load() -> ctypes.CDLL:
         lib.wsg_server_memory.argtypes = [P, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]
         lib.wsg_trim.argtypes = [P]
+        lib.wsg_context_stream.argtypes = [P]
+        lib.wsg_context_stream.restype = P
         for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check",
                      "wsg_footprint", "wsg_image", "wsg_stage_grid", "wsg_stage_fft",
                      "wsg_stage_wcorrect", "wsg_autotune", "wsg_server_create",
@@ -208,7 +210,11 @@ def _stream_of(x, stream):
 
 
 class Context:
-    """One library context on one HIP device (owns workspace and its own stream)."""
+    """One library context on one HIP device (owns workspace and its own stream).
+
+    Calls run on the stream given, else on torch's current stream of the output
+    tensor, else (host outputs) on HIP's null stream; `ctx.stream` is the
+    context's own stream."""
 
     def __init__(self, device: int = 0):
         lib = load()
@@ -240,6 +246,11 @@ class Context:
         if st != OK:
             detail = load().wsg_last_error(self._h).decode()
             raise WsgError(st, f"{what}: {strerror(st)} ({detail})")
+
+    @property
+    def stream(self) -> int:
+        """The context's own hipStream_t, as an integer handle."""
+        return load().wsg_context_stream(self._h)
 
     def set_budget(self, nbytes: int):
         self._check(load().wsg_set_budget(self._h, int(nbytes)), "wsg_set_budget")
