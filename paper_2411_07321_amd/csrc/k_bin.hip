@@ -649,7 +649,8 @@ __global__ void k_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n, uin
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t c = counts[i];
-    nchunk[i] = c == 0 ? 1u : (c + chunk - 1) / chunk;
+    // an empty bin has no work item: its tile is cleared by the zero pass
+    nchunk[i] = (c + chunk - 1) / chunk;
 }
 
 __global__ void k_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,

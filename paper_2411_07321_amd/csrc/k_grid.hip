@@ -1,13 +1,14 @@
 // Convolutional gridding (Eq. 3 of the paper) of binned records.
 //
-// One work item = one (image, plane, tile) bin, or one chunk of a bin that
-// holds more than `chunk` records.  The workgroup accumulates its records into
+// One work item = one non-empty (image, plane, tile) bin, or one chunk of a bin
+// that holds more than `chunk` records.  The workgroup accumulates its records into
 // an LDS copy of the T x T tile (every record adds W V G(i0+a-x) G(j0+b-y) to
 // the cells of its S x S footprint that lie inside the tile), then writes the
 // tile to the plane stack with coalesced stores.  A tile covered by a single
 // chunk is stored (every cell of the stack is written exactly once, so the
 // stack needs no clearing); the chunks of a split bin add their partial tiles
-// with global atomics into a tile that k_zero_split cleared.
+// with global atomics into a tile that k_zero_tiles cleared.  Empty bins get no
+// work item: k_zero_tiles writes their tiles with plain stores, without LDS.
 //
 // The kernel G(d) = exp(-d^2 / (2 sigma^2)) is separable: 2*S exponentials per
 // record, S^2 multiply-adds.
@@ -19,6 +20,7 @@ namespace {
 
 constexpr int kGridThreads = 256;
 constexpr int kRunCap = 16;
+constexpr int kFlushLanes = 32;
 
 template <typename T>
 struct RecTraits;
@@ -151,6 +153,61 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 ai[bb][a] = T(0);
             }
     }
+    if constexpr (ACC) {
+        // A lane whose next record starts a new run (another cell, or kRunCap records
+        // summed) parks until the wave flushes: the wave adds the register sums of
+        // all parked lanes to the tile together once kFlushLanes lanes are parked,
+        // or when no lane can go on, so each pass of 2 S^2 LDS atomics serves many
+        // lanes rather than the one or two whose cell just changed.
+        uint32_t pos = q0;
+        bool pend = false;
+        RecF32 nx{};
+        if (pos < q1) nx = rec[pos];
+        for (;;) {
+            if (pos < q1 && !pend) {
+                const int li = (int)(nx.px >> kFracBits) - H;
+                const int lj = (int)(nx.py >> kFracBits) - H;
+                if (run == 0 || (li == cli && lj == clj && run < kRunCap)) {
+                    int li2, lj2;
+                    T fx, fy, re, im;
+                    RecTraits<T>::decode(nx, H, li2, lj2, fx, fy, re, im);
+                    ++pos;
+                    if (pos < q1) nx = rec[pos];
+                    T gx[SS], gy[SS];
+#pragma unroll
+                    for (int a = 0; a < SS; ++a) {
+                        gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
+                        gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
+                    }
+#pragma unroll
+                    for (int bb = 0; bb < SS; ++bb) {
+                        T wr = re * gy[bb], wi = im * gy[bb];
+#pragma unroll
+                        for (int a = 0; a < SS; ++a) {
+                            ar[bb][a] += wr * gx[a];
+                            ai[bb][a] += wi * gx[a];
+                        }
+                    }
+                    cli = li;
+                    clj = lj;
+                    ++run;
+                    if (pos == q1) pend = true;
+                } else {
+                    pend = true;
+                }
+            }
+            const unsigned long long pm = __ballot(pend);
+            const unsigned long long lm = __ballot(pos < q1 && !pend);
+            if (pm == 0 && lm == 0) break;
+            if (__popcll(pm) >= kFlushLanes || lm == 0) {
+                if (pend) {
+                    flush(cli, clj);
+                    run = 0;
+                    pend = false;
+                }
+            }
+        }
+    } else {
     for (uint32_t ri = q0; ri < q1; ++ri) {
         int li, lj;
         T fx, fy, re, im;
@@ -161,41 +218,20 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
             gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
         }
-        if constexpr (ACC) {
-            if (li != cli || lj != clj || run == kRunCap) {
-                if (cli != INT32_MIN) flush(cli, clj);
-                cli = li;
-                clj = lj;
-                run = 0;
-            }
-            ++run;
 #pragma unroll
-            for (int bb = 0; bb < SS; ++bb) {
-                T wr = re * gy[bb], wi = im * gy[bb];
+        for (int bb = 0; bb < SS; ++bb) {
+            int j = lj + bb - H;
+            if (j < 0 || j >= TT) continue;
+            T wr = re * gy[bb], wi = im * gy[bb];
 #pragma unroll
-                for (int a = 0; a < SS; ++a) {
-                    ar[bb][a] += wr * gx[a];
-                    ai[bb][a] += wi * gx[a];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int bb = 0; bb < SS; ++bb) {
-                int j = lj + bb - H;
-                if (j < 0 || j >= TT) continue;
-                T wr = re * gy[bb], wi = im * gy[bb];
-#pragma unroll
-                for (int a = 0; a < SS; ++a) {
-                    int i = li + a - H;
-                    if (i < 0 || i >= TT) continue;
-                    atomicAdd(&s_re[j * TP + i], (double)(wr * gx[a]));
-                    atomicAdd(&s_im[j * TP + i], (double)(wi * gx[a]));
-                }
+            for (int a = 0; a < SS; ++a) {
+                int i = li + a - H;
+                if (i < 0 || i >= TT) continue;
+                atomicAdd(&s_re[j * TP + i], (double)(wr * gx[a]));
+                atomicAdd(&s_im[j * TP + i], (double)(wi * gx[a]));
             }
         }
     }
-    if constexpr (ACC) {
-        if (cli != INT32_MIN) flush(cli, clj);
     }
     __syncthreads();
 
@@ -219,11 +255,12 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
 }
 
 template <typename T, int TT>
-__global__ __launch_bounds__(kGridThreads) void k_zero_split(JobGeom g, const uint32_t *__restrict__ counts,
+__global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const uint32_t *__restrict__ counts,
                                                              uint32_t chunk, C2<T> *__restrict__ grid,
                                                              int transposed) {
     const uint32_t b = blockIdx.x;
-    if (counts[b] <= chunk) return;
+    const uint32_t c = counts[b];
+    if (c != 0 && c <= chunk) return;
     int img, kl, ty, tx;
     bin_coords(g, b, img, kl, ty, tx);
     const int gi0 = tx * TT, gj0 = ty * TT;
@@ -281,16 +318,16 @@ void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, voi
     C2<T> *gp = (C2<T> *)grid;
     int tr = transposed ? 1 : 0;
     switch (g.T) {
-    case 16: k_zero_split<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
-    case 32: k_zero_split<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
-    case 64: k_zero_split<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 16: k_zero_tiles<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 32: k_zero_tiles<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 64: k_zero_tiles<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
     default: break;
     }
 }
 
 }  // namespace
 
-void launch_zero_split(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
+void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
                        void *grid, bool transposed, hipStream_t s) {
     if (f64)
         dispatch_zero<double>(g, counts, chunk, grid, transposed, s);

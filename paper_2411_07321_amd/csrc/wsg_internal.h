@@ -114,7 +114,7 @@ void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]
 // transposed: store plane k as [i][j] (u index slow) instead of [j][i]
-void launch_zero_split(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
+void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
                        void *grid, bool transposed, hipStream_t s);
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
                  const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,

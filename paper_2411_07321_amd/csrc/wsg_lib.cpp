@@ -549,7 +549,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
 }
 
 wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, hipStream_t s) {
-    launch_zero_split(b.g, b.pl.f64, b.counts, kChunk, grid, transposed, s);
+    launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, grid, transposed, s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
                 b.records, grid, transposed, s);
     WSG_HIP(ctx, hipGetLastError());
