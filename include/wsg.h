@@ -195,9 +195,10 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
 /* ---------------------------------------------------------------------------
  * Tuning
  * ------------------------------------------------------------------------- */
-/* Time the binning tile sizes on this job's data and store the best per
- * (N, N_w, S, precision, visibility-count decade) in the context (and in the
- * text file cache_path if not NULL).  *best_tile receives the choice. */
+/* Time the whole imaging path at each binning tile size (16, 32, 64) on this
+ * job's data, on the context's own stream, and store the fastest per (N, N_w, S,
+ * precision, visibility-count decade) in the context (and in the text file
+ * cache_path if not NULL).  *best_tile receives the choice.  Waits for the device. */
 wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
                         const char *cache_path, int32_t *best_tile);
 

@@ -20,6 +20,10 @@
 // (i -> p) while it walks the planes of a strip of image rows q, multiplies by
 // the phase screen e^{2 pi i w_k (n-1)} and accumulates Re in FP64 registers;
 // the strip of the image is written once, with the post factors applied.
+//
+// The imaging path passes the tile occupancy of the stack: pass 1 then reads
+// only the tiles the gridder wrote and skips rows of empty tile-rows altogether,
+// and pass 2 skips those rows and planes without records.
 #include "wsg_internal.h"
 
 #include <type_traits>
@@ -187,7 +191,8 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
 // ---------------------------------------------------------------- pass 1
 template <typename T, int N>
 __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restrict__ planes,
-                                                                 const C2<T> *__restrict__ tw) {
+                                                                 const C2<T> *__restrict__ tw,
+                                                                 Occupancy occ) {
     using SH = Shape<T, N>;
     constexpr int B = SH::B, P = SH::P, NTR = SH::NTR;
     __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
@@ -197,12 +202,31 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
     const int r_hi = tid / (B * P);
     const int r = r_hi * B + r_lo;
     const int a = blockIdx.x * NTR + r;
-    C2<T> *X = planes + (size_t)blockIdx.y * N * N;
+    const int pi = blockIdx.y;
+    C2<T> *X = planes + (size_t)pi * N * N;
+    // sparse stack: a row of an empty tile-row is neither read nor written (pass 2
+    // skips it too), and an empty tile of a live row reads as zero
+    bool row_live = true;
+    uint32_t on = 0xffffu;
+    if (occ.rows) {
+        const int NT = N >> occ.logT;
+        const int txr = a >> occ.logT;
+        const uint32_t lm = occ.live1[((size_t)pi * NT + txr) * P + t];
+        const uint64_t *rows = occ.rows + (size_t)pi * occ.nw;
+        const int a0 = blockIdx.x * NTR;
+        bool any = false;
+        for (int tx = a0 >> occ.logT; tx <= (a0 + NTR - 1) >> occ.logT; ++tx)
+            any = any || ((rows[tx >> 6] >> (tx & 63)) & 1ull);
+        if (!any) return;   // the same for every thread of the workgroup
+        row_live = (lm >> 16) & 1u;
+        on = lm & 0xffffu;
+    }
     C2<T> v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         int b = t + m * P;
-        C2<T> z = X[(size_t)a * N + b];
+        C2<T> z = C2<T>{T(0), T(0)};
+        if ((on >> m) & 1u) z = X[(size_t)a * N + b];
         if ((a + b) & 1) z = C2<T>{-z.x, -z.y};
         v[m] = z;
     }
@@ -211,8 +235,10 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
     fft_line<T, N>(v, lre, lim, t, tw);
     __syncthreads();   // every load of this region is done before it is overwritten
     C2<T> *Y = X + (size_t)(a / B) * B * N;
+    if (row_live) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) Y[(size_t)(t + s * P) * B + r_lo] = v[s];
+        for (int s = 0; s < E; ++s) Y[(size_t)(t + s * P) * B + r_lo] = v[s];
+    }
 }
 
 // ---------------------------------------------------------------- pass 2
@@ -248,6 +274,24 @@ __device__ __forceinline__ void load_blocked(C2<T> *v, const C2<T> *__restrict__
     for (int m = 0; m < E; ++m) {
         int a = t + m * P;
         v[m] = Y[((size_t)(a / B) * N + bcol) * B + (a % B)];
+    }
+}
+
+// the same for the points m whose bit is set in `live`; the others read as zero.
+// Their loads go to `dummy` (one cached line) instead of being branched around,
+// so that all E loads are issued together.
+template <typename T, int N>
+__device__ __forceinline__ void load_blocked_live(C2<T> *v, const C2<T> *__restrict__ Y, int t,
+                                                  int bcol, uint32_t live,
+                                                  const C2<T> *__restrict__ dummy) {
+    constexpr int B = Shape<T, N>::B, P = N / E;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int a = t + m * P;
+        const bool on = (live >> m) & 1u;
+        const C2<T> *src = on ? Y + ((size_t)(a / B) * N + bcol) * B + (a % B) : dummy;
+        const C2<T> z = *src;
+        v[m] = on ? z : C2<T>{T(0), T(0)};
     }
 }
 
@@ -389,14 +433,26 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
 #pragma unroll
     for (int s = 0; s < E; ++s) acc[s] = 0.0;
     const double w_min = st.w_min, dw = st.dw;
+    uint32_t live_next = 0xffffu;
+    if (a.occ.live2 && a.n_pl > 0) live_next = a.occ.live2[(size_t)img * a.n_pl * P + ix.t];
     T *lre = lds + (size_t)ix.r * SH::NPAD;
     T *lim = lds + (size_t)(NTR + ix.r) * SH::NPAD;
     for (int kl = 0; kl < a.n_pl; ++kl) {
         const int k = a.plane_lo + kl;
         const double wk = (dw == 0.0) ? w_min : w_min + ((double)k + 0.5) * dw;
-        const C2<T> *Y = stack + ((size_t)img * a.n_pl + kl) * N * N;
+        const size_t pi = (size_t)img * a.n_pl + kl;
+        const C2<T> *Y = stack + pi * N * N;
+        // points of rows that pass 1 wrote (all of them for a dense stack; none of a
+        // plane without records, whose transform then only adds zeros).  The mask
+        // of the next plane is fetched now, so that the loads of this iteration
+        // wait on nothing.
+        uint32_t live = 0xffffu;
+        if (a.occ.live2) {
+            live = live_next;
+            if (kl + 1 < a.n_pl) live_next = a.occ.live2[(pi + 1) * P + ix.t];
+        }
         C2<T> v[E];
-        load_blocked<T, N>(v, Y, ix.t, q);
+        load_blocked_live<T, N>(v, Y, ix.t, q, live, tw);
         fft_line<T, N>(v, lre, lim, ix.t, tw);
         // (n - 1 comes from LDS: holding it for all E pixels in registers would not
         // fit next to the points and the FP64 sums)
@@ -471,10 +527,10 @@ __global__ __launch_bounds__(256) void k_transpose(const C2<T> *__restrict__ in,
 }
 
 template <typename T, int N>
-void pass1_n(void *planes, int64_t n_planes, const void *tw, hipStream_t s) {
+void pass1_n(void *planes, int64_t n_planes, const void *tw, const Occupancy &occ, hipStream_t s) {
     using SH = Shape<T, N>;
     dim3 grid(N / SH::NTR, (unsigned)n_planes);
-    k_pass1<T, N><<<grid, SH::THREADS, 0, s>>>((C2<T> *)planes, (const C2<T> *)tw);
+    k_pass1<T, N><<<grid, SH::THREADS, 0, s>>>((C2<T> *)planes, (const C2<T> *)tw, occ);
 }
 
 template <typename T, int N>
@@ -501,12 +557,12 @@ void pass2_wcorr_n(const WcorrArgs &a, const void *stack, const void *tw, double
 int fft_block_rows(bool f64) { return f64 ? BlockRows<double>::value : BlockRows<float>::value; }
 
 void launch_fft_pass1(int N, bool f64, void *planes, int64_t n_planes, const void *twiddle,
-                      hipStream_t s) {
+                      const Occupancy &occ, hipStream_t s) {
     if (n_planes <= 0) return;
 #define X(n)                                                                     \
     case n:                                                                      \
-        if (f64) pass1_n<double, n>(planes, n_planes, twiddle, s);               \
-        else pass1_n<float, n>(planes, n_planes, twiddle, s);                    \
+        if (f64) pass1_n<double, n>(planes, n_planes, twiddle, occ, s);          \
+        else pass1_n<float, n>(planes, n_planes, twiddle, occ, s);               \
         break;
     switch (N) { WSG_FOR_EACH_N(X) default: break; }
 #undef X

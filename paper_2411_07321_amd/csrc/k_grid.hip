@@ -256,11 +256,11 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
 
 template <typename T, int TT>
 __global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const uint32_t *__restrict__ counts,
-                                                             uint32_t chunk, C2<T> *__restrict__ grid,
-                                                             int transposed) {
+                                                             uint32_t chunk, int zero_empty,
+                                                             C2<T> *__restrict__ grid, int transposed) {
     const uint32_t b = blockIdx.x;
     const uint32_t c = counts[b];
-    if (c != 0 && c <= chunk) return;
+    if (!(c > chunk || (zero_empty && c == 0))) return;
     int img, kl, ty, tx;
     bin_coords(g, b, img, kl, ty, tx);
     const int gi0 = tx * TT, gj0 = ty * TT;
@@ -269,6 +269,52 @@ __global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const ui
         int i, j;
         if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
         grid[cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0)] = C2<T>{T(0), T(0)};
+    }
+}
+
+// One workgroup per plane: its tile bitmaps (in LDS), tile-row bitmap and the
+// per-thread point masks of both transform passes.  Consecutive threads take
+// consecutive tile columns tx, so the reads of counts (bin = (plane*NT + ty)*NT
+// + tx) are contiguous.
+__global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__restrict__ counts,
+                                                   uint64_t *__restrict__ rows,
+                                                   uint32_t *__restrict__ live1,
+                                                   uint16_t *__restrict__ live2, int nw) {
+    __shared__ unsigned long long s_tiles[256 * 4];   // [tx][word], NT <= 256
+    __shared__ unsigned long long s_rows[4];
+    const int pi = blockIdx.x;
+    const int NT = g.NT, N = g.N, P = N / 16;
+    if (threadIdx.x < 4) s_rows[threadIdx.x] = 0ull;
+    __syncthreads();
+    const uint32_t *c = counts + ((size_t)pi << (2 * g.logNT));
+    for (int t = threadIdx.x; t < NT * nw; t += blockDim.x) {
+        const int tx = t % NT, wd = t / NT;
+        unsigned long long word = 0ull;
+        for (int bit = 0; bit < 64; ++bit) {
+            const int ty = wd * 64 + bit;
+            if (ty < NT && c[(size_t)ty * NT + tx] != 0u) word |= 1ull << bit;
+        }
+        s_tiles[tx * nw + wd] = word;
+        if (word) atomicOr(&s_rows[tx >> 6], 1ull << (tx & 63));
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nw) rows[(size_t)pi * nw + threadIdx.x] = s_rows[threadIdx.x];
+    for (int idx = threadIdx.x; idx < NT * P; idx += blockDim.x) {
+        const int tx = idx / P, t = idx - tx * P;
+        uint32_t m1 = (uint32_t)((s_rows[tx >> 6] >> (tx & 63)) & 1ull) << 16;
+        for (int m = 0; m < 16; ++m) {
+            const int ty = (t + m * P) >> g.logT;
+            m1 |= (uint32_t)((s_tiles[tx * nw + (ty >> 6)] >> (ty & 63)) & 1ull) << m;
+        }
+        live1[((size_t)pi * NT + tx) * P + t] = m1;
+    }
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        uint32_t m2 = 0u;
+        for (int m = 0; m < 16; ++m) {
+            const int tx = (t + m * P) >> g.logT;
+            m2 |= (uint32_t)((s_rows[tx >> 6] >> (tx & 63)) & 1ull) << m;
+        }
+        live2[(size_t)pi * P + t] = (uint16_t)m2;
     }
 }
 
@@ -312,15 +358,15 @@ void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *off
 }
 
 template <typename T>
-void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, void *grid,
+void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, int ze, void *grid,
                    bool transposed, hipStream_t s) {
     unsigned n_bins = (unsigned)((size_t)g.n_img * g.n_pl * g.NT * g.NT);
     C2<T> *gp = (C2<T> *)grid;
     int tr = transposed ? 1 : 0;
     switch (g.T) {
-    case 16: k_zero_tiles<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
-    case 32: k_zero_tiles<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
-    case 64: k_zero_tiles<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, gp, tr); break;
+    case 16: k_zero_tiles<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
+    case 32: k_zero_tiles<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
+    case 64: k_zero_tiles<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
     default: break;
     }
 }
@@ -328,11 +374,21 @@ void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, voi
 }  // namespace
 
 void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
-                       void *grid, bool transposed, hipStream_t s) {
+                       bool zero_empty, void *grid, bool transposed, hipStream_t s) {
+    const int ze = zero_empty ? 1 : 0;
     if (f64)
-        dispatch_zero<double>(g, counts, chunk, grid, transposed, s);
+        dispatch_zero<double>(g, counts, chunk, ze, grid, transposed, s);
     else
-        dispatch_zero<float>(g, counts, chunk, grid, transposed, s);
+        dispatch_zero<float>(g, counts, chunk, ze, grid, transposed, s);
+}
+
+int occupancy_words(int NT) { return (NT + 63) / 64; }
+
+void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
+                      uint16_t *live2, hipStream_t s) {
+    const unsigned n_planes = (unsigned)(g.n_img * g.n_pl);
+    if (n_planes == 0) return;
+    k_occupancy<<<n_planes, 256, 0, s>>>(g, counts, rows, live1, live2, occupancy_words(g.NT));
 }
 
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,

@@ -114,8 +114,31 @@ void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]
 // transposed: store plane k as [i][j] (u index slow) instead of [j][i]
+// Tile occupancy of the plane stack, so that the transform passes of the imaging
+// path read only what the gridder wrote.  For plane pi (= img * n_pl + kl) of the
+// transposed stack G[i][j], tile-row tx (rows i in [tx*T, tx*T + T)), and the
+// thread index t < P = N/16 of a length-N transform, whose points are
+// t + m*P (m < 16):
+//   rows[pi*nw + (tx >> 6)] bit (tx & 63): tile-row tx has a bin with records
+//   live1[(pi*NT + tx)*P + t]: bit m: column t + m*P of row tile-row tx lies in
+//       a tile with records (pass 1 reads it); bit 16: tile-row tx has records
+//   live2[pi*P + t] bit m: row t + m*P lies in a tile-row with records (pass 2
+//       reads it)
+// with nw = ceil(NT / 64) <= 4.  rows == NULL: every cell of the stack is valid.
+struct Occupancy {
+    const uint64_t *rows = nullptr;
+    const uint32_t *live1 = nullptr;
+    const uint16_t *live2 = nullptr;
+    int logT = 0;
+    int nw = 0;
+};
+int occupancy_words(int NT);
+void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
+                      uint16_t *live2, hipStream_t s);
+// Clear the tiles of split bins (their chunks add with atomics) and, with
+// zero_empty, those of empty bins (which have no work item).
 void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
-                       void *grid, bool transposed, hipStream_t s);
+                       bool zero_empty, void *grid, bool transposed, hipStream_t s);
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
                  const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
                  uint32_t chunk, const void *records, void *grid, bool transposed,
@@ -123,8 +146,10 @@ void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint3
 
 // transforms.  Pass 1: rows of planes [n][N][N] (in place) into the blocked
 // layout [N/B][N][B]; pass 2: along the other axis.
+// With occupancy, rows of empty tile-rows are neither read nor written and empty
+// tiles read as zero.
 void launch_fft_pass1(int N, bool f64, void *planes, int64_t n_planes, const void *twiddle,
-                      hipStream_t s);
+                      const Occupancy &occ, hipStream_t s);
 // pass 2 from the blocked layout `in` to row-major planes `out` (output row =
 // the untransformed index), out of place
 void launch_fft_pass2_store(int N, bool f64, const void *in, void *out, int64_t n_planes,
@@ -142,6 +167,7 @@ struct WcorrArgs {
     double cell;
     const ImgState *st;      // per image: w_min, dw, inv_norm
     const double *inv_c;     // [N] 1/C(nu) or NULL for no grid correction
+    Occupancy occ;           // what pass 1 wrote (live2 is used)
 };
 void launch_fft_pass2_wcorr(const WcorrArgs &a, bool f64, const void *planes,
                             const void *twiddle, double *image, hipStream_t s);

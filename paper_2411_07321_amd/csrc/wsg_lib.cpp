@@ -179,7 +179,9 @@ struct Plan {
     size_t vis_sz, wt_sz;
     // byte offsets in the fixed arena
     size_t o_uvw, o_vis, o_wts, o_flags, o_scale, o_mask, o_state, o_counts, o_offsets,
-        o_cursor, o_nchunk, o_itemoff, o_scan, o_tot, o_stack, o_image, o_aux, fixed_bytes;
+        o_cursor, o_nchunk, o_itemoff, o_scan, o_tot, o_occ_rows, o_occ_live1, o_occ_live2,
+        o_stack, o_image,
+        o_aux, fixed_bytes;
     size_t records_est, items_est;
 };
 
@@ -218,6 +220,12 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image
     pl.o_itemoff = take(nb1 * 4);
     pl.o_scan = take(scan_tmp_elems(nb1) * 4);
     pl.o_tot = take(16);
+    {
+        const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.n_pl;
+        pl.o_occ_rows = take(np * nw * 8);
+        pl.o_occ_live1 = take(np * pl.NT * (pl.N / 16) * 4);
+        pl.o_occ_live2 = take(np * (pl.N / 16) * 2);
+    }
     pl.o_stack = take((size_t)pl.n_img * pl.n_pl * pl.N * pl.N * (pl.f64 ? 16 : 8));
     pl.o_image = take(host_out_image ? (size_t)pl.n_img * pl.N * pl.N * (stage_image_out ? 8 : 8) : 0);
     pl.o_aux = take(0);
@@ -548,8 +556,14 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     return WSG_OK;
 }
 
-wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, hipStream_t s) {
-    launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, grid, transposed, s);
+// dense: every cell of `grid` is written (the stage entry point); otherwise only
+// the tiles of non-empty bins, and the occupancy bitmaps say which those are
+wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, bool dense,
+                       hipStream_t s) {
+    launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, dense, grid, transposed, s);
+    if (!dense)
+        launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
+                         (uint32_t *)(b.fx + b.pl.o_occ_live1), (uint16_t *)(b.fx + b.pl.o_occ_live2), s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
                 b.records, grid, transposed, s);
     WSG_HIP(ctx, hipGetLastError());
@@ -621,6 +635,45 @@ wsg_status common_checks(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
 // ============================================================================
 // C ABI
 // ============================================================================
+// Gridding, both transform passes and the w-correction of a binned job, into the
+// device image img_dev [n_img][N][N].
+wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *img_dev, hipStream_t s) {
+    const Plan &pl = b.pl;
+    void *stack = b.fx + pl.o_stack;
+    const void *tw = nullptr;
+    wsg_status rc = get_twiddle(ctx, pl.N, pl.f64, &tw);
+    if (rc) return rc;
+    const double *inv_c = nullptr;
+    rc = get_inv_c(ctx, p, s, &inv_c);
+    if (rc) return rc;
+    rc = grid_binned(ctx, b, stack, true, false, s);
+    if (rc) return rc;
+    mark(ctx, kMarkGrid, s);
+    Occupancy occ;
+    occ.rows = (const uint64_t *)(b.fx + pl.o_occ_rows);
+    occ.live1 = (const uint32_t *)(b.fx + pl.o_occ_live1);
+    occ.live2 = (const uint16_t *)(b.fx + pl.o_occ_live2);
+    occ.logT = b.g.logT;
+    occ.nw = occupancy_words(pl.NT);
+    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, tw, occ, s);
+    mark(ctx, kMarkFft1, s);
+    WcorrArgs a{};
+    a.N = pl.N;
+    a.n_img = pl.n_img;
+    a.n_pl = pl.n_pl;
+    a.plane_lo = pl.plane_lo;
+    a.n_w = pl.n_w;
+    a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
+    a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
+    a.cell = p->cell_rad;
+    a.st = b.st;
+    a.inv_c = inv_c;
+    a.occ = occ;
+    launch_fft_pass2_wcorr(a, pl.f64, stack, tw, img_dev, s);
+    WSG_HIP(ctx, hipGetLastError());
+    return WSG_OK;
+}
+
 extern "C" {
 
 wsg_status wsg_create(int device, wsg_ctx **out) {
@@ -752,31 +805,9 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
     rc = bin_job(ctx, p, v, s, host_img, b);
     if (rc) return rc;
     const Plan &pl = b.pl;
-    void *stack = b.fx + pl.o_stack;
-    const void *tw = nullptr;
-    rc = get_twiddle(ctx, pl.N, pl.f64, &tw);
-    if (rc) return rc;
-    const double *inv_c = nullptr;
-    rc = get_inv_c(ctx, p, s, &inv_c);
-    if (rc) return rc;
-    rc = grid_binned(ctx, b, stack, true, s);
-    if (rc) return rc;
-    mark(ctx, kMarkGrid, s);
-    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, tw, s);
-    mark(ctx, kMarkFft1, s);
-    WcorrArgs a{};
-    a.N = pl.N;
-    a.n_img = pl.n_img;
-    a.n_pl = pl.n_pl;
-    a.plane_lo = pl.plane_lo;
-    a.n_w = pl.n_w;
-    a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
-    a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
-    a.cell = p->cell_rad;
-    a.st = b.st;
-    a.inv_c = inv_c;
     double *img_dev = host_img ? (double *)(b.fx + pl.o_image) : image;
-    launch_fft_pass2_wcorr(a, pl.f64, stack, tw, img_dev, s);
+    rc = image_binned(ctx, p, b, img_dev, s);
+    if (rc) return rc;
     WSG_HIP(ctx, hipGetLastError());
     if (host_img)
         WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)pl.n_img * pl.N * pl.N * 8, hipMemcpyDeviceToHost, s));
@@ -797,7 +828,7 @@ wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, v
     if (rc) return rc;
     const Plan &pl = b.pl;
     void *dst = (mem == WSG_MEM_HOST) ? (void *)(b.fx + pl.o_stack) : grid;
-    rc = grid_binned(ctx, b, dst, false, s);
+    rc = grid_binned(ctx, b, dst, false, true, s);
     if (rc) return rc;
     if (mem == WSG_MEM_HOST) {
         size_t bytes = (size_t)pl.n_img * pl.n_pl * pl.N * pl.N * cplx_size(p);
@@ -833,7 +864,7 @@ wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_
     rc = get_twiddle(ctx, N, f64, &tw);
     if (rc) return rc;
     launch_transpose(N, f64, src, work, n_planes, s);
-    launch_fft_pass1(N, f64, work, n_planes, tw, s);
+    launch_fft_pass1(N, f64, work, n_planes, tw, Occupancy(), s);
     launch_fft_pass2_store(N, f64, work, src, n_planes, tw, s);
     WSG_HIP(ctx, hipGetLastError());
     if (mem == WSG_MEM_HOST) {
@@ -908,7 +939,7 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
                         int32_t *best_tile) {
     wsg_status rc = common_checks(ctx, p, v);
     if (rc) return rc;
-    hipStream_t s = pick_stream(ctx, nullptr);
+    hipStream_t s = pick_stream(ctx, ctx->stream);
     const int cands[] = {16, 32, 64};
     float best_ms = 1e30f;
     int best = default_tile(p);
@@ -919,10 +950,12 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
         float acc = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
             WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
+            // the whole path: the tile also sets how much of the stack the
+            // transform passes skip
             Binned b;
-            rc = bin_job(ctx, &q, v, s, false, b);
+            rc = bin_job(ctx, &q, v, s, true, b);
             if (rc) return rc;
-            rc = grid_binned(ctx, b, b.fx + b.pl.o_stack, true, s);
+            rc = image_binned(ctx, &q, b, (double *)(b.fx + b.pl.o_image), s);
             if (rc) return rc;
             WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
             WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));

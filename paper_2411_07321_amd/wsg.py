@@ -86,6 +86,13 @@ def load() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch brings its own HIP runtime; loading it first makes the library bind
+        # to that same runtime (one per process).  Loaded the other way round, a
+        # second runtime initialises the device first and torch then finds none.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         P, S = ctypes.c_void_p, ctypes.c_int32
         lib.wsg_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]

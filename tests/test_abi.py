@@ -107,3 +107,17 @@ def test_no_device_is_a_loud_error():
     with pytest.raises(wsg.WsgError) as e:
         wsg.Context(0)
     assert e.value.status in (wsg.EDEVICE, wsg.EINVAL)
+
+
+def test_load_binds_to_torchs_hip_runtime():
+    """Loading the library imports torch first, so both use one HIP runtime (a second
+    runtime initialised first would leave torch without devices)."""
+    import subprocess
+    import sys
+    code = ("import sys; from paper_2411_07321_amd import wsg; "
+            "assert 'torch' not in sys.modules; wsg.load(); print('torch' in sys.modules)")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "True"
