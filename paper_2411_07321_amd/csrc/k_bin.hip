@@ -218,6 +218,7 @@ __global__ void k_finalize(JobGeom g, ImgState *st) {
 // only when it lies within a few ulps (< 1e-9 here, as it is below 65536) of an
 // integer, and only then is the division done.
 __device__ __forceinline__ int plane_of(double w, double w_min, double dw, double inv_dw, int n_w) {
+#pragma clang fp contract(off)
     if (dw == 0.0) return 0;
     const double d = w - w_min;
     double q = d * inv_dw;
@@ -237,6 +238,9 @@ struct Placed {
 // the row's (u, v, w) as stored and the channel's scale.
 __device__ __forceinline__ bool place_vals(const JobGeom &g, const ImgState &s, double um,
                                            double vm, double wm, double sc, Placed &pl) {
+    // every product and difference rounded on its own (no contraction), so that both
+    // binning passes, and the oracle, take the same decisions
+#pragma clang fp contract(off)
     double w = wm * sc;
     if (!(w >= s.w_min && w <= s.w_max)) return false;
     double u = um * sc, v = vm * sc;
@@ -262,141 +266,6 @@ struct Keys {
     int n;
     uint32_t k[4];
 };
-
-__device__ __forceinline__ bool has_key(const Keys &ks, uint32_t key) {
-    bool f = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f |= (i < ks.n) && ks.k[i] == key;
-    return f;
-}
-
-// (channel, baseline, time block) of a track thread
-struct Track {
-    int c;
-    int64_t b, t0, t1;
-    bool ok;
-};
-
-__device__ __forceinline__ Track track_of(const JobGeom &g, int64_t idx) {
-    Track tr;
-    tr.c = (int)(idx % g.n_chan);
-    int64_t rest = idx / g.n_chan;
-    tr.b = rest % g.P;
-    int64_t tb = rest / g.P;
-    tr.t0 = tb * g.L;
-    tr.t1 = min(g.n_t, tr.t0 + g.L);
-    tr.ok = tb < g.n_tb;
-    return tr;
-}
-
-template <bool F64W>
-__global__ __launch_bounds__(kThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
-                                                    const void *__restrict__ wts,
-                                                    const uint8_t *__restrict__ mask,
-                                                    ImgState *st, uint32_t *__restrict__ counts) {
-    __shared__ unsigned long long s_used[256];
-    __shared__ double s_sumw[256];
-    const int n_img = g.n_img;
-    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
-        s_used[i] = 0;
-        s_sumw[i] = 0.0;
-    }
-    __syncthreads();
-    const Track tr = track_of(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    const int img = (n_img > 1) ? tr.c : 0;
-    unsigned long long nu = 0;
-    double sw = 0.0;
-    if (tr.ok) {
-        const ImgState s = st[img];
-        uint32_t okey[4] = {0, 0, 0, 0};
-        uint32_t ocnt[4] = {0, 0, 0, 0};
-        const double sc = g.chan_scale[tr.c];
-        int64_t t_end = tr.t1;
-        if (t_end > tr.t0 && (t_end - 1) * g.P + tr.b >= g.n_rows) t_end = (g.n_rows - 1 - tr.b) / g.P + 1;
-        for (int64_t t0b = tr.t0; t0b < t_end; t0b += kBatch) {
-        // the loads of kBatch elements are issued together
-        uint8_t mb[kBatch];
-        double ub[kBatch], vb[kBatch], wb[kBatch], wtb[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int64_t t = min(t0b + j, t_end - 1);
-            const int64_t r = t * g.P + tr.b;
-            const int64_t e = r * g.n_chan + tr.c;
-            mb[j] = (t0b + j < t_end) ? mask[e] : 0;
-            ub[j] = uvw[3 * r];
-            vb[j] = uvw[3 * r + 1];
-            wb[j] = uvw[3 * r + 2];
-            wtb[j] = wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
-        }
-        for (int j = 0; j < kBatch && t0b + j < t_end; ++j) {
-            Placed pl;
-            Keys ks;
-            ks.n = 0;
-            const bool in_range = place_vals(g, s, ub[j], vb[j], wb[j], sc, pl);
-            if (mb[j] && in_range) {
-                ++nu;
-                sw += wtb[j];
-                int kl = pl.k - g.plane_lo;
-                if (kl >= 0 && kl < g.n_pl) {
-                    int64_t base = bin_base(g, img, kl);
-                    int tx0 = (pl.i0 - g.h) >> g.logT, tx1 = (pl.i0 + g.h) >> g.logT;
-                    int ty0 = (pl.j0 - g.h) >> g.logT, ty1 = (pl.j0 + g.h) >> g.logT;
-                    for (int ty = ty0; ty <= ty1; ++ty)
-                        for (int tx = tx0; tx <= tx1; ++tx)
-                            ks.k[ks.n++] = (uint32_t)(base + (int64_t)ty * g.NT + tx);
-                }
-            }
-            // close runs whose bin this element does not touch
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (ocnt[q] && !has_key(ks, okey[q])) {
-                    atomicAdd(&counts[okey[q]], ocnt[q]);
-                    ocnt[q] = 0;
-                }
-            // extend or open runs
-            for (int i = 0; i < ks.n; ++i) {
-                bool done = false;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (!done && ocnt[q] && okey[q] == ks.k[i]) {
-                        ++ocnt[q];
-                        done = true;
-                    }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (!done && ocnt[q] == 0) {
-                        okey[q] = ks.k[i];
-                        ocnt[q] = 1;
-                        done = true;
-                    }
-            }
-        }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (ocnt[j]) atomicAdd(&counts[okey[j]], ocnt[j]);
-    }
-    if (n_img == 1) {
-        for (int off = 32; off > 0; off >>= 1) {
-            nu += __shfl_xor(nu, off);
-            sw += __shfl_xor(sw, off);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&s_used[0], nu);
-            atomicAdd(&s_sumw[0], sw);
-        }
-    } else if (tr.ok) {
-        atomicAdd(&s_used[img], nu);
-        atomicAdd(&s_sumw[img], sw);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
-        if (s_used[i]) {
-            atomicAdd(&st[i].n_used, s_used[i]);
-            atomicAdd(&st[i].sum_w, s_sumw[i]);
-        }
-    }
-}
 
 template <typename VT>
 __device__ __forceinline__ void write_record(void *records, uint32_t slot, const JobGeom &g,
@@ -427,16 +296,30 @@ __device__ __forceinline__ void write_record(void *records, uint32_t slot, const
     }
 }
 
-// The scatter walks the same tracks in blocks of kScatL time slices, in three
-// phases with the same trip count on every lane (so no lane waits on another's
-// inner loop):
-//   1. the bins of each element, packed into one word, into LDS;
-//   2. backwards through the block, the length of the run that starts at each
-//      (element, bin);
-//   3. forwards, one slot reservation per run (an atomic on the bin's cursor),
-//      then the records.
-constexpr int kScatThreads = 128;
-constexpr int kScatL = 64;
+// One binning thread: kStretch consecutive time slices of the track of baseline
+// b (rows t*P + b) in channel c.  Consecutive threads take consecutive channels,
+// then baselines, so that the loads of a wave fall on neighbouring rows.
+struct Stretch {
+    int c;
+    int64_t b, t0, t_end;   // time slices [t0, t_end)
+    bool ok;
+};
+
+__device__ __forceinline__ Stretch stretch_of(const JobGeom &g, int64_t idx) {
+    Stretch sr;
+    sr.c = (int)(idx % g.n_chan);
+    const int64_t rest = idx / g.n_chan;
+    sr.b = rest % g.P;
+    const int64_t tb = rest / g.P;
+    sr.ok = tb < g.n_tb;
+    sr.t0 = tb * kStretch;
+    int64_t t1 = min(g.n_t, sr.t0 + kStretch);
+    // the last time slice may be short of P rows
+    if (sr.ok && t1 > sr.t0 && (t1 - 1) * g.P + sr.b >= g.n_rows) t1 = (g.n_rows - 1 - sr.b) / g.P + 1;
+    sr.t_end = sr.ok ? max(t1, sr.t0) : sr.t0;
+    return sr;
+}
+
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 // base bin (lowest tile) in bits 0..26, bit 27: also the tile to the right, bit 28:
@@ -450,114 +333,206 @@ __device__ __forceinline__ uint32_t pack_placed(const JobGeom &g, int img, const
     return base | ((uint32_t)(tx1 > tx0) << 27) | ((uint32_t)(ty1 > ty0) << 28);
 }
 
+// the 1, 2 or 4 bins in a fixed order: base, then right or above, then above,
+// then above-right (positions are static, so the keys stay in registers)
 __device__ __forceinline__ void unpack_keys(uint32_t pk, int NT, Keys &ks) {
-    ks.n = 0;
-    if (pk == kNoKey) return;
-    uint32_t b = pk & 0x7ffffffu;
-    bool cx = (pk >> 27) & 1u, cy = (pk >> 28) & 1u;
-    ks.k[ks.n++] = b;
-    if (cx) ks.k[ks.n++] = b + 1;
-    if (cy) ks.k[ks.n++] = b + (uint32_t)NT;
-    if (cx && cy) ks.k[ks.n++] = b + (uint32_t)NT + 1;
+    const uint32_t b = pk & 0x7ffffffu;
+    const bool cx = (pk >> 27) & 1u, cy = (pk >> 28) & 1u;
+    ks.k[0] = b;
+    ks.k[1] = cx ? b + 1u : b + (uint32_t)NT;
+    ks.k[2] = b + (uint32_t)NT;
+    ks.k[3] = b + (uint32_t)NT + 1u;
+    ks.n = pk == kNoKey ? 0 : (cx && cy) ? 4 : (cx || cy) ? 2 : 1;
 }
 
-template <typename VT>
-__global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
-                                                          const void *__restrict__ vis,
-                                                          const void *__restrict__ wts,
-                                                          const uint8_t *__restrict__ mask,
-                                                          const ImgState *st, uint32_t *cursor,
-                                                          void *__restrict__ records, uint32_t capacity,
-                                                          uint32_t *overflow) {
-    // one word per element: the packed bins (phase 1), then, in place, the 4 x
-    // 8-bit run lengths (phase 2); phase 3 recomputes the bins
-    __shared__ uint32_t s_key[kScatL][kScatThreads];
+constexpr int kBinThreads = 256;
+
+// Counting pass.  Along its stretch a thread tracks runs of elements with the
+// same packed bins (a track moves slowly, so runs are long) and adds each run to
+// its private table of (bin, records) in LDS; a table that would exceed kTab
+// bins sends the rest of the stretch's runs straight to the global counts.  At
+// the end the table goes to `counts` (one atomic per entry) and, for the
+// scatter, to tab / tab_n.
+template <bool F64W>
+__global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
+                                                       const void *__restrict__ wts,
+                                                       const uint8_t *__restrict__ mask,
+                                                       ImgState *st, uint32_t *__restrict__ cls_counts,
+                                                       int n_cls, TabEntry *__restrict__ tab,
+                                                       uint32_t *__restrict__ tab_n) {
+    __shared__ uint32_t s_tb[kTab][kBinThreads];
+    __shared__ uint32_t s_tc[kTab][kBinThreads];
+    __shared__ unsigned long long s_used[256];
+    __shared__ double s_sumw[256];
+    const int n_img = g.n_img;
     const int lane = threadIdx.x;
-    // track of this thread: blocks of kScatL time slices
+    for (int i = lane; i < n_img; i += blockDim.x) {
+        s_used[i] = 0;
+        s_sumw[i] = 0.0;
+    }
+    __syncthreads();
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
-    const int c = (int)(idx % g.n_chan);
-    const int64_t rest = idx / g.n_chan;
-    const int64_t b = rest % g.P;
-    const int64_t tb = rest / g.P;
-    const int64_t t0 = tb * kScatL;
-    const bool ok = t0 < g.n_t;
-    const int img = (g.n_img > 1) ? c : 0;
-    const ImgState s = st[ok ? img : 0];
-    int nt = 0;
-    if (ok) {
-        int64_t t1 = min(g.n_t, t0 + kScatL);
-        for (int64_t t = t0; t < t1; ++t) {
-            if (t * g.P + b >= g.n_rows) break;
-            ++nt;
-        }
-    }
-    const double sc = g.chan_scale[c];
-    // phase 1: packed bins (the loads of kBatch elements are issued together)
-    for (int k0 = 0; k0 < kScatL; k0 += kBatch) {
-        uint8_t m[kBatch];
-        double u[kBatch], v[kBatch], w[kBatch];
+    const Stretch sr = stretch_of(g, idx);
+    const int img = (n_img > 1) ? sr.c : 0;
+    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
+    uint32_t *counts = cls_counts + (size_t)(blockIdx.x % (unsigned)n_cls) * n_bins;
+    unsigned long long nu = 0;
+    double sw = 0.0;
+    if (sr.ok) {
+        const ImgState s = st[img];
+        const double sc = g.chan_scale[sr.c];
+        int n_ent = 0;
+        bool ovf = false;
+        uint32_t cur = kNoKey, run = 0;
+        bool cur_tab = false;
+        Keys cks;
+        cks.n = 0;
+        int ent[4] = {0, 0, 0, 0};
+        for (int64_t t0b = sr.t0; t0b < sr.t_end; t0b += kBatch) {
+            // the loads of kBatch elements are issued together
+            uint8_t mb[kBatch];
+            double ub[kBatch], vb[kBatch], wb[kBatch], wtb[kBatch];
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int k = k0 + j;
-            const bool in = k < nt;
-            // clamped to a real row so that no load can leave the buffers
-            const int64_t r = min((t0 + min(k, max(nt - 1, 0))) * g.P + b, g.n_rows - 1);
-            m[j] = in ? mask[r * g.n_chan + c] : 0;
-            u[j] = in ? uvw[3 * r] : 0.0;
-            v[j] = in ? uvw[3 * r + 1] : 0.0;
-            w[j] = in ? uvw[3 * r + 2] : 0.0;
-        }
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t t = min(t0b + j, sr.t_end - 1);
+                const int64_t r = t * g.P + sr.b;
+                const int64_t e = r * g.n_chan + sr.c;
+                mb[j] = (t0b + j < sr.t_end) ? mask[e] : 0;
+                ub[j] = uvw[3 * r];
+                vb[j] = uvw[3 * r + 1];
+                wb[j] = uvw[3 * r + 2];
+                wtb[j] = wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
+            }
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            Placed pl;
-            uint32_t pk = kNoKey;
-            if (m[j] && place_vals(g, s, u[j], v[j], w[j], sc, pl)) pk = pack_placed(g, img, pl);
-            s_key[k0 + j][lane] = pk;
+            for (int j = 0; j < kBatch; ++j) {
+                Placed pl;
+                uint32_t pk = kNoKey;
+                if (mb[j] && place_vals(g, s, ub[j], vb[j], wb[j], sc, pl)) {
+                    ++nu;
+                    sw += wtb[j];
+                    pk = pack_placed(g, img, pl);
+                }
+                if (pk != cur) {
+                    // close the run of `cur`
+                    if (run) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (i >= cks.n) continue;
+                            if (cur_tab) s_tc[ent[i]][lane] += run;
+                            else atomicAdd(&counts[cks.k[i]], run);
+                        }
+                    }
+                    // open a run of `pk`: its bins in the table, added when missing
+                    cur = pk;
+                    run = 0;
+                    unpack_keys(pk, g.NT, cks);
+                    cur_tab = !ovf;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (i >= cks.n || !cur_tab) continue;
+                        int f = -1;
+                        for (int e = 0; e < n_ent; ++e)
+                            if (s_tb[e][lane] == cks.k[i]) f = e;
+                        if (f < 0) {
+                            if (n_ent < kTab) {
+                                f = n_ent++;
+                                s_tb[f][lane] = cks.k[i];
+                                s_tc[f][lane] = 0u;
+                            } else {
+                                ovf = true;
+                                cur_tab = false;
+                            }
+                        }
+                        ent[i] = f;
+                    }
+                }
+                if (pk != kNoKey) ++run;
+            }
         }
-    }
-    // phase 2: run lengths, backwards; `open` holds the bins of element k+1 with the
-    // length of their run from k+1 on
-    {
-        uint32_t okey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
-        uint32_t olen[4] = {0, 0, 0, 0};
-        for (int k = kScatL - 1; k >= 0; --k) {
-            Keys ks;
-            unpack_keys(s_key[k][lane], g.NT, ks);
-            uint32_t nkey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
-            uint32_t nlen[4] = {0, 0, 0, 0};
-            uint32_t packed = 0;
+        if (run) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (i >= ks.n) continue;
-                uint32_t len = 1;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (okey[j] == ks.k[i]) len = olen[j] + 1;
-                nkey[i] = ks.k[i];
-                nlen[i] = len;
-                packed |= min(len, 255u) << (8 * i);
-            }
-            s_key[k][lane] = packed;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                okey[i] = nkey[i];
-                olen[i] = nlen[i];
+                if (i >= cks.n) continue;
+                if (cur_tab) s_tc[ent[i]][lane] += run;
+                else atomicAdd(&counts[cks.k[i]], run);
             }
         }
+        for (int e = 0; e < n_ent; ++e) {
+            const uint32_t bin = s_tb[e][lane], n = s_tc[e][lane];
+            if (n) atomicAdd(&counts[bin], n);
+            tab[idx * kTab + e] = TabEntry{bin, n};
+        }
+        tab_n[idx] = ovf ? kTabOverflow : (uint32_t)n_ent;
     }
-    // phase 3: forwards, one reservation per run
-    uint32_t okey[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
-    uint32_t onext[4] = {0, 0, 0, 0};
-    uint32_t orem[4] = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < nt; k0 += kBatch) {
+    if (n_img == 1) {
+        for (int off = 32; off > 0; off >>= 1) {
+            nu += __shfl_xor(nu, off);
+            sw += __shfl_xor(sw, off);
+        }
+        if ((lane & 63) == 0) {
+            atomicAdd(&s_used[0], nu);
+            atomicAdd(&s_sumw[0], sw);
+        }
+    } else if (sr.ok) {
+        atomicAdd(&s_used[img], nu);
+        atomicAdd(&s_sumw[img], sw);
+    }
+    __syncthreads();
+    for (int i = lane; i < n_img; i += blockDim.x) {
+        if (s_used[i]) {
+            atomicAdd(&st[i].n_used, s_used[i]);
+            atomicAdd(&st[i].sum_w, s_sumw[i]);
+        }
+    }
+}
+
+// Scatter.  A thread reserves, for each (bin, records) pair its stretch left in
+// the table, one range of slots (one atomic on the bin's cursor), then walks the
+// stretch once more and writes each record into the next slot of its bin, so the
+// records of one stretch are contiguous, in time order, inside every bin they
+// reach.  An overflowed stretch reserves record by record.
+template <typename VT>
+__global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
+                                                         const void *__restrict__ vis,
+                                                         const void *__restrict__ wts,
+                                                         const uint8_t *__restrict__ mask,
+                                                         const ImgState *st, uint32_t *cls_cursor,
+                                                         int n_cls, const TabEntry *__restrict__ tab,
+                                                         const uint32_t *__restrict__ tab_n,
+                                                         void *__restrict__ records, uint32_t capacity,
+                                                         uint32_t *overflow) {
+    __shared__ uint32_t s_tb[kTab][kBinThreads];
+    __shared__ uint32_t s_tn[kTab][kBinThreads];   // next free slot of the entry's bin
+    const int lane = threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
+    const Stretch sr = stretch_of(g, idx);
+    if (!sr.ok) return;   // no barrier below
+    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
+    uint32_t *cursor = cls_cursor + (size_t)(blockIdx.x % (unsigned)n_cls) * n_bins;
+    const int img = (g.n_img > 1) ? sr.c : 0;
+    const ImgState s = st[img];
+    const double sc = g.chan_scale[sr.c];
+    const uint32_t tn = tab_n[idx];
+    const bool ovf = tn == kTabOverflow;
+    const int n_ent = ovf ? 0 : (int)tn;
+    for (int e = 0; e < n_ent; ++e) {
+        const TabEntry te = tab[idx * kTab + e];
+        s_tb[e][lane] = te.bin;
+        s_tn[e][lane] = te.n ? atomicAdd(&cursor[te.bin], te.n) : 0u;
+    }
+    uint32_t cur = kNoKey;
+    Keys ks;
+    ks.n = 0;
+    int ent[4] = {-1, -1, -1, -1};
+    for (int64_t t0b = sr.t0; t0b < sr.t_end; t0b += kBatch) {
         uint8_t m[kBatch];
         double u[kBatch], v[kBatch], w[kBatch], vr[kBatch], vi[kBatch], wt[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-            const int k = min(k0 + j, nt - 1);
-            const int64_t r = (t0 + k) * g.P + b;
-            const int64_t e = r * g.n_chan + c;
-            m[j] = (k0 + j < nt) ? mask[e] : 0;
+            const int64_t t = min(t0b + j, sr.t_end - 1);
+            const int64_t r = t * g.P + sr.b;
+            const int64_t e = r * g.n_chan + sr.c;
+            m[j] = (t0b + j < sr.t_end) ? mask[e] : 0;
             u[j] = uvw[3 * r];
             v[j] = uvw[3 * r + 1];
             w[j] = uvw[3 * r + 2];
@@ -565,47 +540,64 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(JobGeom g, const doubl
         }
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-        Placed pl;
-        if (!m[j] || !place_vals(g, s, u[j], v[j], w[j], sc, pl)) continue;
-        const uint32_t pk = pack_placed(g, img, pl);
-        if (pk == kNoKey) continue;
-        Keys ks;
-        unpack_keys(pk, g.NT, ks);
-        const uint32_t lens = s_key[k0 + j][lane];
+            Placed pl;
+            if (!m[j] || !place_vals(g, s, u[j], v[j], w[j], sc, pl)) continue;
+            const uint32_t pk = pack_placed(g, img, pl);
+            if (pk == kNoKey) continue;
+            if (pk != cur) {
+                cur = pk;
+                unpack_keys(pk, g.NT, ks);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (i >= ks.n) continue;
-            const uint32_t key = ks.k[i];
-            uint32_t slot = 0;
-            bool have = false;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (!have && orem[j] && okey[j] == key) {
-                    slot = onext[j]++;
-                    --orem[j];
-                    have = true;
+                for (int i = 0; i < 4; ++i) {
+                    int f = -1;
+                    if (i < ks.n && !ovf)
+                        for (int e = 0; e < n_ent; ++e)
+                            if (s_tb[e][lane] == ks.k[i]) f = e;
+                    ent[i] = f;
                 }
-            if (!have) {
-                const uint32_t len = (lens >> (8 * i)) & 0xffu;
-                const uint32_t base = atomicAdd(&cursor[key], len);
-                slot = base;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (!have && orem[j] == 0) {
-                        okey[j] = key;
-                        onext[j] = base + 1;
-                        orem[j] = len - 1;
-                        have = true;
-                    }
             }
-            // the counting pass sized the buffer; a slot beyond it would mean the two
-            // passes disagree: never write there, report it instead
-            if (slot < capacity)
-                write_record<VT>(records, slot, g, pl, key, vr[j], vi[j], wt[j]);
-            else
-                atomicAdd(overflow, 1u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i >= ks.n) continue;
+                uint32_t slot;
+                if (ovf) {
+                    slot = atomicAdd(&cursor[ks.k[i]], 1u);
+                } else if (ent[i] >= 0) {
+                    slot = s_tn[ent[i]][lane];
+                    s_tn[ent[i]][lane] = slot + 1u;
+                } else {
+                    slot = capacity;   // the passes disagree: reported below
+                }
+                // the counting pass sized the buffer; a slot beyond it would mean the
+                // two passes disagree: never write there, report it instead
+                if (slot < capacity)
+                    write_record<VT>(records, slot, g, pl, ks.k[i], vr[j], vi[j], wt[j]);
+                else
+                    atomicAdd(overflow, 1u);
+            }
         }
-        }
+    }
+}
+
+__global__ void k_class_totals(const uint32_t *__restrict__ cls_counts, int n_cls, size_t n_bins,
+                               uint32_t *__restrict__ counts) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n_bins) return;
+    uint32_t t = 0;
+    if (i < n_bins)
+        for (int c = 0; c < n_cls; ++c) t += cls_counts[(size_t)c * n_bins + i];
+    counts[i] = t;   // the entry after the last bin stays 0: its offset is the total
+}
+
+__global__ void k_class_cursors(const uint32_t *__restrict__ cls_counts, int n_cls, size_t n_bins,
+                                const uint32_t *__restrict__ offsets,
+                                uint32_t *__restrict__ cls_cursor) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_bins) return;
+    uint32_t run = offsets[i];
+    for (int c = 0; c < n_cls; ++c) {
+        cls_cursor[(size_t)c * n_bins + i] = run;
+        run += cls_counts[(size_t)c * n_bins + i];
     }
 }
 
@@ -685,32 +677,47 @@ void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s) {
     k_finalize<<<(g.n_img + 63) / 64, 64, 0, s>>>(g, st);
 }
 
-int64_t track_threads(const JobGeom &g) { return (int64_t)g.n_chan * g.P * g.n_tb; }
+int64_t stretch_threads(int64_t n_chan, int64_t P, int64_t n_tb) { return n_chan * P * n_tb; }
+
+int binning_classes(size_t n_bins) { return n_bins <= ((size_t)1 << 22) ? kMaxClasses : 1; }
 
 void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
-                  const uint8_t *mask, ImgState *st, uint32_t *counts, hipStream_t s) {
-    int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
-    if (n_elem == 0) return;
-    unsigned blocks = (unsigned)((track_threads(g) + kThreads - 1) / kThreads);
+                  const uint8_t *mask, ImgState *st, uint32_t *cls_counts, int n_cls,
+                  TabEntry *tab, uint32_t *tab_n, hipStream_t s) {
+    const int64_t n = stretch_threads(g.n_chan, g.P, g.n_tb);
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)((n + kBinThreads - 1) / kBinThreads);
     if (f64)
-        k_count<true><<<blocks, kThreads, 0, s>>>(g, uvw, wts, mask, st, counts);
+        k_count<true><<<blocks, kBinThreads, 0, s>>>(g, uvw, wts, mask, st, cls_counts, n_cls, tab, tab_n);
     else
-        k_count<false><<<blocks, kThreads, 0, s>>>(g, uvw, wts, mask, st, counts);
+        k_count<false><<<blocks, kBinThreads, 0, s>>>(g, uvw, wts, mask, st, cls_counts, n_cls, tab, tab_n);
+}
+
+void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
+                         hipStream_t s) {
+    k_class_totals<<<(unsigned)((n_bins + 1 + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, counts);
+}
+
+void launch_class_cursors(const uint32_t *cls_counts, int n_cls, size_t n_bins,
+                          const uint32_t *offsets, uint32_t *cls_cursor, hipStream_t s) {
+    if (n_bins == 0) return;
+    k_class_cursors<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, offsets,
+                                                                    cls_cursor);
 }
 
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
-                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
-                    void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s) {
-    int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
-    if (n_elem == 0) return;
-    int64_t threads = (int64_t)g.n_chan * g.P * ((g.n_t + kScatL - 1) / kScatL);
-    unsigned blocks = (unsigned)((threads + kScatThreads - 1) / kScatThreads);
+                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cls_cursor,
+                    int n_cls, const TabEntry *tab, const uint32_t *tab_n, void *records,
+                    uint32_t capacity, uint32_t *overflow, hipStream_t s) {
+    const int64_t n = stretch_threads(g.n_chan, g.P, g.n_tb);
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)((n + kBinThreads - 1) / kBinThreads);
     if (f64)
-        k_scatter<double><<<blocks, kScatThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor,
-                                                          records, capacity, overflow);
+        k_scatter<double><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
+                                                         tab, tab_n, records, capacity, overflow);
     else
-        k_scatter<float><<<blocks, kScatThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cursor,
-                                                         records, capacity, overflow);
+        k_scatter<float><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
+                                                        tab, tab_n, records, capacity, overflow);
 }
 
 size_t scan_tmp_elems(size_t n) {

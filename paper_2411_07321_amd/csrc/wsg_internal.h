@@ -83,9 +83,29 @@ struct JobGeom {
     const double *chan_scale;  // device [n_chan]: f/c or 1
     // track traversal of the binning passes: rows are viewed as [n_t][P]
     // (P = row period, the baselines per time slice); a thread follows one
-    // (baseline, channel) track through L consecutive time slices
-    int64_t P, n_t, L, n_tb;
+    // (baseline, channel) track through kStretch consecutive time slices, the
+    // n_tb stretches of a track being threads of their own
+    int64_t P, n_t, n_tb;
 };
+
+// Binning stretch: kStretch time slices of one (baseline, channel) track per
+// thread.  The counting pass leaves, per stretch, a table of up to kTab
+// (bin, records) pairs; the scatter reserves one slot range per pair.  A stretch
+// that touches more than kTab bins is marked kTabOverflow and reserves per record.
+constexpr int kStretch = 64;
+constexpr int kTab = 8;
+constexpr uint32_t kTabOverflow = 0xffffffffu;
+struct TabEntry {
+    uint32_t bin, n;
+};
+int64_t stretch_threads(int64_t n_chan, int64_t P, int64_t n_tb);
+// The binning passes spread the atomics on one bin over n_cls classes (the
+// workgroup index mod n_cls): class c counts into cls_counts[c][bin] and the
+// scatter reserves from its own sub-range of the bin, starting at
+// cls_cursor[c][bin].  Hot bins (the centre of the uv plane) otherwise take
+// hundreds of thousands of atomics on one address.
+constexpr int kMaxClasses = 8;
+int binning_classes(size_t n_bins);
 
 // ----------------------------------------------------------------------------
 // launchers (each enqueues on `s`; no host synchronisation)
@@ -95,9 +115,17 @@ void launch_prep(const JobGeom &g, bool f64, const double *uvw, const void *vis,
                  const void *wts, const uint8_t *flags, uint8_t *mask, ImgState *st,
                  hipStream_t s);
 void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s);
-// bin counts per (image, plane, tile); n_used and sum_w
+// bin counts per (image, plane, tile); n_used and sum_w; the per-stretch tables
+// tab [stretch][kTab] and tab_n [stretch]
 void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
-                  const uint8_t *mask, ImgState *st, uint32_t *counts, hipStream_t s);
+                  const uint8_t *mask, ImgState *st, uint32_t *cls_counts, int n_cls,
+                  TabEntry *tab, uint32_t *tab_n, hipStream_t s);
+// counts[bin] = sum over classes (counts[n_bins] = 0)
+void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
+                         hipStream_t s);
+// cls_cursor[c][bin] = offsets[bin] + records of classes < c in the bin
+void launch_class_cursors(const uint32_t *cls_counts, int n_cls, size_t n_bins,
+                          const uint32_t *offsets, uint32_t *cls_cursor, hipStream_t s);
 // exclusive scan of n entries (u32) into out; tmp holds >= scan_tmp_elems(n) u32
 size_t scan_tmp_elems(size_t n);
 void launch_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp, hipStream_t s);
@@ -108,8 +136,9 @@ void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t 
                      size_t n_bins, hipStream_t s);
 // records beyond `capacity` are not written; each such slot increments *overflow
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
-                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cursor,
-                    void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s);
+                    bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cls_cursor,
+                    int n_cls, const TabEntry *tab, const uint32_t *tab_n, void *records,
+                    uint32_t capacity, uint32_t *overflow, hipStream_t s);
 void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]

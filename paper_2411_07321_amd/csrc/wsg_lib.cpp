@@ -183,6 +183,10 @@ struct Plan {
         o_stack, o_image,
         o_aux, fixed_bytes;
     size_t records_est, items_est;
+    int64_t P, n_t, n_tb, n_stretch;   // binning traversal (see JobGeom)
+    int n_cls;                         // atomic classes of the binning passes
+    size_t o_cls_counts;
+    size_t o_tab, o_tabn;
 };
 
 Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image_out,
@@ -215,11 +219,19 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image
     size_t nb1 = pl.n_bins + 1;
     pl.o_counts = take(nb1 * 4);
     pl.o_offsets = take(nb1 * 4);
-    pl.o_cursor = take(nb1 * 4);
+    pl.n_cls = binning_classes(pl.n_bins);
+    pl.o_cls_counts = take((size_t)pl.n_cls * pl.n_bins * 4);
+    pl.o_cursor = take((size_t)pl.n_cls * pl.n_bins * 4);
     pl.o_nchunk = take(nb1 * 4);
     pl.o_itemoff = take(nb1 * 4);
     pl.o_scan = take(scan_tmp_elems(nb1) * 4);
     pl.o_tot = take(16);
+    pl.P = (v->row_period > 1 && v->row_period <= pl.n_rows) ? v->row_period : 1;
+    pl.n_t = pl.n_rows > 0 ? (pl.n_rows + pl.P - 1) / pl.P : 0;
+    pl.n_tb = (pl.n_t + kStretch - 1) / kStretch;
+    pl.n_stretch = stretch_threads(v->n_chan, pl.P, pl.n_tb);
+    pl.o_tab = take((size_t)pl.n_stretch * kTab * sizeof(TabEntry));
+    pl.o_tabn = take((size_t)pl.n_stretch * 4);
     {
         const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.n_pl;
         pl.o_occ_rows = take(np * nw * 8);
@@ -475,17 +487,11 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     g.w_min_given = p->w_min;
     g.w_max_given = p->w_max;
     g.chan_scale = (const double *)(fx + pl.o_scale);
-    // track traversal: P = row period (1 without the hint), L time slices per thread,
-    // about 2^20 threads in all
-    g.P = (v->row_period > 1 && v->row_period <= pl.n_rows) ? v->row_period : 1;
-    g.n_t = pl.n_rows > 0 ? (pl.n_rows + g.P - 1) / g.P : 0;
-    {
-        int64_t lanes = g.P * (int64_t)v->n_chan;
-        int64_t want = (int64_t)1 << 20;
-        int64_t L = (g.n_t * lanes + want - 1) / want;
-        g.L = std::max<int64_t>(1, std::min<int64_t>(L, std::max<int64_t>(g.n_t, 1)));
-        g.n_tb = g.n_t > 0 ? (g.n_t + g.L - 1) / g.L : 0;
-    }
+    // track traversal: P = row period (1 without the hint), kStretch time slices
+    // per thread
+    g.P = pl.P;
+    g.n_t = pl.n_t;
+    g.n_tb = pl.n_tb;
 
     b.st = (ImgState *)(fx + pl.o_state);
     b.counts = (uint32_t *)(fx + pl.o_counts);
@@ -514,19 +520,23 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     WSG_HIP(ctx, hipMemcpyAsync(b.st, (char *)ctx->pin + align_up((size_t)v->n_chan * 8),
                                 init.size() * sizeof(ImgState), hipMemcpyHostToDevice, s));
     WSG_HIP(ctx, hipEventRecord(ctx->pin_done, s));
-    WSG_HIP(ctx, hipMemsetAsync(b.counts, 0, (pl.n_bins + 1) * 4, s));
+    uint32_t *cls_counts = (uint32_t *)(fx + pl.o_cls_counts);
+    WSG_HIP(ctx, hipMemsetAsync(cls_counts, 0, (size_t)pl.n_cls * pl.n_bins * 4, s));
 
     launch_prep(g, pl.f64, b.uvw, b.vis, b.wts, b.flags, mask, b.st, s);
     launch_finalize_range(g, b.st, s);
     mark(ctx, kMarkPrep, s);
-    launch_count(g, b.uvw, b.wts, pl.f64, mask, b.st, b.counts, s);
+    TabEntry *tab = (TabEntry *)(fx + pl.o_tab);
+    uint32_t *tab_n = (uint32_t *)(fx + pl.o_tabn);
+    launch_count(g, b.uvw, b.wts, pl.f64, mask, b.st, cls_counts, pl.n_cls, tab, tab_n, s);
+    launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, s);
     launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
     // offsets over n_bins + 1 entries: the last one is the record total
     launch_scan(b.counts, b.offsets, pl.n_bins + 1, scan_tmp, s);
     launch_chunks(b.counts, b.nchunk, pl.n_bins, kChunk, s);
     WSG_HIP(ctx, hipMemsetAsync(b.nchunk + pl.n_bins, 0, 4, s));
     launch_scan(b.nchunk, b.itemoff, pl.n_bins + 1, scan_tmp, s);
-    WSG_HIP(ctx, hipMemcpyAsync(b.cursor, b.offsets, (pl.n_bins + 1) * 4, hipMemcpyDeviceToDevice, s));
+    launch_class_cursors(cls_counts, pl.n_cls, pl.n_bins, b.offsets, b.cursor, s);
     // totals: records = offsets[n_bins], items = itemoff[n_bins]
     uint32_t *tot = (uint32_t *)(fx + pl.o_tot);
     WSG_HIP(ctx, hipMemcpyAsync(tot, b.offsets + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
@@ -550,8 +560,8 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
     b.overflow = tot + 2;
     WSG_HIP(ctx, hipMemsetAsync(b.overflow, 0, 4, s));
-    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, b.records, b.n_records,
-                   b.overflow, s);
+    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, pl.n_cls, tab, tab_n, b.records,
+                   b.n_records, b.overflow, s);
     mark(ctx, kMarkScatter, s);
     return WSG_OK;
 }
