@@ -118,13 +118,19 @@ typedef struct {
     int64_t n_used, n_flagged, n_dropped;
     int64_t n_records;       /* binning records of the whole job: one per (visibility, uv     */
                              /*   tile its footprint touches)                                 */
+    int64_t n_tiles;         /* wsg_image: (plane, uv tile) cells of this image's w-stack     */
+                             /*   that received visibilities; the rest are never written or   */
+                             /*   read (0 from the stage entry points)                        */
+    int64_t n_tile_rows;     /* wsg_image: (plane, tile row) pairs with such a tile           */
     double sum_w, w_min, w_max;
     /* device time in ms between hipEvents recorded on the job's stream, filled when
      * timing is on (wsg_set_timing); all 0 otherwise.  The stages are: staging of
      * host inputs and the validity pass; counting and scans; record scatter;
-     * gridding; transform pass 1; transform pass 2 with w-correction and plane sum.
-     * ms_total spans the whole call, host waits included. */
-    float ms_prep, ms_count, ms_scatter, ms_grid, ms_fft1, ms_fft2_wcorr, ms_total;
+     * clearing of split tiles; gridding (the gridding kernel alone); the tile
+     * occupancy pass; transform pass 1; transform pass 2 with w-correction and
+     * plane sum.  ms_total spans the whole call, host waits included. */
+    float ms_prep, ms_count, ms_scatter, ms_zero, ms_grid, ms_occupancy, ms_fft1, ms_fft2_wcorr,
+        ms_total;
 } wsg_stats;
 
 /* ---------------------------------------------------------------------------

@@ -279,7 +279,8 @@ __global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const ui
 __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__restrict__ counts,
                                                    uint64_t *__restrict__ rows,
                                                    uint32_t *__restrict__ live1,
-                                                   uint16_t *__restrict__ live2, int nw) {
+                                                   uint16_t *__restrict__ live2, ImgState *st,
+                                                   int nw) {
     __shared__ unsigned long long s_tiles[256 * 4];   // [tx][word], NT <= 256
     __shared__ unsigned long long s_rows[4];
     const int pi = blockIdx.x;
@@ -299,6 +300,14 @@ __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__
     }
     __syncthreads();
     if ((int)threadIdx.x < nw) rows[(size_t)pi * nw + threadIdx.x] = s_rows[threadIdx.x];
+    if (threadIdx.x == 0) {
+        unsigned long long nt = 0, nr = 0;
+        for (int i = 0; i < NT * nw; ++i) nt += __popcll(s_tiles[i]);
+        for (int i = 0; i < nw; ++i) nr += __popcll(s_rows[i]);
+        const int img = pi / g.n_pl;
+        if (nt) atomicAdd(&st[img].n_tiles, nt);
+        if (nr) atomicAdd(&st[img].n_tile_rows, nr);
+    }
     for (int idx = threadIdx.x; idx < NT * P; idx += blockDim.x) {
         const int tx = idx / P, t = idx - tx * P;
         uint32_t m1 = (uint32_t)((s_rows[tx >> 6] >> (tx & 63)) & 1ull) << 16;
@@ -385,10 +394,10 @@ void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint3
 int occupancy_words(int NT) { return (NT + 63) / 64; }
 
 void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
-                      uint16_t *live2, hipStream_t s) {
+                      uint16_t *live2, ImgState *st, hipStream_t s) {
     const unsigned n_planes = (unsigned)(g.n_img * g.n_pl);
     if (n_planes == 0) return;
-    k_occupancy<<<n_planes, 256, 0, s>>>(g, counts, rows, live1, live2, occupancy_words(g.NT));
+    k_occupancy<<<n_planes, 256, 0, s>>>(g, counts, rows, live1, live2, st, occupancy_words(g.NT));
 }
 
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,

@@ -61,6 +61,7 @@ struct ImgState {
     double w_min, w_max, dw;                 // plane geometry used by the job
     double inv_dw;                           // 1/dw (0 when dw = 0)
     double inv_norm;                         // 1/sum_w (or 1, or 0 for an empty image)
+    unsigned long long n_tiles, n_tile_rows; // occupied (plane, tile) / (plane, tile-row)
 };
 
 // Everything the binning and gridding kernels need about one job.
@@ -163,7 +164,7 @@ struct Occupancy {
 };
 int occupancy_words(int NT);
 void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
-                      uint16_t *live2, hipStream_t s);
+                      uint16_t *live2, ImgState *st, hipStream_t s);
 // Clear the tiles of split bins (their chunks add with atomics) and, with
 // zero_empty, those of empty bins (which have no work item).
 void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,

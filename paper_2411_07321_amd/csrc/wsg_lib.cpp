@@ -59,7 +59,7 @@ struct wsg_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // stage timing: events recorded at the stage boundaries of wsg_image
     int timing = 0;
-    hipEvent_t tev[8] = {};
+    hipEvent_t tev[10] = {};
     hipStream_t last_stream = nullptr;   // stream of the previous call (arena users);
     bool has_last = false;               // NULL is a real stream (the null stream)
 };
@@ -395,7 +395,10 @@ int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
 }
 
 // stage boundary marks (no-ops unless timing is on)
-enum { kMarkStart = 0, kMarkPrep, kMarkCount, kMarkScatterStart, kMarkScatter, kMarkGrid, kMarkFft1, kMarkEnd };
+enum {
+    kMarkStart = 0, kMarkPrep, kMarkCount, kMarkScatterStart, kMarkScatter, kMarkZero, kMarkGrid,
+    kMarkOcc, kMarkFft1, kMarkEnd, kMarks
+};
 
 void mark(wsg_ctx *ctx, int i, hipStream_t s) {
     if (ctx->timing) (void)hipEventRecord(ctx->tev[i], s);
@@ -571,11 +574,15 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
 wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, bool dense,
                        hipStream_t s) {
     launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, dense, grid, transposed, s);
-    if (!dense)
-        launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
-                         (uint32_t *)(b.fx + b.pl.o_occ_live1), (uint16_t *)(b.fx + b.pl.o_occ_live2), s);
+    mark(ctx, kMarkZero, s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
                 b.records, grid, transposed, s);
+    mark(ctx, kMarkGrid, s);
+    if (!dense)
+        launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
+                         (uint32_t *)(b.fx + b.pl.o_occ_live1), (uint16_t *)(b.fx + b.pl.o_occ_live2),
+                         b.st, s);
+    mark(ctx, kMarkOcc, s);
     WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
 }
@@ -591,14 +598,15 @@ wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream
         if (*(const uint32_t *)ctx->pin != 0)
             return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
     }
-    float t[7] = {0, 0, 0, 0, 0, 0, 0};
+    float t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (timed) {
         WSG_HIP(ctx, hipEventSynchronize(ctx->tev[kMarkEnd]));
-        const int pairs[7][2] = {{kMarkStart, kMarkPrep}, {kMarkPrep, kMarkCount},
-                                 {kMarkScatterStart, kMarkScatter}, {kMarkScatter, kMarkGrid},
-                                 {kMarkGrid, kMarkFft1}, {kMarkFft1, kMarkEnd},
+        const int pairs[9][2] = {{kMarkStart, kMarkPrep}, {kMarkPrep, kMarkCount},
+                                 {kMarkScatterStart, kMarkScatter}, {kMarkScatter, kMarkZero},
+                                 {kMarkZero, kMarkGrid}, {kMarkGrid, kMarkOcc},
+                                 {kMarkOcc, kMarkFft1}, {kMarkFft1, kMarkEnd},
                                  {kMarkStart, kMarkEnd}};
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 9; ++i)
             WSG_HIP(ctx, hipEventElapsedTime(&t[i], ctx->tev[pairs[i][0]], ctx->tev[pairs[i][1]]));
     }
     size_t bytes = (size_t)b.pl.n_img * sizeof(ImgState);
@@ -613,16 +621,20 @@ wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream
         stats[i].n_flagged = (int64_t)hs[i].n_flagged;
         stats[i].n_dropped = per_img - stats[i].n_used - stats[i].n_flagged;
         stats[i].n_records = (int64_t)b.n_records;
+        stats[i].n_tiles = (int64_t)hs[i].n_tiles;
+        stats[i].n_tile_rows = (int64_t)hs[i].n_tile_rows;
         stats[i].sum_w = hs[i].sum_w;
         stats[i].w_min = hs[i].w_min;
         stats[i].w_max = hs[i].w_max;
         stats[i].ms_prep = t[0];
         stats[i].ms_count = t[1];
         stats[i].ms_scatter = t[2];
-        stats[i].ms_grid = t[3];
-        stats[i].ms_fft1 = t[4];
-        stats[i].ms_fft2_wcorr = t[5];
-        stats[i].ms_total = t[6];
+        stats[i].ms_zero = t[3];
+        stats[i].ms_grid = t[4];
+        stats[i].ms_occupancy = t[5];
+        stats[i].ms_fft1 = t[6];
+        stats[i].ms_fft2_wcorr = t[7];
+        stats[i].ms_total = t[8];
     }
     return WSG_OK;
 }
@@ -658,7 +670,6 @@ wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *im
     if (rc) return rc;
     rc = grid_binned(ctx, b, stack, true, false, s);
     if (rc) return rc;
-    mark(ctx, kMarkGrid, s);
     Occupancy occ;
     occ.rows = (const uint64_t *)(b.fx + pl.o_occ_rows);
     occ.live1 = (const uint32_t *)(b.fx + pl.o_occ_live1);

@@ -54,10 +54,12 @@ class Vis(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n_used", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
                 ("n_dropped", ctypes.c_int64), ("n_records", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("n_tile_rows", ctypes.c_int64),
                 ("sum_w", ctypes.c_double),
                 ("w_min", ctypes.c_double), ("w_max", ctypes.c_double),
                 ("ms_prep", ctypes.c_float), ("ms_count", ctypes.c_float),
-                ("ms_scatter", ctypes.c_float), ("ms_grid", ctypes.c_float),
+                ("ms_scatter", ctypes.c_float), ("ms_zero", ctypes.c_float),
+                ("ms_grid", ctypes.c_float), ("ms_occupancy", ctypes.c_float),
                 ("ms_fft1", ctypes.c_float), ("ms_fft2_wcorr", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
 
