@@ -91,10 +91,11 @@ __device__ __forceinline__ bool is_finite(double a) { return isfinite(a); }
 template <typename VT>
 __device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, const void *vis,
                                        const void *wts, const uint8_t *flags, int64_t e,
-                                       int64_t r, int c, bool &flagged, double &w_out) {
+                                       int64_t r, int c, bool &flagged, double &w_out,
+                                       double &wt) {
     flagged = flags && flags[e];
     if (flagged) return false;
-    double vr, vi, wt;
+    double vr, vi;
     ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
     if (!(wt > 0.0) || !is_finite(wt)) return false;
     double sc = g.chan_scale[c];
@@ -130,25 +131,29 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
                                                    const void *__restrict__ wts,
                                                    const uint8_t *__restrict__ flags,
                                                    uint8_t *__restrict__ mask, ImgState *st) {
-    __shared__ unsigned long long s_min[256], s_max[256], s_flag[256], s_valid[256];
+    __shared__ unsigned long long s_min[256], s_max[256], s_flag[256], s_valid[256], s_used[256];
+    __shared__ double s_sumw[256];
     const int n_img = g.n_img;
     for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
         s_min[i] = ~0ull;
         s_max[i] = 0ull;
         s_flag[i] = 0;
         s_valid[i] = 0;
+        s_used[i] = 0;
+        s_sumw[i] = 0.0;
     }
     __syncthreads();
     const int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long kmin = ~0ull, kmax = 0ull, nf = 0, nv = 0;
+    unsigned long long kmin = ~0ull, kmax = 0ull, nf = 0, nv = 0, nu = 0;
+    double sw = 0.0;
     const int c = (int)(e0 % g.n_chan);
     for (int64_t e = e0; e < n_elem; e += stride) {
         int64_t r = e / g.n_chan;
         bool fl;
-        double w;
-        bool ok = valid0<VT>(g, uvw, vis, wts, flags, e, r, c, fl, w);
+        double w, wt;
+        bool ok = valid0<VT>(g, uvw, vis, wts, flags, e, r, c, fl, w, wt);
         mask[e] = ok ? 1 : 0;
         nf += fl ? 1 : 0;
         if (ok) {
@@ -156,6 +161,12 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
             unsigned long long k = order_key(w);
             kmin = k < kmin ? k : kmin;
             kmax = k > kmax ? k : kmax;
+            // used: valid and inside the w range (the data's own range holds every
+            // valid visibility; a given range may not)
+            if (!g.range_given || (w >= g.w_min_given && w <= g.w_max_given)) {
+                ++nu;
+                sw += wt;
+            }
         }
     }
     const int img = (n_img > 1) ? c : 0;
@@ -168,18 +179,24 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
             kmax = b > kmax ? b : kmax;
             nf += __shfl_xor(nf, off);
             nv += __shfl_xor(nv, off);
+            nu += __shfl_xor(nu, off);
+            sw += __shfl_xor(sw, off);
         }
         if ((threadIdx.x & 63) == 0) {
             atomicMin(&s_min[0], kmin);
             atomicMax(&s_max[0], kmax);
             atomicAdd(&s_flag[0], nf);
             atomicAdd(&s_valid[0], nv);
+            atomicAdd(&s_used[0], nu);
+            atomicAdd(&s_sumw[0], sw);
         }
     } else {
         atomicMin(&s_min[img], kmin);
         atomicMax(&s_max[img], kmax);
         atomicAdd(&s_flag[img], nf);
         atomicAdd(&s_valid[img], nv);
+        atomicAdd(&s_used[img], nu);
+        atomicAdd(&s_sumw[img], sw);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n_img; i += blockDim.x) {
@@ -187,6 +204,10 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
             atomicMin(&st[i].wmin_key, s_min[i]);
             atomicMax(&st[i].wmax_key, s_max[i]);
             atomicAdd(&st[i].n_valid0, s_valid[i]);
+        }
+        if (s_used[i]) {
+            atomicAdd(&st[i].n_used, s_used[i]);
+            atomicAdd(&st[i].sum_w, s_sumw[i]);
         }
         if (s_flag[i]) atomicAdd(&st[i].n_flagged, s_flag[i]);
     }
@@ -267,58 +288,6 @@ struct Keys {
     uint32_t k[4];
 };
 
-template <typename VT>
-__device__ __forceinline__ void write_record(void *records, uint32_t slot, const JobGeom &g,
-                                             const Placed &pl, uint32_t key, double vr, double vi,
-                                             double wt) {
-    uint32_t t = key & ((1u << (2 * g.logNT)) - 1u);
-    int ty = (int)(t >> g.logNT), tx = (int)(t & (uint32_t)(g.NT - 1));
-    double fx = pl.x - (double)pl.i0;
-    double fy = pl.y - (double)pl.j0;
-    if constexpr (sizeof(VT) == 8) {
-        RecF64 rec;
-        rec.fx = fx;
-        rec.fy = fy;
-        rec.re = wt * vr;
-        rec.im = wt * vi;
-        rec.li = pl.i0 - (tx << g.logT);
-        rec.lj = pl.j0 - (ty << g.logT);
-        ((RecF64 *)records)[slot] = rec;
-    } else {
-        uint32_t qx = (uint32_t)fmin((fx + 0.5) * 16777216.0 + 0.5, 16777215.0);
-        uint32_t qy = (uint32_t)fmin((fy + 0.5) * 16777216.0 + 0.5, 16777215.0);
-        RecF32 rec;
-        rec.px = ((uint32_t)(pl.i0 - (tx << g.logT) + g.h) << kFracBits) | qx;
-        rec.py = ((uint32_t)(pl.j0 - (ty << g.logT) + g.h) << kFracBits) | qy;
-        rec.re = (float)wt * (float)vr;
-        rec.im = (float)wt * (float)vi;
-        ((RecF32 *)records)[slot] = rec;
-    }
-}
-
-// One binning thread: kStretch consecutive time slices of the track of baseline
-// b (rows t*P + b) in channel c.  Consecutive threads take consecutive channels,
-// then baselines, so that the loads of a wave fall on neighbouring rows.
-struct Stretch {
-    int c;
-    int64_t b, t0, t_end;   // time slices [t0, t_end)
-    bool ok;
-};
-
-__device__ __forceinline__ Stretch stretch_of(const JobGeom &g, int64_t idx) {
-    Stretch sr;
-    sr.c = (int)(idx % g.n_chan);
-    const int64_t rest = idx / g.n_chan;
-    sr.b = rest % g.P;
-    const int64_t tb = rest / g.P;
-    sr.ok = tb < g.n_tb;
-    sr.t0 = tb * kStretch;
-    int64_t t1 = min(g.n_t, sr.t0 + kStretch);
-    // the last time slice may be short of P rows
-    if (sr.ok && t1 > sr.t0 && (t1 - 1) * g.P + sr.b >= g.n_rows) t1 = (g.n_rows - 1 - sr.b) / g.P + 1;
-    sr.t_end = sr.ok ? max(t1, sr.t0) : sr.t0;
-    return sr;
-}
 
 constexpr uint32_t kNoKey = 0xffffffffu;
 
@@ -345,237 +314,269 @@ __device__ __forceinline__ void unpack_keys(uint32_t pk, int NT, Keys &ks) {
     ks.n = pk == kNoKey ? 0 : (cx && cy) ? 4 : (cx || cy) ? 2 : 1;
 }
 
+// Binning works on tiles of kBinStretches stretches (kStretch = 64 consecutive
+// time slices of one (baseline, channel) track each) per workgroup.
+//   Phase A reads the tile coalesced: consecutive threads take consecutive
+//   stretches of one time slice, which are neighbouring elements in memory.
+//   Each element leaves its packed bins (and, for the scatter, the parts of its
+//   record that do not depend on the tile) in LDS.
+//   Phase B gives each wave whole stretches, one time slice per lane: the
+//   elements of a stretch that share a bin are counted with one ballot and get
+//   one atomic, and their records take consecutive slots, in time order,
+//   written by consecutive lanes.
+// Consecutive workgroups run on one XCD, so rows they share meet in its L2.
 constexpr int kBinThreads = 256;
+constexpr int kBinStretches = 16;
+constexpr int kPitch = kBinStretches + 1;              // LDS row pitch (no bank conflicts)
+constexpr int kTileElems = kStretch * kPitch;
+constexpr int kPerThread = kStretch * kBinStretches / kBinThreads;   // 4
+constexpr int kPerWave = kBinStretches / (kBinThreads / 64);         // 4
 
-// Counting pass.  Along its stretch a thread tracks runs of elements with the
-// same packed bins (a track moves slowly, so runs are long) and adds each run to
-// its private table of (bin, records) in LDS; a table that would exceed kTab
-// bins sends the rest of the stretch's runs straight to the global counts.  At
-// the end the table goes to `counts` (one atomic per entry) and, for the
-// scatter, to tab / tab_n.
-template <bool F64W>
-__global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
-                                                       const void *__restrict__ wts,
-                                                       const uint8_t *__restrict__ mask,
-                                                       ImgState *st, uint32_t *__restrict__ cls_counts,
-                                                       int n_cls, TabEntry *__restrict__ tab,
-                                                       uint32_t *__restrict__ tab_n) {
-    __shared__ uint32_t s_tb[kTab][kBinThreads];
-    __shared__ uint32_t s_tc[kTab][kBinThreads];
-    __shared__ unsigned long long s_used[256];
-    __shared__ double s_sumw[256];
-    const int n_img = g.n_img;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < n_img; i += blockDim.x) {
-        s_used[i] = 0;
-        s_sumw[i] = 0.0;
-    }
-    __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
-    const Stretch sr = stretch_of(g, idx);
-    const int img = (n_img > 1) ? sr.c : 0;
-    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
-    uint32_t *counts = cls_counts + (size_t)(blockIdx.x % (unsigned)n_cls) * n_bins;
-    unsigned long long nu = 0;
-    double sw = 0.0;
-    if (sr.ok) {
-        const ImgState s = st[img];
-        const double sc = g.chan_scale[sr.c];
-        int n_ent = 0;
-        bool ovf = false;
-        uint32_t cur = kNoKey, run = 0;
-        bool cur_tab = false;
-        Keys cks;
-        cks.n = 0;
-        int ent[4] = {0, 0, 0, 0};
-        for (int64_t t0b = sr.t0; t0b < sr.t_end; t0b += kBatch) {
-            // the loads of kBatch elements are issued together
-            uint8_t mb[kBatch];
-            double ub[kBatch], vb[kBatch], wb[kBatch], wtb[kBatch];
+__device__ __forceinline__ int64_t bin_block(int64_t bid, int64_t n_blocks) {
+    // workgroups are dealt to the 8 XCDs round robin
+    constexpr int kXcd = 8;
+    if (n_blocks % kXcd) return bid;
+    return (bid % kXcd) * (n_blocks / kXcd) + bid / kXcd;
+}
+
+struct Slice {
+    int c;
+    int64_t r, e;   // row and element of one time slice of one stretch
+    bool ok;
+};
+
+__device__ __forceinline__ Slice slice_of(const JobGeom &g, int64_t stretch, int t_in) {
+    Slice sl;
+    sl.c = (int)(stretch % g.n_chan);
+    const int64_t rest = stretch / g.n_chan;
+    const int64_t b = rest % g.P;
+    const int64_t tb = rest / g.P;
+    const int64_t t = tb * kStretch + t_in;
+    sl.r = t * g.P + b;
+    sl.ok = tb < g.n_tb && t < g.n_t && sl.r < g.n_rows;
+    sl.e = sl.r * g.n_chan + sl.c;
+    return sl;
+}
+
+// phase-A slot q of a workgroup: time slice and stretch within the tile
+__device__ __forceinline__ void tile_slot(int q, int &t, int &s) {
+    t = q / kBinStretches;
+    s = q - t * kBinStretches;
+}
+
+// For every bin among the lanes' keys (0 to 4 per lane, none repeated within a
+// lane): f(bin, lanes holding it, leader lane, this lane holds it).  Every lane
+// takes every step (the ballots and shuffles need the whole wave).
+template <typename F>
+__device__ __forceinline__ void for_each_bin(const Keys &ks, F &&f) {
+    unsigned done = 0u;
+    for (;;) {
+        int first = -1;
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t t = min(t0b + j, sr.t_end - 1);
-                const int64_t r = t * g.P + sr.b;
-                const int64_t e = r * g.n_chan + sr.c;
-                mb[j] = (t0b + j < sr.t_end) ? mask[e] : 0;
-                ub[j] = uvw[3 * r];
-                vb[j] = uvw[3 * r + 1];
-                wb[j] = uvw[3 * r + 2];
-                wtb[j] = wts ? (F64W ? ((const double *)wts)[e] : (double)((const float *)wts)[e]) : 1.0;
-            }
+        for (int i = 3; i >= 0; --i)
+            if (i < ks.n && !((done >> i) & 1u)) first = i;
+        const unsigned long long hm = __ballot(first >= 0);
+        if (hm == 0ull) break;
+        const int leader = __ffsll((long long)hm) - 1;
+        uint32_t cand = 0u;
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                Placed pl;
-                uint32_t pk = kNoKey;
-                if (mb[j] && place_vals(g, s, ub[j], vb[j], wb[j], sc, pl)) {
-                    ++nu;
-                    sw += wtb[j];
-                    pk = pack_placed(g, img, pl);
-                }
-                if (pk != cur) {
-                    // close the run of `cur`
-                    if (run) {
+        for (int i = 0; i < 4; ++i)
+            if (i == first) cand = ks.k[i];
+        const uint32_t bin = (uint32_t)__shfl((int)cand, leader);
+        int hit = -1;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if (i >= cks.n) continue;
-                            if (cur_tab) s_tc[ent[i]][lane] += run;
-                            else atomicAdd(&counts[cks.k[i]], run);
-                        }
-                    }
-                    // open a run of `pk`: its bins in the table, added when missing
-                    cur = pk;
-                    run = 0;
-                    unpack_keys(pk, g.NT, cks);
-                    cur_tab = !ovf;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (i >= cks.n || !cur_tab) continue;
-                        int f = -1;
-                        for (int e = 0; e < n_ent; ++e)
-                            if (s_tb[e][lane] == cks.k[i]) f = e;
-                        if (f < 0) {
-                            if (n_ent < kTab) {
-                                f = n_ent++;
-                                s_tb[f][lane] = cks.k[i];
-                                s_tc[f][lane] = 0u;
-                            } else {
-                                ovf = true;
-                                cur_tab = false;
-                            }
-                        }
-                        ent[i] = f;
-                    }
-                }
-                if (pk != kNoKey) ++run;
-            }
-        }
-        if (run) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (i >= cks.n) continue;
-                if (cur_tab) s_tc[ent[i]][lane] += run;
-                else atomicAdd(&counts[cks.k[i]], run);
-            }
-        }
-        for (int e = 0; e < n_ent; ++e) {
-            const uint32_t bin = s_tb[e][lane], n = s_tc[e][lane];
-            if (n) atomicAdd(&counts[bin], n);
-            tab[idx * kTab + e] = TabEntry{bin, n};
-        }
-        tab_n[idx] = ovf ? kTabOverflow : (uint32_t)n_ent;
-    }
-    if (n_img == 1) {
-        for (int off = 32; off > 0; off >>= 1) {
-            nu += __shfl_xor(nu, off);
-            sw += __shfl_xor(sw, off);
-        }
-        if ((lane & 63) == 0) {
-            atomicAdd(&s_used[0], nu);
-            atomicAdd(&s_sumw[0], sw);
-        }
-    } else if (sr.ok) {
-        atomicAdd(&s_used[img], nu);
-        atomicAdd(&s_sumw[img], sw);
-    }
-    __syncthreads();
-    for (int i = lane; i < n_img; i += blockDim.x) {
-        if (s_used[i]) {
-            atomicAdd(&st[i].n_used, s_used[i]);
-            atomicAdd(&st[i].sum_w, s_sumw[i]);
-        }
+        for (int i = 0; i < 4; ++i)
+            if (i < ks.n && !((done >> i) & 1u) && ks.k[i] == bin) hit = i;
+        const unsigned long long m = __ballot(hit >= 0);
+        f(bin, m, leader, hit >= 0);
+        if (hit >= 0) done |= 1u << hit;
     }
 }
 
-// Scatter.  A thread reserves, for each (bin, records) pair its stretch left in
-// the table, one range of slots (one atomic on the bin's cursor), then walks the
-// stretch once more and writes each record into the next slot of its bin, so the
-// records of one stretch are contiguous, in time order, inside every bin they
-// reach.  An overflowed stretch reserves record by record.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m, int lane) {
+    return (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// sub-cell offset f in [-1/2, 1/2) as 24-bit fixed point
+__device__ __forceinline__ uint32_t quant_frac(double f) {
+    return (uint32_t)fmin((f + 0.5) * 16777216.0 + 0.5, 16777215.0);
+}
+
+// Counting pass: records per bin, into the workgroup's atomic class.
+__global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
+                                                       const uint8_t *__restrict__ mask,
+                                                       const ImgState *st,
+                                                       uint32_t *__restrict__ cls_counts, int n_cls) {
+    __shared__ uint32_t s_pk[kTileElems];
+    const int64_t blk = bin_block(blockIdx.x, gridDim.x);
+    const int64_t s0 = blk * kBinStretches;
+    // phase A: all loads first
+    Slice sl[kPerThread];
+    uint8_t mk[kPerThread];
+    double u[kPerThread], v[kPerThread], w[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int t, s;
+        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        sl[k] = slice_of(g, s0 + s, t);
+        mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
+        const int64_t r = sl[k].ok ? sl[k].r : 0;
+        u[k] = mk[k] ? uvw[3 * r] : 0.0;
+        v[k] = mk[k] ? uvw[3 * r + 1] : 0.0;
+        w[k] = mk[k] ? uvw[3 * r + 2] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int t, s;
+        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        const int img = (g.n_img > 1) ? sl[k].c : 0;
+        uint32_t pk = kNoKey;
+        Placed pl;
+        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl))
+            pk = pack_placed(g, img, pl);
+        s_pk[t * kPitch + s] = pk;
+    }
+    __syncthreads();
+    // phase B
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
+    uint32_t *counts = cls_counts + (size_t)(blk % n_cls) * n_bins;
+    for (int j = 0; j < kPerWave; ++j) {
+        const int s = wave * kPerWave + j;
+        Keys ks;
+        unpack_keys(s_pk[lane * kPitch + s], g.NT, ks);
+        for_each_bin(ks, [&](uint32_t bin, unsigned long long m, int leader, bool) {
+            if (lane == leader) atomicAdd(&counts[bin], (uint32_t)__popcll(m));
+        });
+    }
+}
+
+// Scatter: each bin of a stretch reserves its records' slots with one atomic
+// on the class cursor; the records go to consecutive slots in time order.
+// The LDS holds, per element, the packed bins and the record without its tile:
+// complex64 mesh: 24-bit sub-cell offsets with the cell relative to the lowest
+// tile in the top byte, and W V; complex128 mesh: FP64 offsets, W V and the cell
+// relative to the lowest tile.
+template <typename VT>
+struct ScatterLds;
+template <>
+struct ScatterLds<float> {
+    uint32_t pk[kTileElems], a[kTileElems], b[kTileElems];
+    float re[kTileElems], im[kTileElems];
+};
+template <>
+struct ScatterLds<double> {
+    uint32_t pk[kTileElems], lij[kTileElems];
+    double fx[kTileElems], fy[kTileElems], re[kTileElems], im[kTileElems];
+};
+
 template <typename VT>
 __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
                                                          const void *__restrict__ vis,
                                                          const void *__restrict__ wts,
                                                          const uint8_t *__restrict__ mask,
                                                          const ImgState *st, uint32_t *cls_cursor,
-                                                         int n_cls, const TabEntry *__restrict__ tab,
-                                                         const uint32_t *__restrict__ tab_n,
-                                                         void *__restrict__ records, uint32_t capacity,
-                                                         uint32_t *overflow) {
-    __shared__ uint32_t s_tb[kTab][kBinThreads];
-    __shared__ uint32_t s_tn[kTab][kBinThreads];   // next free slot of the entry's bin
-    const int lane = threadIdx.x;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + lane;
-    const Stretch sr = stretch_of(g, idx);
-    if (!sr.ok) return;   // no barrier below
-    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
-    uint32_t *cursor = cls_cursor + (size_t)(blockIdx.x % (unsigned)n_cls) * n_bins;
-    const int img = (g.n_img > 1) ? sr.c : 0;
-    const ImgState s = st[img];
-    const double sc = g.chan_scale[sr.c];
-    const uint32_t tn = tab_n[idx];
-    const bool ovf = tn == kTabOverflow;
-    const int n_ent = ovf ? 0 : (int)tn;
-    for (int e = 0; e < n_ent; ++e) {
-        const TabEntry te = tab[idx * kTab + e];
-        s_tb[e][lane] = te.bin;
-        s_tn[e][lane] = te.n ? atomicAdd(&cursor[te.bin], te.n) : 0u;
+                                                         int n_cls, void *__restrict__ records,
+                                                         uint32_t capacity, uint32_t *overflow) {
+    __shared__ ScatterLds<VT> L;
+    const int64_t blk = bin_block(blockIdx.x, gridDim.x);
+    const int64_t s0 = blk * kBinStretches;
+    Slice sl[kPerThread];
+    uint8_t mk[kPerThread];
+    double u[kPerThread], v[kPerThread], w[kPerThread], vr[kPerThread], vi[kPerThread], wt[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        int t, s;
+        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        sl[k] = slice_of(g, s0 + s, t);
+        mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
+        const int64_t r = sl[k].ok ? sl[k].r : 0;
+        const int64_t e = sl[k].ok ? sl[k].e : 0;
+        u[k] = mk[k] ? uvw[3 * r] : 0.0;
+        v[k] = mk[k] ? uvw[3 * r + 1] : 0.0;
+        w[k] = mk[k] ? uvw[3 * r + 2] : 0.0;
+        vr[k] = vi[k] = wt[k] = 0.0;
+        if (mk[k]) ElemIO<VT, VT>::load(vis, wts, e, vr[k], vi[k], wt[k]);
     }
-    uint32_t cur = kNoKey;
-    Keys ks;
-    ks.n = 0;
-    int ent[4] = {-1, -1, -1, -1};
-    for (int64_t t0b = sr.t0; t0b < sr.t_end; t0b += kBatch) {
-        uint8_t m[kBatch];
-        double u[kBatch], v[kBatch], w[kBatch], vr[kBatch], vi[kBatch], wt[kBatch];
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int64_t t = min(t0b + j, sr.t_end - 1);
-            const int64_t r = t * g.P + sr.b;
-            const int64_t e = r * g.n_chan + sr.c;
-            m[j] = (t0b + j < sr.t_end) ? mask[e] : 0;
-            u[j] = uvw[3 * r];
-            v[j] = uvw[3 * r + 1];
-            w[j] = uvw[3 * r + 2];
-            ElemIO<VT, VT>::load(vis, wts, e, vr[j], vi[j], wt[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            Placed pl;
-            if (!m[j] || !place_vals(g, s, u[j], v[j], w[j], sc, pl)) continue;
-            const uint32_t pk = pack_placed(g, img, pl);
-            if (pk == kNoKey) continue;
-            if (pk != cur) {
-                cur = pk;
-                unpack_keys(pk, g.NT, ks);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    int f = -1;
-                    if (i < ks.n && !ovf)
-                        for (int e = 0; e < n_ent; ++e)
-                            if (s_tb[e][lane] == ks.k[i]) f = e;
-                    ent[i] = f;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (i >= ks.n) continue;
-                uint32_t slot;
-                if (ovf) {
-                    slot = atomicAdd(&cursor[ks.k[i]], 1u);
-                } else if (ent[i] >= 0) {
-                    slot = s_tn[ent[i]][lane];
-                    s_tn[ent[i]][lane] = slot + 1u;
-                } else {
-                    slot = capacity;   // the passes disagree: reported below
-                }
-                // the counting pass sized the buffer; a slot beyond it would mean the
-                // two passes disagree: never write there, report it instead
-                if (slot < capacity)
-                    write_record<VT>(records, slot, g, pl, ks.k[i], vr[j], vi[j], wt[j]);
-                else
-                    atomicAdd(overflow, 1u);
+    for (int k = 0; k < kPerThread; ++k) {
+        int t, s;
+        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        const int img = (g.n_img > 1) ? sl[k].c : 0;
+        uint32_t pk = kNoKey;
+        Placed pl;
+        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl))
+            pk = pack_placed(g, img, pl);
+        const int q = t * kPitch + s;
+        L.pk[q] = pk;
+        if (pk != kNoKey) {
+            // cell relative to the lowest tile the footprint reaches
+            const int li0 = pl.i0 - (((pl.i0 - g.h) >> g.logT) << g.logT);
+            const int lj0 = pl.j0 - (((pl.j0 - g.h) >> g.logT) << g.logT);
+            const double fx = pl.x - (double)pl.i0, fy = pl.y - (double)pl.j0;
+            if constexpr (sizeof(VT) == 8) {
+                L.lij[q] = (uint32_t)li0 | ((uint32_t)lj0 << 16);
+                L.fx[q] = fx;
+                L.fy[q] = fy;
+                L.re[q] = wt[k] * vr[k];
+                L.im[q] = wt[k] * vi[k];
+            } else {
+                L.a[q] = quant_frac(fx) | ((uint32_t)li0 << kFracBits);
+                L.b[q] = quant_frac(fy) | ((uint32_t)lj0 << kFracBits);
+                L.re[q] = (float)wt[k] * (float)vr[k];
+                L.im[q] = (float)wt[k] * (float)vi[k];
             }
         }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
+    uint32_t *cursor = cls_cursor + (size_t)(blk % n_cls) * n_bins;
+    const uint32_t tmask = (1u << (2 * g.logNT)) - 1u;
+    for (int j = 0; j < kPerWave; ++j) {
+        const int s = wave * kPerWave + j;
+        const int q = lane * kPitch + s;
+        const uint32_t pk = L.pk[q];
+        Keys ks;
+        unpack_keys(pk, g.NT, ks);
+        const uint32_t tb0 = pk & tmask;   // lowest tile of the footprint
+        const int tx0 = (int)(tb0 & (uint32_t)(g.NT - 1)), ty0 = (int)(tb0 >> g.logNT);
+        for_each_bin(ks, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
+            uint32_t base = 0u;
+            if (lane == leader) base = atomicAdd(&cursor[bin], (uint32_t)__popcll(m));
+            base = (uint32_t)__shfl((int)base, leader);
+            if (!mine) return;
+            const uint32_t slot = base + lanes_below(m, lane);
+            // the counting pass sized the buffer; a slot beyond it would mean the
+            // two passes disagree: never write there, report it instead
+            if (slot >= capacity) {
+                atomicAdd(overflow, 1u);
+                return;
+            }
+            const uint32_t tt = bin & tmask;
+            const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
+            if constexpr (sizeof(VT) == 8) {
+                const uint32_t lij = L.lij[q];
+                RecF64 rec;
+                rec.fx = L.fx[q];
+                rec.fy = L.fy[q];
+                rec.re = L.re[q];
+                rec.im = L.im[q];
+                rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
+                rec.lj = (int)(lij >> 16) - (dy << g.logT);
+                ((RecF64 *)records)[slot] = rec;
+            } else {
+                const uint32_t a = L.a[q], b = L.b[q];
+                RecF32 rec;
+                rec.px = (((a >> kFracBits) - ((uint32_t)dx << g.logT) + (uint32_t)g.h) << kFracBits) |
+                         (a & 0xffffffu);
+                rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
+                         (b & 0xffffffu);
+                rec.re = L.re[q];
+                rec.im = L.im[q];
+                ((RecF32 *)records)[slot] = rec;
+            }
+        });
     }
 }
 
@@ -681,16 +682,16 @@ int64_t stretch_threads(int64_t n_chan, int64_t P, int64_t n_tb) { return n_chan
 
 int binning_classes(size_t n_bins) { return n_bins <= ((size_t)1 << 22) ? kMaxClasses : 1; }
 
-void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
-                  const uint8_t *mask, ImgState *st, uint32_t *cls_counts, int n_cls,
-                  TabEntry *tab, uint32_t *tab_n, hipStream_t s) {
+static unsigned binning_blocks(const JobGeom &g) {
     const int64_t n = stretch_threads(g.n_chan, g.P, g.n_tb);
-    if (n == 0) return;
-    const unsigned blocks = (unsigned)((n + kBinThreads - 1) / kBinThreads);
-    if (f64)
-        k_count<true><<<blocks, kBinThreads, 0, s>>>(g, uvw, wts, mask, st, cls_counts, n_cls, tab, tab_n);
-    else
-        k_count<false><<<blocks, kBinThreads, 0, s>>>(g, uvw, wts, mask, st, cls_counts, n_cls, tab, tab_n);
+    return (unsigned)((n + kBinStretches - 1) / kBinStretches);
+}
+
+void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, const ImgState *st,
+                  uint32_t *cls_counts, int n_cls, hipStream_t s) {
+    const unsigned blocks = binning_blocks(g);
+    if (blocks == 0) return;
+    k_count<<<blocks, kBinThreads, 0, s>>>(g, uvw, mask, st, cls_counts, n_cls);
 }
 
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
@@ -707,17 +708,15 @@ void launch_class_cursors(const uint32_t *cls_counts, int n_cls, size_t n_bins,
 
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
                     bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cls_cursor,
-                    int n_cls, const TabEntry *tab, const uint32_t *tab_n, void *records,
-                    uint32_t capacity, uint32_t *overflow, hipStream_t s) {
-    const int64_t n = stretch_threads(g.n_chan, g.P, g.n_tb);
-    if (n == 0) return;
-    const unsigned blocks = (unsigned)((n + kBinThreads - 1) / kBinThreads);
+                    int n_cls, void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s) {
+    const unsigned blocks = binning_blocks(g);
+    if (blocks == 0) return;
     if (f64)
         k_scatter<double><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
-                                                         tab, tab_n, records, capacity, overflow);
+                                                         records, capacity, overflow);
     else
         k_scatter<float><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
-                                                        tab, tab_n, records, capacity, overflow);
+                                                        records, capacity, overflow);
 }
 
 size_t scan_tmp_elems(size_t n) {

@@ -83,22 +83,15 @@ struct JobGeom {
     double w_min_given, w_max_given;
     const double *chan_scale;  // device [n_chan]: f/c or 1
     // track traversal of the binning passes: rows are viewed as [n_t][P]
-    // (P = row period, the baselines per time slice); a thread follows one
-    // (baseline, channel) track through kStretch consecutive time slices, the
-    // n_tb stretches of a track being threads of their own
+    // (P = row period, the baselines per time slice); a wave takes one
+    // (baseline, channel) track through kStretch consecutive time slices, a
+    // track having n_tb such stretches
     int64_t P, n_t, n_tb;
 };
 
-// Binning stretch: kStretch time slices of one (baseline, channel) track per
-// thread.  The counting pass leaves, per stretch, a table of up to kTab
-// (bin, records) pairs; the scatter reserves one slot range per pair.  A stretch
-// that touches more than kTab bins is marked kTabOverflow and reserves per record.
+// Binning stretch: kStretch time slices of one (baseline, channel) track, one per
+// lane of a binning wave (the wavefront size).
 constexpr int kStretch = 64;
-constexpr int kTab = 8;
-constexpr uint32_t kTabOverflow = 0xffffffffu;
-struct TabEntry {
-    uint32_t bin, n;
-};
 int64_t stretch_threads(int64_t n_chan, int64_t P, int64_t n_tb);
 // The binning passes spread the atomics on one bin over n_cls classes (the
 // workgroup index mod n_cls): class c counts into cls_counts[c][bin] and the
@@ -111,16 +104,15 @@ int binning_classes(size_t n_bins);
 // ----------------------------------------------------------------------------
 // launchers (each enqueues on `s`; no host synchronisation)
 // ----------------------------------------------------------------------------
-// validity pass: mask[e] = valid except w range; per-image w range and counts
+// validity pass: mask[e] = valid except w range; per-image w range, counts,
+// n_used and sum_w
 void launch_prep(const JobGeom &g, bool f64, const double *uvw, const void *vis,
                  const void *wts, const uint8_t *flags, uint8_t *mask, ImgState *st,
                  hipStream_t s);
 void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s);
-// bin counts per (image, plane, tile); n_used and sum_w; the per-stretch tables
-// tab [stretch][kTab] and tab_n [stretch]
-void launch_count(const JobGeom &g, const double *uvw, const void *wts, bool f64,
-                  const uint8_t *mask, ImgState *st, uint32_t *cls_counts, int n_cls,
-                  TabEntry *tab, uint32_t *tab_n, hipStream_t s);
+// records per (image, plane, tile) bin, per atomic class
+void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, const ImgState *st,
+                  uint32_t *cls_counts, int n_cls, hipStream_t s);
 // counts[bin] = sum over classes (counts[n_bins] = 0)
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
                          hipStream_t s);
@@ -138,8 +130,7 @@ void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t 
 // records beyond `capacity` are not written; each such slot increments *overflow
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
                     bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cls_cursor,
-                    int n_cls, const TabEntry *tab, const uint32_t *tab_n, void *records,
-                    uint32_t capacity, uint32_t *overflow, hipStream_t s);
+                    int n_cls, void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s);
 void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]

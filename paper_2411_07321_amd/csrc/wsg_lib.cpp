@@ -186,7 +186,6 @@ struct Plan {
     int64_t P, n_t, n_tb, n_stretch;   // binning traversal (see JobGeom)
     int n_cls;                         // atomic classes of the binning passes
     size_t o_cls_counts;
-    size_t o_tab, o_tabn;
 };
 
 Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image_out,
@@ -230,8 +229,6 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image
     pl.n_t = pl.n_rows > 0 ? (pl.n_rows + pl.P - 1) / pl.P : 0;
     pl.n_tb = (pl.n_t + kStretch - 1) / kStretch;
     pl.n_stretch = stretch_threads(v->n_chan, pl.P, pl.n_tb);
-    pl.o_tab = take((size_t)pl.n_stretch * kTab * sizeof(TabEntry));
-    pl.o_tabn = take((size_t)pl.n_stretch * 4);
     {
         const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.n_pl;
         pl.o_occ_rows = take(np * nw * 8);
@@ -529,9 +526,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     launch_prep(g, pl.f64, b.uvw, b.vis, b.wts, b.flags, mask, b.st, s);
     launch_finalize_range(g, b.st, s);
     mark(ctx, kMarkPrep, s);
-    TabEntry *tab = (TabEntry *)(fx + pl.o_tab);
-    uint32_t *tab_n = (uint32_t *)(fx + pl.o_tabn);
-    launch_count(g, b.uvw, b.wts, pl.f64, mask, b.st, cls_counts, pl.n_cls, tab, tab_n, s);
+    launch_count(g, b.uvw, mask, b.st, cls_counts, pl.n_cls, s);
     launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, s);
     launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
     // offsets over n_bins + 1 entries: the last one is the record total
@@ -563,7 +558,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
     b.overflow = tot + 2;
     WSG_HIP(ctx, hipMemsetAsync(b.overflow, 0, 4, s));
-    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, pl.n_cls, tab, tab_n, b.records,
+    launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, pl.n_cls, b.records,
                    b.n_records, b.overflow, s);
     mark(ctx, kMarkScatter, s);
     return WSG_OK;
