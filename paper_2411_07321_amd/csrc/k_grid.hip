@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kGridThreads = 256;
 constexpr int kRunCap = 16;
-constexpr int kFlushLanes = 32;
+constexpr int kFlushLanes = 56;
 
 template <typename T>
 struct RecTraits;
@@ -60,6 +60,28 @@ struct RecTraits<double> {
     static __device__ __forceinline__ double gauss(double d, double inv2s2) { return exp(-d * d * inv2s2); }
 };
 
+// G(k - f) for k = -H..H (g[H + k]) from three exponentials:
+//   exp(-(k - f)^2 / (2 sigma^2)) = e^{-c f^2} * (e^{2 c f})^k * e^{-c k^2},  c = 1/(2 sigma^2)
+// (cl2 = c log2(e), q[k] = e^{-c k^2}).  For |f| <= 1/2 the powers of e^{+-2cf} stay within
+// [e^{-3c}, e^{3c}], and each value carries at most three more roundings than
+// a direct evaluation, ~4e-7 relative in FP32.
+template <int SS>
+__device__ __forceinline__ void gauss_line(float f, float cl2, const float *q, float *g) {
+    constexpr int H = (SS - 1) / 2;
+    const float e0 = __builtin_amdgcn_exp2f(-(f * f) * cl2);
+    const float r = __builtin_amdgcn_exp2f((2.0f * f) * cl2);
+    const float ri = __builtin_amdgcn_exp2f((-2.0f * f) * cl2);
+    g[H] = e0;
+    float pp = e0, pm = e0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        pp *= r;
+        pm *= ri;
+        g[H + k] = pp * q[k];
+        g[H - k] = pm * q[k];
+    }
+}
+
 __device__ __forceinline__ void bin_coords(const JobGeom &g, uint32_t b, int &img, int &kl, int &ty,
                                            int &tx) {
     uint32_t per_plane = (uint32_t)g.NT * g.NT;
@@ -88,8 +110,9 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // such records in registers and adds them to the LDS tile only when the cell
 // changes, or after kRunCap records (so an FP32 register sum never holds more
 // than kRunCap terms); otherwise every record is added to the tile directly.
-// (A variant that adds the footprint with one base address when it lies inside
-// the tile measured slower: the burst of 98 back-to-back FP64 LDS atomics.)
+// (Variants that add the whole footprint from one base address, inside the tile
+// or into an LDS apron, measured slower: bursts of 98 back-to-back FP64 LDS
+// atomics, and an apron that leaves room for one workgroup per CU.)
 template <typename T, int TT, int SS, bool ACC>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,
@@ -154,6 +177,11 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             }
     }
     if constexpr (ACC) {
+        // exp(-k^2/(2 sigma^2)) for k = 1..H, for gauss_line
+        const float cl2 = (float)g.inv2s2 * 1.4426950408889634f;
+        float q[H + 1];
+#pragma unroll
+        for (int k = 0; k <= H; ++k) q[k] = __builtin_amdgcn_exp2f(-(float)(k * k) * cl2);
         // A lane whose next record starts a new run (another cell, or kRunCap records
         // summed) parks until the wave flushes: the wave adds the register sums of
         // all parked lanes to the tile together once kFlushLanes lanes are parked,
@@ -174,11 +202,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                     ++pos;
                     if (pos < q1) nx = rec[pos];
                     T gx[SS], gy[SS];
-#pragma unroll
-                    for (int a = 0; a < SS; ++a) {
-                        gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
-                        gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
-                    }
+                    gauss_line<SS>(fx, cl2, q, gx);
+                    gauss_line<SS>(fy, cl2, q, gy);
 #pragma unroll
                     for (int bb = 0; bb < SS; ++bb) {
                         T wr = re * gy[bb], wi = im * gy[bb];
