@@ -149,8 +149,10 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
     unsigned long long kmin = ~0ull, kmax = 0ull, nf = 0, nv = 0, nu = 0;
     double sw = 0.0;
     const int c = (int)(e0 % g.n_chan);
-    for (int64_t e = e0; e < n_elem; e += stride) {
-        int64_t r = e / g.n_chan;
+    // the stride is a multiple of n_chan: the row advances by a constant
+    const int64_t dr = stride / g.n_chan;
+    int64_t r = e0 / g.n_chan;
+    for (int64_t e = e0; e < n_elem; e += stride, r += dr) {
         bool fl;
         double w, wt;
         bool ok = valid0<VT>(g, uvw, vis, wts, flags, e, r, c, fl, w, wt);
@@ -345,24 +347,44 @@ struct Slice {
     bool ok;
 };
 
-__device__ __forceinline__ Slice slice_of(const JobGeom &g, int64_t stretch, int t_in) {
+// (channel, baseline, time block) of a stretch, in 32-bit arithmetic: a job holds
+// at most 2^29 visibilities, so stretch indices stay far below 2^32 (64-bit
+// division is a long software sequence on the GPU)
+struct StretchPos {
+    int c;
+    uint32_t b, tb;
+    bool ok;
+};
+
+__device__ __forceinline__ StretchPos stretch_pos(const JobGeom &g, uint32_t stretch) {
+    StretchPos p;
+    const uint32_t nc = (uint32_t)g.n_chan;
+    p.c = (int)(stretch % nc);
+    const uint32_t rest = stretch / nc;
+    p.b = rest % (uint32_t)g.P;
+    p.tb = rest / (uint32_t)g.P;
+    p.ok = p.tb < (uint32_t)g.n_tb;
+    return p;
+}
+
+__device__ __forceinline__ Slice slice_at(const JobGeom &g, const StretchPos &p, int t_in) {
     Slice sl;
-    sl.c = (int)(stretch % g.n_chan);
-    const int64_t rest = stretch / g.n_chan;
-    const int64_t b = rest % g.P;
-    const int64_t tb = rest / g.P;
-    const int64_t t = tb * kStretch + t_in;
-    sl.r = t * g.P + b;
-    sl.ok = tb < g.n_tb && t < g.n_t && sl.r < g.n_rows;
+    sl.c = p.c;
+    const int64_t t = (int64_t)p.tb * kStretch + t_in;
+    sl.r = t * g.P + p.b;
+    sl.ok = p.ok && t < g.n_t && sl.r < g.n_rows;
     sl.e = sl.r * g.n_chan + sl.c;
     return sl;
 }
 
-// phase-A slot q of a workgroup: time slice and stretch within the tile
-__device__ __forceinline__ void tile_slot(int q, int &t, int &s) {
+// phase-A slot k of a thread: stretch s (the same for every k, as kBinThreads is a
+// multiple of kBinStretches) and time slice t within the tile
+__device__ __forceinline__ void tile_slot(int k, int &t, int &s) {
+    const int q = threadIdx.x + k * kBinThreads;
     t = q / kBinStretches;
     s = q - t * kBinStretches;
 }
+static_assert(kBinThreads % kBinStretches == 0, "phase A keeps one stretch per thread");
 
 // For every bin among the lanes' keys (0 to 4 per lane, none repeated within a
 // lane): f(bin, lanes holding it, leader lane, this lane holds it).  Every lane
@@ -410,6 +432,7 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
     __shared__ uint32_t s_pk[kTileElems];
     const int64_t blk = bin_block(blockIdx.x, gridDim.x);
     const int64_t s0 = blk * kBinStretches;
+    const StretchPos pos = stretch_pos(g, (uint32_t)(s0 + (int)threadIdx.x % kBinStretches));
     // phase A: all loads first
     Slice sl[kPerThread];
     uint8_t mk[kPerThread];
@@ -417,8 +440,8 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
-        tile_slot(threadIdx.x + k * kBinThreads, t, s);
-        sl[k] = slice_of(g, s0 + s, t);
+        tile_slot(k, t, s);
+        sl[k] = slice_at(g, pos, t);
         mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
         const int64_t r = sl[k].ok ? sl[k].r : 0;
         u[k] = mk[k] ? uvw[3 * r] : 0.0;
@@ -428,7 +451,7 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
-        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        tile_slot(k, t, s);
         const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;
@@ -481,14 +504,15 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
     __shared__ ScatterLds<VT> L;
     const int64_t blk = bin_block(blockIdx.x, gridDim.x);
     const int64_t s0 = blk * kBinStretches;
+    const StretchPos pos = stretch_pos(g, (uint32_t)(s0 + (int)threadIdx.x % kBinStretches));
     Slice sl[kPerThread];
     uint8_t mk[kPerThread];
     double u[kPerThread], v[kPerThread], w[kPerThread], vr[kPerThread], vi[kPerThread], wt[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
-        tile_slot(threadIdx.x + k * kBinThreads, t, s);
-        sl[k] = slice_of(g, s0 + s, t);
+        tile_slot(k, t, s);
+        sl[k] = slice_at(g, pos, t);
         mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
         const int64_t r = sl[k].ok ? sl[k].r : 0;
         const int64_t e = sl[k].ok ? sl[k].e : 0;
@@ -501,7 +525,7 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
-        tile_slot(threadIdx.x + k * kBinThreads, t, s);
+        tile_slot(k, t, s);
         const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;

@@ -327,8 +327,8 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C
 // phase screen of one pixel for plane w: e^{2 pi i w (n-1)}
 //   MODE 0 (FP64 mesh):      argument and sin/cos in FP64
 //   MODE 1 (FP32 mesh):      argument w (n-1) in turns formed in FP64 and reduced
-//                            exactly to [-1/2, 1/2]; sin/cos of the reduced angle in
-//                            FP32 (error ~6e-8, below the FP32 mesh rounding)
+//                            exactly to [-1/2, 1/2]; sin/cos of the reduced angle by
+//                            the hardware's FP32 functions (error <= 1.3e-7)
 //   MODE 2 (FP32 phase):     argument and sin/cos in FP32 (the precision study)
 template <int MODE>
 struct Phase;
@@ -370,7 +370,10 @@ struct Phase<1> {
     static __device__ __forceinline__ void screen(R nm1v, double w, float &c, float &s) {
         double t = w * nm1v;             // turns
         double r = t - rint(t);          // exact: |r| <= 1/2
-        sincospif(2.0f * (float)r, &s, &c);
+        // hardware sine and cosine of an argument in turns: max error 1.3e-7 over
+        // [-1/2, 1/2] (measured against FP64), about twice the FP32 mesh rounding
+        s = __builtin_amdgcn_sinf((float)r);
+        c = __builtin_amdgcn_cosf((float)r);
     }
 };
 
