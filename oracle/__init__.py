@@ -73,13 +73,19 @@ def _load():
         lib.oracle_grid.restype = ctypes.c_int
         lib.oracle_grid.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+                                    ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    P, P]
         lib.oracle_pixels.restype = ctypes.c_int
         lib.oracle_pixels.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_int, ctypes.c_int, P, P, P]
+                                      ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, P]
+        lib.oracle_bessel_i0.restype = ctypes.c_double
+        lib.oracle_bessel_i0.argtypes = [ctypes.c_double]
+        lib.oracle_kernel_value.restype = ctypes.c_double
+        lib.oracle_kernel_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double]
         _lib = lib
     return _lib
 
@@ -99,6 +105,8 @@ class Params:
     grid_correct: bool = True
     normalize: bool = True
     per_channel: bool = False
+    kernel: str = "gauss"              # "gauss" or "kb" (Kaiser-Bessel)
+    kernel_beta: float = 0.0           # Kaiser-Bessel beta; 0 -> kb_default_beta(support)
 
 
 @dataclass
@@ -184,7 +192,7 @@ def grid(inp: Inputs, prm: Params, w_min: float, w_max: float, plane_lo: int = 0
     sc = inp.chan_scale()
     rc = lib.oracle_grid(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
                          _ptr(inp.weights), _ptr(inp.flags), n, prm.n_wplanes, prm.support,
-                         prm.cell_rad, prm.kernel_sigma, w_min, w_max, plane_lo, plane_hi,
+                         prm.cell_rad, *_kernel_args(prm), w_min, w_max, plane_lo, plane_hi,
                          chan, _ptr(g), ctypes.byref(cnt))
     if rc != 0:
         raise ValueError("oracle_grid: unsupported support")
@@ -232,14 +240,38 @@ def wcorrect(F: np.ndarray, w_min: float, w_max: float, n_w: int, cell: float,
 # ----------------------------------------------------------------------------
 # O7: grid correction and normalisation
 # ----------------------------------------------------------------------------
-def kernel_transform(n: int, support: int, sigma: float, nodes: int = 64) -> np.ndarray:
-    """C(nu_p) = int_{-S/2}^{S/2} exp(-d^2/(2 sigma^2)) cos(2 pi nu_p d) dd at
-    nu_p = (p - N/2)/N, by Gauss-Legendre quadrature."""
+def kb_default_beta(support: int) -> float:
+    """Kaiser-Bessel shape for a mesh oversampled twice over the image, after Beatty,
+    Nishimura and Pauly (2005): beta = pi sqrt((S/2)^2 (2 - 1/2)^2 - 0.8).  The paper
+    names the Kaiser-Bessel kernel of Jackson et al. (1991) without its beta."""
+    return math.pi * math.sqrt((support / 2.0) ** 2 * 1.5 ** 2 - 0.8)
+
+
+def _kernel_args(prm: Params) -> tuple[int, float]:
+    if prm.kernel == "gauss":
+        return 0, prm.kernel_sigma
+    if prm.kernel == "kb":
+        return 1, (prm.kernel_beta if prm.kernel_beta > 0 else kb_default_beta(prm.support))
+    raise ValueError(f"unknown kernel {prm.kernel!r}")
+
+
+def kernel_value(prm: Params, d) -> np.ndarray:
+    """G(d) of the gridding kernel (Eq. 3), elementwise over d (cells)."""
+    lib = _load()
+    kind, par = _kernel_args(prm)
+    return np.vectorize(lambda x: lib.oracle_kernel_value(kind, par, prm.support, float(x)))(d)
+
+
+def kernel_transform(n: int, support: int, sigma: float, nodes: int = 64, kernel: str = "gauss",
+                     beta: float = 0.0) -> np.ndarray:
+    """C(nu_p) = int_{-S/2}^{S/2} G(d) cos(2 pi nu_p d) dd at nu_p = (p - N/2)/N, by
+    Gauss-Legendre quadrature (G is analytic on the support for both kernels)."""
     x, wq = np.polynomial.legendre.leggauss(nodes)
     a = support / 2.0
     d = a * x
     nu = (np.arange(n, dtype=np.float64) - n / 2) / n
-    f = np.exp(-d * d / (2.0 * sigma * sigma))
+    prm = Params(n, 1, support, 1.0, sigma, kernel=kernel, kernel_beta=beta)
+    f = kernel_value(prm, d)
     return a * (np.cos(2.0 * np.pi * nu[:, None] * d[None, :]) * (wq * f)[None, :]).sum(axis=1)
 
 
@@ -247,7 +279,8 @@ def post(A: np.ndarray, sum_w: float, prm: Params) -> np.ndarray:
     """D = Re A / (sum W * C(nu_p) C(nu_q)), each factor switchable; 0 if sum W = 0."""
     d = A.real.copy()
     if prm.grid_correct:
-        c = kernel_transform(prm.grid_n, prm.support, prm.kernel_sigma)
+        c = kernel_transform(prm.grid_n, prm.support, prm.kernel_sigma, kernel=prm.kernel,
+                             beta=prm.kernel_beta)
         d /= c[:, None] * c[None, :]
     if prm.normalize:
         if sum_w > 0.0:
@@ -303,7 +336,7 @@ def pixels(inp: Inputs, prm: Params, pix_q, pix_p, chan: int = -1) -> np.ndarray
     sc = inp.chan_scale()
     rc = lib.oracle_pixels(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
                            _ptr(inp.weights), _ptr(inp.flags), prm.grid_n, prm.n_wplanes,
-                           prm.support, prm.cell_rad, prm.kernel_sigma, wmin, wmax, chan,
+                           prm.support, prm.cell_rad, *_kernel_args(prm), wmin, wmax, chan,
                            len(q), _ptr(q), _ptr(p), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_pixels failed")

@@ -16,8 +16,11 @@
  *     and the description of the third and fourth algorithmic components).
  *
  * Readings of points the paper leaves open (listed in the design notes):
- *   - G(d) = exp(-d^2 / (2 sigma^2)), separable in u and v, support S odd,
- *     h = (S-1)/2 cells on each side of the nearest cell i0 = floor(x + 1/2);
+ *   - G is separable in u and v, support S odd, h = (S-1)/2 cells on each
+ *     side of the nearest cell i0 = floor(x + 1/2); either a Gaussian
+ *     G(d) = exp(-d^2 / (2 sigma^2)) or the Kaiser-Bessel window the paper's
+ *     runs use (Sec. 2, after Eq. 3; Jackson et al. 1991)
+ *     G(d) = I0(beta sqrt(1 - (2d/S)^2)) / I0(beta) for |d| <= S/2;
  *   - x = u * (N * dl) + N/2 with no fused multiply-add, so that the cell and
  *     plane decisions are reproducible bit for bit;
  *   - N_w cell-centred planes over [w_min, w_max]: dw = (w_max - w_min)/N_w,
@@ -118,6 +121,32 @@ static int plane_of(double w, double w_min, double dw, int n_w)
     return k;
 }
 
+/* Modified Bessel function of the first kind, order 0, by its power series
+ * sum_k (x^2/4)^k / (k!)^2 (every term positive), summed until a term no
+ * longer changes the sum. */
+double oracle_bessel_i0(double x)
+{
+    double q = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        double next = sum + term;
+        if (next == sum) break;
+        sum = next;
+    }
+    return sum;
+}
+
+/* The gridding kernel at offset d (cells): kind 0 Gaussian with par = sigma,
+ * kind 1 Kaiser-Bessel with par = beta over the support S.  0 outside |d| <= S/2. */
+double oracle_kernel_value(int kind, double par, int support, double d)
+{
+    if (kind == 0) return exp(-d * d / (2.0 * par * par));
+    double t = 2.0 * d / (double)support;
+    double u = 1.0 - t * t;
+    if (u < 0.0) return 0.0;
+    return oracle_bessel_i0(par * sqrt(u)) / oracle_bessel_i0(par);
+}
+
 /*
  * Eq. 3 on the (u,v) mesh of the nearest w-plane:
  *   g_k[j0+b][i0+a] += W V G(i0+a-x) G(j0+b-y),  a, b in [-h, h].
@@ -127,14 +156,13 @@ static int plane_of(double w, double w_min, double dw, int n_w)
  */
 int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
                 const double *vis, const double *weights, const uint8_t *flags,
-                int n, int n_w, int support, double cell, double sigma,
+                int n, int n_w, int support, double cell, int kernel, double kpar,
                 double w_min, double w_max, int plane_lo, int plane_hi, int chan,
                 double *grid, oracle_counts *counts)
 {
     int h = (support - 1) / 2;
     double scale = (double)n * cell;
     double dw = (w_max - w_min) / (double)n_w;
-    double inv2s2 = 1.0 / (2.0 * sigma * sigma);
     double gx[64], gy[64];
     oracle_counts cnt = {0, 0, 0, 0.0};
     if (support > 63) return -1;
@@ -162,14 +190,10 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
             position(u, v, scale, n, &x, &y);
             fits(x, n, h, &i0);
             fits(y, n, h, &j0);
-            for (int a = -h; a <= h; ++a) {
-                double d = (double)(i0 + a) - x;
-                gx[a + h] = exp(-d * d * inv2s2);
-            }
-            for (int b = -h; b <= h; ++b) {
-                double d = (double)(j0 + b) - y;
-                gy[b + h] = exp(-d * d * inv2s2);
-            }
+            for (int a = -h; a <= h; ++a)
+                gx[a + h] = oracle_kernel_value(kernel, kpar, support, (double)(i0 + a) - x);
+            for (int b = -h; b <= h; ++b)
+                gy[b + h] = oracle_kernel_value(kernel, kpar, support, (double)(j0 + b) - y);
             double wv_re = wt * vis[2 * rc + 0];
             double wv_im = wt * vis[2 * rc + 1];
             double *plane = grid + (size_t)(k - plane_lo) * (size_t)n * (size_t)n * 2;
@@ -204,7 +228,7 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
  */
 int oracle_pixels(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
                   const double *vis, const double *weights, const uint8_t *flags,
-                  int n, int n_w, int support, double cell, double sigma,
+                  int n, int n_w, int support, double cell, int kernel, double kpar,
                   double w_min, double w_max, int chan,
                   int n_pix, const int32_t *pix_q, const int32_t *pix_p, double *out)
 {
@@ -212,7 +236,6 @@ int oracle_pixels(int64_t n_rows, int n_chan, const double *uvw, const double *c
     int h = (support - 1) / 2;
     double scale = (double)n * cell;
     double dw = (w_max - w_min) / (double)n_w;
-    double inv2s2 = 1.0 / (2.0 * sigma * sigma);
     if (support > 63 || n_pix <= 0) return n_pix < 0 ? -1 : 0;
 
     double *ct = (double *)malloc(sizeof(double) * (size_t)n);
@@ -265,14 +288,10 @@ int oracle_pixels(int64_t n_rows, int n_chan, const double *uvw, const double *c
                 position(u, v, scale, n, &x, &y);
                 fits(x, n, h, &i0);
                 fits(y, n, h, &j0);
-                for (int a = -h; a <= h; ++a) {
-                    double d = (double)(i0 + a) - x;
-                    gx[a + h] = exp(-d * d * inv2s2);
-                }
-                for (int b = -h; b <= h; ++b) {
-                    double d = (double)(j0 + b) - y;
-                    gy[b + h] = exp(-d * d * inv2s2);
-                }
+                for (int a = -h; a <= h; ++a)
+                    gx[a + h] = oracle_kernel_value(kernel, kpar, support, (double)(i0 + a) - x);
+                for (int b = -h; b <= h; ++b)
+                    gy[b + h] = oracle_kernel_value(kernel, kpar, support, (double)(j0 + b) - y);
                 double wv_re = wt * vis[2 * rc + 0];
                 double wv_im = wt * vis[2 * rc + 1];
                 for (int ip = 0; ip < n_pix; ++ip) {

@@ -325,3 +325,89 @@ def test_channels_cube_and_metres():
                                               vis[:, c:c + 1]),
                            oracle.Params(64, 4, 7, 0.2 / 64, SIG))["image"][0]
         assert np.linalg.norm(cube[c] - one) <= 1e-13 * np.linalg.norm(one)
+
+
+# ---------------------------------------------------------------- Kaiser-Bessel kernel
+# The paper's runs grid with a Kaiser-Bessel window (Sec. 2, after Eq. 3; Jackson
+# et al. 1991): G(d) = I0(beta sqrt(1 - (2d/S)^2)) / I0(beta) on |d| <= S/2.
+def _kb_ref(d, S, beta):
+    from scipy.special import i0
+    t = 2.0 * np.asarray(d, dtype=np.float64) / S
+    u = np.clip(1.0 - t * t, 0.0, None)
+    return np.where(1.0 - t * t >= 0.0, i0(beta * np.sqrt(u)) / i0(beta), 0.0)
+
+
+def test_bessel_i0_against_scipy():
+    from scipy.special import i0
+    lib = oracle._load()
+    for x in (0.0, 1e-3, 0.5, 1.0, 3.75, 7.0, 10.0, 16.252239469813198, 25.0, 40.0):
+        assert abs(lib.oracle_bessel_i0(x) - i0(x)) <= 2e-15 * i0(x), x
+
+
+@pytest.mark.parametrize("S", [5, 7, 9])
+def test_kb_kernel_values(S):
+    beta = oracle.kb_default_beta(S)
+    prm = oracle.Params(64, 1, S, 1.0, kernel="kb")
+    x = np.linspace(0.0, S / 2, 21)
+    d = np.concatenate([-x[::-1], x])                       # exact mirror images
+    g = oracle.kernel_value(prm, d)
+    assert np.abs(g - _kb_ref(d, S, beta)).max() <= 1e-14
+    assert oracle.kernel_value(prm, np.array([0.0]))[0] == 1.0
+    assert np.array_equal(g, g[::-1])                       # even
+    assert oracle.kernel_value(prm, np.array([S / 2 + 1e-9]))[0] == 0.0
+
+
+def test_kb_default_beta_reading():
+    # Beatty et al. (2005) for twofold oversampling: beta = pi sqrt((S/2)^2 1.5^2 - 0.8)
+    assert abs(oracle.kb_default_beta(7) - 16.252239469813198) < 1e-12
+    assert abs(oracle.kb_default_beta(5) - math.pi * math.sqrt(6.25 * 2.25 - 0.8)) < 1e-12
+
+
+@pytest.mark.parametrize("S,beta", [(7, 0.0), (5, 0.0), (9, 0.0), (7, 9.0)])
+def test_kb_kernel_transform_closed_form(S, beta):
+    # the window's continuous transform: S sinh(sqrt(beta^2 - (pi S nu)^2)) / sqrt(...) / I0(beta)
+    from scipy.special import i0
+    n = 128
+    b = beta if beta > 0 else oracle.kb_default_beta(S)
+    c = oracle.kernel_transform(n, S, SIG, kernel="kb", beta=beta)
+    nu = (np.arange(n) - n / 2) / n
+    z2 = b * b - (np.pi * S * nu) ** 2
+    ref = np.where(z2 > 0, S * np.sinh(np.sqrt(np.abs(z2))) / np.sqrt(np.abs(z2)),
+                   S * np.sin(np.sqrt(np.abs(z2))) / np.sqrt(np.abs(z2))) / i0(b)
+    assert np.abs(c - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_kb_single_visibility_footprint():
+    n, cell, S = 64, 1.0 / 100, 7
+    uvw = np.array([[12.34567, -8.7654, 5.0]])
+    vis = np.array([[0.3 - 0.8j]])
+    wts = np.array([[1.7]])
+    prm = oracle.Params(n, 1, S, cell, kernel="kb")
+    g, cnt = oracle.grid(_inputs(uvw, vis, wts), prm, 5.0, 5.0)
+    x, y = pinlib.positions(uvw, n, cell)
+    i0_, j0 = int(math.floor(x[0] + 0.5)), int(math.floor(y[0] + 0.5))
+    beta = oracle.kb_default_beta(S)
+    ref = np.zeros((n, n), complex)
+    for b in range(-3, 4):
+        for a in range(-3, 4):
+            ref[j0 + b, i0_ + a] = 1.7 * vis[0, 0] * _kb_ref(i0_ + a - x[0], S, beta) * \
+                _kb_ref(j0 + b - y[0], S, beta)
+    assert np.abs(g[0] - ref).max() < 1e-15
+    assert cnt["n_used"] == 1
+
+
+def test_kb_pure_fringe_closed_form():
+    # a visibility on a cell: its image is the fringe times the discrete kernel transform
+    n, cell, S = 64, 1.0 / 128, 7
+    u, v, w = 2.0 * 9, 2.0 * -13, 37.5
+    inp = _inputs(np.array([[u, v, w]]), np.array([[1.0 + 0j]]))
+    A = _raw(inp, oracle.Params(n, 4, S, cell, kernel="kb"))
+    c = (np.arange(n) - n / 2)
+    l = c * cell
+    nu = c / n
+    a = np.arange(-3, 4)
+    kb = _kb_ref(a, S, oracle.kb_default_beta(S))
+    cd = (kb[None, :] * np.cos(2 * np.pi * a[None, :] * nu[:, None])).sum(1)
+    nm1 = np.sqrt(1 - l[None, :] ** 2 - l[:, None] ** 2) - 1
+    ref = np.exp(2j * np.pi * (u * l[None, :] + v * l[:, None] + w * nm1)) * cd[None, :] * cd[:, None]
+    assert np.abs(A - ref).max() < 1e-12
