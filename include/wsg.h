@@ -19,7 +19,11 @@
  *     index fastest: grid[k][j][i], image[q][p];
  *   - a visibility sits at x = u * (N * cell_rad) + N/2 (no fused multiply-
  *     add), nearest cell i0 = floor(x + 1/2), footprint i0-h .. i0+h with
- *     h = (S-1)/2; G(d) = exp(-d^2 / (2 sigma^2)), separable in u and v;
+ *     h = (S-1)/2; G is separable in u and v: the Gaussian
+ *     G(d) = exp(-d^2 / (2 sigma^2)), or the Kaiser-Bessel window the paper's
+ *     runs use (Sec. 2, after Eq. 3) G(d) = I0(beta sqrt(1 - (2d/S)^2)) / I0(beta)
+ *     on |d| <= S/2 (beta = 0 in wsg_params: pi sqrt((S/2)^2 1.5^2 - 0.8), the
+ *     choice of Beatty et al. 2005 for a mesh twice oversampled);
  *   - planes are N_w cells of width dw = (w_max - w_min)/N_w over [w_min,
  *     w_max]; k = min(N_w-1, floor((w - w_min)/dw)), w_k = w_min + (k+1/2) dw;
  *     dw = 0 puts everything on plane 0 at w_0 = w_min;
@@ -78,6 +82,9 @@ enum {
 
 enum { WSG_MEM_HOST = 0, WSG_MEM_DEVICE = 1 };
 
+/* Gridding kernel G. */
+enum { WSG_KERNEL_GAUSSIAN = 0, WSG_KERNEL_KAISER_BESSEL = 1 };
+
 enum {
     WSG_GRID_CORRECT = 1u,   /* divide by C(nu_p) C(nu_q)                                    */
     WSG_NORMALIZE = 2u,      /* divide by sum W                                              */
@@ -91,12 +98,15 @@ typedef struct {
     int32_t support;       /* S: odd, 1 .. 15, S <= N                                          */
     int32_t precision;     /* WSG_PREC_*                                                       */
     double cell_rad;       /* image pixel size dl in radians (> 0, finite)                     */
-    double kernel_sigma;   /* Gaussian width in cells (> 0); 0.9 is the reading for S = 7      */
+    double kernel_sigma;   /* Gaussian width in cells (> 0); 0.9 is the reading for S = 7;     */
+                           /*   not used by the Kaiser-Bessel kernel                          */
     double w_min, w_max;   /* plane range; both NaN: taken from the data                       */
     int32_t plane_lo;      /* image only planes [plane_lo, plane_hi) of N_w (both 0: all);    */
     int32_t plane_hi;      /*   needs a given w range, so that every shard agrees             */
     uint32_t flags;        /* WSG_GRID_CORRECT | WSG_NORMALIZE | ...                           */
     int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64     */
+    int32_t kernel;        /* WSG_KERNEL_*                                                     */
+    double kernel_beta;    /* Kaiser-Bessel beta (>= 0, finite; 0: the default for S)          */
 } wsg_params;
 
 typedef struct {

@@ -10,8 +10,10 @@
 // with global atomics into a tile that k_zero_tiles cleared.  Empty bins get no
 // work item: k_zero_tiles writes their tiles with plain stores, without LDS.
 //
-// The kernel G(d) = exp(-d^2 / (2 sigma^2)) is separable: 2*S exponentials per
-// record, S^2 multiply-adds.
+// G is separable: 2*S kernel values per record, S^2 multiply-adds.  KIND 0 is the
+// Gaussian exp(-d^2 / (2 sigma^2)), KIND 1 the Kaiser-Bessel window
+// I0(beta sqrt(1 - (2d/S)^2)) / I0(beta) that the paper's runs use (Sec. 2, after
+// Eq. 3), from the tables described with KbTable.
 #include "wsg_internal.h"
 
 namespace wsg {
@@ -82,6 +84,42 @@ __device__ __forceinline__ void gauss_line(float f, float cl2, const float *q, f
     }
 }
 
+// Kaiser-Bessel taps g[a] = G((a - H) - f), a = 0..SS-1, on an FP32 mesh: tap a and
+// tap SS-1-a are one fitted polynomial at x = 2f and at -x, E(x^2) +- x O(x^2).
+template <int SS>
+__device__ __forceinline__ void kb_line(float f, const float *__restrict__ poly, float *g) {
+    constexpr int H = (SS - 1) / 2;
+    const float x = 2.0f * f, x2 = x * x;
+#pragma unroll
+    for (int a = 0; a <= H; ++a) {
+        const float *c = poly + a * kKbStride;
+        float e = c[kKbEven - 1];
+#pragma unroll
+        for (int k = kKbEven - 2; k >= 0; --k) e = __builtin_fmaf(e, x2, c[k]);
+        if (a == H) {
+            g[H] = e;
+        } else {
+            float o = c[kKbStride - 1];
+#pragma unroll
+            for (int k = kKbOdd - 2; k >= 0; --k) o = __builtin_fmaf(o, x2, c[kKbEven + k]);
+            o *= x;
+            g[a] = e + o;
+            g[SS - 1 - a] = e - o;
+        }
+    }
+}
+
+// Kaiser-Bessel value on an FP64 mesh: Horner's rule on the power series in u
+// (0 outside the support, where u < 0).
+__device__ __forceinline__ double kb_value(double d, const double *__restrict__ c, int n, int S) {
+    const double t = 2.0 * d / (double)S;
+    const double u = 1.0 - t * t;
+    if (u < 0.0) return 0.0;
+    double acc = c[n - 1];
+    for (int k = n - 2; k >= 0; --k) acc = fma(acc, u, c[k]);
+    return acc;
+}
+
 __device__ __forceinline__ void bin_coords(const JobGeom &g, uint32_t b, int &img, int &kl, int &ty,
                                            int &tx) {
     uint32_t per_plane = (uint32_t)g.NT * g.NT;
@@ -113,7 +151,7 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // (Variants that add the whole footprint from one base address, inside the tile
 // or into an LDS apron, measured slower: bursts of 98 back-to-back FP64 LDS
 // atomics, and an apron that leaves room for one workgroup per CU.)
-template <typename T, int TT, int SS, bool ACC>
+template <typename T, int TT, int SS, bool ACC, int KIND>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,
                                                         const uint32_t *__restrict__ item_off,
@@ -182,6 +220,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         float q[H + 1];
 #pragma unroll
         for (int k = 0; k <= H; ++k) q[k] = __builtin_amdgcn_exp2f(-(float)(k * k) * cl2);
+        const float *__restrict__ kbp = g.kb_poly;
         // A lane whose next record starts a new run (another cell, or kRunCap records
         // summed) parks until the wave flushes: the wave adds the register sums of
         // all parked lanes to the tile together once kFlushLanes lanes are parked,
@@ -202,8 +241,13 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                     ++pos;
                     if (pos < q1) nx = rec[pos];
                     T gx[SS], gy[SS];
-                    gauss_line<SS>(fx, cl2, q, gx);
-                    gauss_line<SS>(fy, cl2, q, gy);
+                    if constexpr (KIND == 0) {
+                        gauss_line<SS>(fx, cl2, q, gx);
+                        gauss_line<SS>(fy, cl2, q, gy);
+                    } else {
+                        kb_line<SS>(fx, kbp, gx);
+                        kb_line<SS>(fy, kbp, gy);
+                    }
 #pragma unroll
                     for (int bb = 0; bb < SS; ++bb) {
                         T wr = re * gy[bb], wi = im * gy[bb];
@@ -238,10 +282,21 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         T fx, fy, re, im;
         RecTraits<T>::decode(rec[ri], H, li, lj, fx, fy, re, im);
         T gx[SS], gy[SS];
+        if constexpr (KIND == 0) {
 #pragma unroll
-        for (int a = 0; a < SS; ++a) {
-            gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
-            gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
+            for (int a = 0; a < SS; ++a) {
+                gx[a] = RecTraits<T>::gauss((T)(a - H) - fx, inv2s2);
+                gy[a] = RecTraits<T>::gauss((T)(a - H) - fy, inv2s2);
+            }
+        } else if constexpr (sizeof(T) == 4) {
+            kb_line<SS>(fx, g.kb_poly, gx);
+            kb_line<SS>(fy, g.kb_poly, gy);
+        } else {
+#pragma unroll
+            for (int a = 0; a < SS; ++a) {
+                gx[a] = kb_value((T)(a - H) - fx, g.kb_series, g.kb_n, SS);
+                gy[a] = kb_value((T)(a - H) - fy, g.kb_series, g.kb_n, SS);
+            }
         }
 #pragma unroll
         for (int bb = 0; bb < SS; ++bb) {
@@ -357,8 +412,12 @@ void launch_tile(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *cou
                  const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
                  uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr) {
     constexpr bool ACC = (sizeof(T) == 4) && SS <= 7;
-    k_grid<T, TT, SS, ACC><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin, chunk,
-                                                         r, gp, tr);
+    if (g.kernel == 1)
+        k_grid<T, TT, SS, ACC, 1><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
+                                                                chunk, r, gp, tr);
+    else
+        k_grid<T, TT, SS, ACC, 0><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
+                                                                chunk, r, gp, tr);
 }
 
 template <typename T, int TT>

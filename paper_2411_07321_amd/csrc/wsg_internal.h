@@ -64,6 +64,19 @@ struct ImgState {
     unsigned long long n_tiles, n_tile_rows; // occupied (plane, tile) / (plane, tile-row)
 };
 
+// Kaiser-Bessel kernel tables.  FP64 meshes evaluate G(d) = I0(beta sqrt(u)) /
+// I0(beta), u = 1 - (2d/S)^2, by its power series in u (every coefficient positive,
+// so Horner's rule loses nothing to cancellation).  FP32 meshes take tap a of a
+// footprint (d = (a - h) - f, f in [-1/2, 1/2)) from a degree-kKbDeg polynomial in
+// x = 2f, fitted per tap by Chebyshev interpolation and split into its even part
+// (kKbEven coefficients in x^2) and odd part (kKbOdd coefficients in x^2, times x):
+// tap S-1-a is the same polynomial at -x, so the two share both parts.
+constexpr int kKbMaxSeries = 128;
+constexpr int kKbDeg = 8;
+constexpr int kKbEven = kKbDeg / 2 + 1;
+constexpr int kKbOdd = (kKbDeg + 1) / 2;
+constexpr int kKbStride = kKbEven + kKbOdd;
+
 // Everything the binning and gridding kernels need about one job.
 struct JobGeom {
     int64_t n_rows;
@@ -77,8 +90,12 @@ struct JobGeom {
     int32_t logT, logNT;
     double scale;           // N * cell_rad
     double half;            // N / 2
-    double sigma;
-    double inv2s2;          // 1 / (2 sigma^2)
+    int32_t kernel;         // WSG_KERNEL_GAUSSIAN or WSG_KERNEL_KAISER_BESSEL
+    double inv2s2;          // Gaussian: 1 / (2 sigma^2)
+    // Kaiser-Bessel, device tables of the context (see KbTable)
+    const double *kb_series;  // G = sum_k kb_series[k] u^k, u = 1 - (2d/S)^2, k < kb_n
+    int32_t kb_n;
+    const float *kb_poly;     // per-tap polynomials in x = 2f, kKbStride floats per tap
     int32_t range_given;
     double w_min_given, w_max_given;
     const double *chan_scale;  // device [n_chan]: f/c or 1

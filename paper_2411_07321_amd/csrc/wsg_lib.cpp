@@ -50,7 +50,8 @@ struct wsg_ctx {
     Arena fixed, dyn;
     // cached tables
     std::map<std::pair<int, int>, DevBuf> twiddles;                       // (N, f64)
-    std::map<std::tuple<int, int, double>, DevBuf> inv_c;                 // (N, S, sigma)
+    std::map<std::tuple<int, int, int, double>, DevBuf> inv_c;            // (N, S, kernel, shape)
+    std::map<std::pair<int, double>, DevBuf> kb;                          // (S, beta)
     std::map<std::tuple<int, int, int, int, int>, int> tuned;             // -> tile
     // pinned host staging
     void *pin = nullptr;
@@ -92,6 +93,117 @@ size_t cplx_size(const wsg_params *p) { return f64_mode(p) ? 16 : 8; }
 
 bool range_given(const wsg_params *p) { return std::isfinite(p->w_min) && std::isfinite(p->w_max); }
 
+// ---------------------------------------------------------------- Kaiser-Bessel
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kKbMaxBeta = 64.0;
+constexpr double kKbFitTol = 2e-7;   // largest |fitted - exact| tap value on an FP32 mesh
+
+// I0(x) by its power series sum_k (x^2/4)^k / (k!)^2 (every term positive).
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 1000; ++k) {
+        term *= q / ((double)k * k);
+        const double next = sum + term;
+        if (next == sum) break;
+        sum = next;
+    }
+    return sum;
+}
+
+// beta = 0 in the parameters: pi sqrt((S/2)^2 1.5^2 - 0.8), Beatty, Nishimura and
+// Pauly (2005) for a mesh oversampled twice over the image; undefined (NaN) for S = 1
+double kb_beta(const wsg_params *p) {
+    if (p->kernel_beta > 0.0) return p->kernel_beta;
+    const double a = 0.75 * p->support;
+    const double r = a * a - 0.8;
+    return r > 0.0 ? kPi * std::sqrt(r) : std::nan("");
+}
+
+double kb_exact(int S, double beta, double i0b, double d) {
+    const double t = 2.0 * d / S;
+    const double u = 1.0 - t * t;
+    return u < 0.0 ? 0.0 : bessel_i0(beta * std::sqrt(u)) / i0b;
+}
+
+// Host copy of the Kaiser-Bessel tables the gridder reads (see wsg_internal.h), and
+// the largest error of the FP32 per-tap polynomials against the exact kernel.
+struct KbHost {
+    std::vector<double> series;
+    std::vector<float> poly;
+    double fit_err = 0.0;
+};
+
+KbHost make_kb(int S, double beta) {
+    KbHost kb;
+    const int H = (S - 1) / 2;
+    // power series in u: c_k = (beta^2/4)^k / (k!)^2 / I0(beta), cut where the terms
+    // have passed their peak and fall below 1e-18 of the sum
+    const double q = 0.25 * beta * beta;
+    std::vector<double> t(1, 1.0);
+    double sum = 1.0;
+    for (int k = 1; k < kKbMaxSeries; ++k) {
+        t.push_back(t.back() * q / ((double)k * k));
+        sum += t.back();
+        if ((double)k * k > q && t.back() < 1e-18 * sum) break;
+    }
+    for (double v : t) kb.series.push_back(v / sum);
+    const double i0b = bessel_i0(beta);
+    // tap a of a footprint as a polynomial in x = 2f: Chebyshev interpolation at
+    // kKbDeg + 1 nodes on [-1, 1], then the monomial coefficients through
+    // T_{m+1} = 2x T_m - T_{m-1}
+    constexpr int n = kKbDeg + 1;
+    kb.poly.assign((size_t)(H + 1) * kKbStride, 0.0f);
+    for (int a = 0; a <= H; ++a) {
+        auto tap = [&](double x) { return kb_exact(S, beta, i0b, (double)(a - H) - 0.5 * x); };
+        double fx[n], cheb[n];
+        for (int j = 0; j < n; ++j) fx[j] = tap(std::cos(kPi * (j + 0.5) / n));
+        for (int m = 0; m < n; ++m) {
+            double c = 0.0;
+            for (int j = 0; j < n; ++j) c += fx[j] * std::cos(kPi * m * (j + 0.5) / n);
+            cheb[m] = (m == 0 ? 1.0 : 2.0) * c / n;
+        }
+        double mono[n] = {}, tm1[n] = {}, tm[n] = {};
+        tm1[0] = 1.0;                      // T_0
+        tm[1] = 1.0;                       // T_1
+        mono[0] = cheb[0];
+        for (int k = 0; k < n; ++k) mono[k] += cheb[1] * tm[k];
+        for (int m = 2; m < n; ++m) {
+            double tn[n] = {};
+            for (int k = 0; k < n; ++k) tn[k] = (k ? 2.0 * tm[k - 1] : 0.0) - tm1[k];
+            for (int k = 0; k < n; ++k) mono[k] += cheb[m] * tn[k];
+            std::copy(tm, tm + n, tm1);
+            std::copy(tn, tn + n, tm);
+        }
+        float *c = kb.poly.data() + (size_t)a * kKbStride;
+        for (int k = 0; k < kKbEven; ++k) c[k] = (float)mono[2 * k];
+        for (int k = 0; k < kKbOdd; ++k) c[kKbEven + k] = a == H ? 0.0f : (float)mono[2 * k + 1];
+        // error of the stored (FP32-rounded) coefficients, for this tap (x) and its
+        // mirror tap S-1-a (-x)
+        for (int i = 0; i <= 1024; ++i) {
+            const double x = -1.0 + i / 512.0, x2 = x * x;
+            double e = 0.0, o = 0.0;
+            for (int k = kKbEven - 1; k >= 0; --k) e = e * x2 + c[k];
+            for (int k = kKbOdd - 1; k >= 0; --k) o = o * x2 + c[kKbEven + k];
+            const double err = std::fabs(e + x * o - tap(x));
+            const double err_m = std::fabs(e - x * o - tap(-x));
+            kb.fit_err = std::max(kb.fit_err, std::max(err, a == H ? err : err_m));
+        }
+    }
+    return kb;
+}
+
+// the tables for (S, beta), built once per process
+const KbHost &kb_host(int S, double beta) {
+    static std::mutex mu;
+    static std::map<std::pair<int, double>, KbHost> memo;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(S, beta);
+    auto it = memo.find(key);
+    if (it == memo.end()) it = memo.emplace(key, make_kb(S, beta)).first;
+    return it->second;
+}
+
 wsg_status check_params(const wsg_params *p, std::string &why) {
     if (!p) { why = "params is NULL"; return WSG_EINVAL; }
     if (!is_pow2(p->grid_n) || p->grid_n < 4) { why = "grid_n must be a power of two"; return WSG_EINVAL; }
@@ -106,7 +218,21 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
     // tiles per axis, which the binning passes rely on)
     if (p->precision < WSG_PREC_F64 || p->precision > WSG_PREC_F32_PHASE32) { why = "bad precision"; return WSG_EINVAL; }
     if (!(p->cell_rad > 0.0) || !std::isfinite(p->cell_rad)) { why = "cell_rad must be finite and > 0"; return WSG_EINVAL; }
-    if (!(p->kernel_sigma > 0.0) || !std::isfinite(p->kernel_sigma)) { why = "kernel_sigma must be finite and > 0"; return WSG_EINVAL; }
+    if (p->kernel == WSG_KERNEL_GAUSSIAN) {
+        if (!(p->kernel_sigma > 0.0) || !std::isfinite(p->kernel_sigma)) { why = "kernel_sigma must be finite and > 0"; return WSG_EINVAL; }
+    } else if (p->kernel == WSG_KERNEL_KAISER_BESSEL) {
+        if (!(p->kernel_beta >= 0.0) || !std::isfinite(p->kernel_beta)) { why = "kernel_beta must be finite and >= 0"; return WSG_EINVAL; }
+        if (p->kernel_beta > kKbMaxBeta) { why = "kernel_beta above 64"; return WSG_EUNSUPPORTED; }
+        const double beta = kb_beta(p);
+        if (!(beta > 0.0)) { why = "support 1 has no default kernel_beta: give one"; return WSG_EINVAL; }
+        if (!f64_mode(p) && kb_host(p->support, beta).fit_err > kKbFitTol) {
+            why = "kernel_beta too steep for the FP32 mesh's fitted kernel (use the FP64 mesh)";
+            return WSG_EUNSUPPORTED;
+        }
+    } else {
+        why = "unknown kernel";
+        return WSG_EINVAL;
+    }
     bool lo_nan = std::isnan(p->w_min), hi_nan = std::isnan(p->w_max);
     if (lo_nan != hi_nan) { why = "w_min and w_max must both be given or both NaN"; return WSG_EINVAL; }
     if (!lo_nan && (!std::isfinite(p->w_min) || !std::isfinite(p->w_max) || p->w_min > p->w_max)) {
@@ -322,22 +448,29 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
 wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const double **out) {
     *out = nullptr;
     if (!(p->flags & WSG_GRID_CORRECT)) return WSG_OK;
-    auto key = std::make_tuple(p->grid_n, p->support, p->kernel_sigma);
+    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    const double shape = kb ? kb_beta(p) : p->kernel_sigma;
+    auto key = std::make_tuple(p->grid_n, p->support, (int)p->kernel, shape);
     auto it = ctx->inv_c.find(key);
     if (it == ctx->inv_c.end()) {
+        // C(nu) = int_{-S/2}^{S/2} G(d) cos(2 pi nu d) dd by 64-point Gauss-Legendre
+        // quadrature (both kernels are analytic on the support)
         int N = p->grid_n;
         std::vector<double> xs, ws;
         gauss_legendre(64, xs, ws);
         double a = p->support / 2.0, s2 = 2.0 * p->kernel_sigma * p->kernel_sigma;
+        const double i0b = kb ? bessel_i0(shape) : 1.0;
         const double two_pi = 6.283185307179586476925286766559;
+        std::vector<double> gk(xs.size());
+        for (size_t k = 0; k < xs.size(); ++k) {
+            double d = a * xs[k];
+            gk[k] = kb ? kb_exact(p->support, shape, i0b, d) : std::exp(-d * d / s2);
+        }
         std::vector<double> h(N);
         for (int i = 0; i < N; ++i) {
             double nu = (double)(i - N / 2) / N;
             double c = 0.0;
-            for (size_t k = 0; k < xs.size(); ++k) {
-                double d = a * xs[k];
-                c += ws[k] * std::exp(-d * d / s2) * std::cos(two_pi * nu * d);
-            }
+            for (size_t k = 0; k < xs.size(); ++k) c += ws[k] * gk[k] * std::cos(two_pi * nu * a * xs[k]);
             h[i] = 1.0 / (a * c);
         }
         DevBuf b;
@@ -348,6 +481,30 @@ wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const dou
     }
     (void)s;
     *out = (const double *)it->second.ptr;
+    return WSG_OK;
+}
+
+// Device copy of the Kaiser-Bessel tables: kKbMaxSeries doubles of the power series,
+// then the per-tap polynomials.
+wsg_status get_kb(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
+    const double beta = kb_beta(p);
+    const KbHost &h = kb_host(p->support, beta);
+    auto key = std::make_pair((int)p->support, beta);
+    auto it = ctx->kb.find(key);
+    const size_t o_poly = kKbMaxSeries * sizeof(double);
+    if (it == ctx->kb.end()) {
+        std::vector<char> host(o_poly + h.poly.size() * sizeof(float), 0);
+        std::memcpy(host.data(), h.series.data(), h.series.size() * sizeof(double));
+        std::memcpy(host.data() + o_poly, h.poly.data(), h.poly.size() * sizeof(float));
+        DevBuf b;
+        WSG_HIP(ctx, hipMalloc(&b.ptr, host.size()));
+        b.size = host.size();
+        WSG_HIP(ctx, hipMemcpy(b.ptr, host.data(), b.size, hipMemcpyHostToDevice));
+        it = ctx->kb.emplace(key, b).first;
+    }
+    g->kb_series = (const double *)it->second.ptr;
+    g->kb_n = (int32_t)h.series.size();
+    g->kb_poly = (const float *)((const char *)it->second.ptr + o_poly);
     return WSG_OK;
 }
 
@@ -481,8 +638,15 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     while ((1 << g.logNT) < g.NT) ++g.logNT;
     g.scale = (double)pl.N * p->cell_rad;
     g.half = 0.5 * (double)pl.N;
-    g.sigma = p->kernel_sigma;
-    g.inv2s2 = 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma);
+    g.kernel = p->kernel;
+    g.inv2s2 = p->kernel == WSG_KERNEL_GAUSSIAN ? 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma) : 0.0;
+    g.kb_series = nullptr;
+    g.kb_n = 0;
+    g.kb_poly = nullptr;
+    if (p->kernel == WSG_KERNEL_KAISER_BESSEL) {
+        rc = get_kb(ctx, p, &g);
+        if (rc) return rc;
+    }
     g.range_given = range_given(p) ? 1 : 0;
     g.w_min_given = p->w_min;
     g.w_max_given = p->w_max;
@@ -727,6 +891,7 @@ void wsg_destroy(wsg_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &kv : ctx->twiddles) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->inv_c) (void)hipFree(kv.second.ptr);
+    for (auto &kv : ctx->kb) (void)hipFree(kv.second.ptr);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     if (ctx->pin_done) (void)hipEventDestroy(ctx->pin_done);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);

@@ -62,9 +62,34 @@ def _v(n_rows=10, n_chan=1, **kw):
     (dict(tile=128), wsg.EUNSUPPORTED),                  # FP64 LDS tile limit
     (dict(tile=128, precision="f32_phase64"), wsg.EUNSUPPORTED),
     (dict(tile=16, precision="f32_phase64"), wsg.OK),
+    (dict(kernel="kb"), wsg.OK),
+    (dict(kernel="kb", kernel_sigma=-1.0), wsg.OK),      # sigma is the Gaussian's
+    (dict(kernel="kb", kernel_beta=-1.0), wsg.EINVAL),
+    (dict(kernel="kb", kernel_beta=math.nan), wsg.EINVAL),
+    (dict(kernel="kb", kernel_beta=65.0), wsg.EUNSUPPORTED),
+    (dict(kernel="kb", support=1), wsg.EINVAL),           # no default beta for S = 1
+    (dict(kernel="kb", support=1, kernel_beta=2.0), wsg.OK),
+    (dict(kernel="kb", kernel_beta=60.0), wsg.OK),        # FP64: exact series
+    # FP32 mesh: per-tap degree-8 fit, 1.7e-6 off at beta = 60, S = 7
+    (dict(kernel="kb", kernel_beta=60.0, precision="f32_phase64"), wsg.EUNSUPPORTED),
+    (dict(kernel="kb", kernel_beta=25.0, precision="f32_phase64"), wsg.OK),
+    (dict(kernel="kb", support=3, kernel_beta=10.0, precision="f32_phase32"), wsg.EUNSUPPORTED),
 ])
 def test_parameter_validation(kw, code):
     assert wsg.check(_p(**kw), _v()) == code
+
+
+def test_unknown_kernel():
+    p = _p()
+    p.kernel = 2
+    assert wsg.check(p, _v()) == wsg.EINVAL
+
+
+@pytest.mark.parametrize("support", [3, 5, 7, 9, 11, 13, 15])
+def test_kb_default_beta_fits_fp32_mesh(support):
+    """The default Kaiser-Bessel shape of every support passes the FP32 mesh's fit
+    check (its per-tap polynomials within 2e-7 of the exact kernel)."""
+    assert wsg.check(_p(kernel="kb", support=support, precision="f32_phase64"), _v()) == wsg.OK
 
 
 def test_vis_validation():
