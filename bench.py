@@ -7,6 +7,8 @@ with plane sum (Eq. 2), on the single-large-image workload: 256 antennas
 (log-radial, 20 km), 2,048 times, 4 channels -> 267,386,880 complex64
 visibilities onto a 4096^2 x 64-plane complex64 stack, support 7, FP64 phase.
 Inputs are synthetic (seeded), generated on and resident in HBM before timing.
+The gridding kernel is the Gaussian of width 0.9 cells, or with --kernel kb the
+Kaiser-Bessel window of the paper's runs (default beta for the support).
 
 Prints ONE JSON line.  Roofline figures credit the method's own traffic: every
 input byte read once (B_in), the w-stack written once by the gridder and read
@@ -103,7 +105,8 @@ def cpu_baseline(ds_host: dict, params: dict, n_total: int) -> dict:
     m_s = vis.size
     inp = oracle.Inputs.make(uvw, freq, vis, wts)
     n = params["grid_n"]
-    prm1 = oracle.Params(n, 1, params["support"], params["cell_rad"], params["kernel_sigma"])
+    prm1 = oracle.Params(n, 1, params["support"], params["cell_rad"], params["kernel_sigma"],
+                         kernel=params.get("kernel", "gauss"))
     t0 = time.perf_counter()
     wmin, wmax = oracle.w_range(inp, prm1)
     g, cnt = oracle.grid(inp, prm1, wmin, wmax)
@@ -133,6 +136,8 @@ def main():
     ap.add_argument("--rows-stride", type=int, default=1,
                     help="keep every k-th row (quick runs only; not the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", choices=("gauss", "kb"), default="gauss",
+                    help="gridding kernel: Gaussian (sigma 0.9) or Kaiser-Bessel")
     ap.add_argument("--cpu-sample-rows", type=int, default=400_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a reference elementwise pass of known traffic (2 GiB read, "
@@ -164,6 +169,7 @@ def main():
     d = synth.config1_device(dev, rows_stride=args.rows_stride)
     torch.cuda.synchronize()
     progress(f"inputs ready in {time.perf_counter() - t0:.1f} s: vis {tuple(d['vis'].shape)}")
+    d["params"]["kernel"] = args.kernel
     prm = wsg.make_params(**d["params"], tile=TILE)
     vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"], d["row_period"])
     n = d["params"]["grid_n"]
@@ -196,6 +202,8 @@ def main():
     kname = sb[dom][0]
     workload = "config1_4096sq_64w_2.67e8vis" if args.rows_stride == 1 else \
         f"config1_rows_stride_{args.rows_stride}"
+    if args.kernel == "kb":
+        workload += "_kaiser_bessel"
     if kname == "k_grid":
         # VALU / LDS-atomic bound: useful arithmetic per launch over the launch time
         flops = GRID_FLOP_PER_VIS * n_used
@@ -225,7 +233,8 @@ def main():
         "data": "synthetic (seeded, device-generated config-1 interferometer data)",
         "config": {"workload": workload, "grid_n": n, "n_wplanes": d["params"]["n_wplanes"],
                    "support": 7, "visibilities": int(d["vis"].numel()), "n_used": n_used,
-                   "precision": d["params"]["precision"], "tile": TILE},
+                   "precision": d["params"]["precision"], "tile": TILE,
+                   "kernel": args.kernel},
         "roofline": roof,
         "path_roofline": {"bound": "hbm", "B_alg_bytes": model["B_alg"],
                           "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -106,7 +106,10 @@ typedef struct {
     uint32_t flags;        /* WSG_GRID_CORRECT | WSG_NORMALIZE | ...                           */
     int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64     */
     int32_t kernel;        /* WSG_KERNEL_*                                                     */
-    double kernel_beta;    /* Kaiser-Bessel beta (>= 0, finite; 0: the default for S)          */
+    double kernel_beta;    /* Kaiser-Bessel beta (0 .. 64; 0: the default for S, which S = 1  */
+                           /*   lacks: WSG_EINVAL).  FP32 meshes take each tap from a fitted   */
+                           /*   degree-8 polynomial; a beta it cannot follow within 2e-7 is    */
+                           /*   WSG_EUNSUPPORTED there (the FP64 mesh takes any beta)          */
 } wsg_params;
 
 typedef struct {

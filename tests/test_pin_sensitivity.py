@@ -63,3 +63,28 @@ def test_wrong_plane_w_is_caught(config0, monkeypatch):
     monkeypatch.setattr(oracle, "plane_w", lower_edge)
     bad = oracle.image(oracle.Inputs.make(uvw, None, vis, wts), prm)
     assert np.abs(bad["image"][0][q, p] - Dq).max() > bound
+
+
+def test_kaiser_bessel_mistakes_are_caught():
+    """Plausible slips in the Kaiser-Bessel window (argument scaled by S instead of S/2,
+    no 1/I0(beta), the default beta without the oversampling factor) each fail the
+    kernel-value pin against scipy's I0."""
+    from scipy.special import i0
+    S = 7
+    beta = oracle.kb_default_beta(S)
+    x = np.linspace(0.0, S / 2, 21)
+    d = np.concatenate([-x[::-1], x])
+
+    def ref(d, b=beta):
+        t = 2.0 * d / S
+        return i0(b * np.sqrt(np.clip(1.0 - t * t, 0.0, None))) / i0(b)
+
+    good = oracle.kernel_value(oracle.Params(64, 1, S, 1.0, kernel="kb"), d)
+    assert np.abs(good - ref(d)).max() <= 1e-14
+    slips = {
+        "d/S": i0(beta * np.sqrt(np.clip(1.0 - (d / S) ** 2, 0.0, None))) / i0(beta),
+        "no 1/I0(beta)": ref(d) * i0(beta),
+        "beta without 1.5": ref(d, np.pi * np.sqrt((S / 2) ** 2 - 0.8)),
+    }
+    for name, bad in slips.items():
+        assert np.abs(bad - ref(d)).max() > 1e-6, name
