@@ -212,6 +212,54 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
                               double *image, int32_t mem, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Chunked imaging: data larger than one call, loaded chunk after chunk by time
+ * or by frequency (Sec. 6), onto one resident w-stack
+ * ------------------------------------------------------------------------- */
+/*
+ * An accumulator owns the w-stack of one imaging job (n_images x planes x N x N,
+ * complex64 or complex128; wsg_accum_footprint says how much) plus small state.
+ * Each wsg_accum_add bins and grids one chunk of visibilities (Eq. 3) into it;
+ * wsg_accum_finish transforms, w-corrects and sums the planes (Eq. 2) into the
+ * image.  The result equals wsg_image over the concatenated chunks (up to the
+ * order of floating-point sums).
+ *
+ * Rules:
+ *   - the w range must be given (w_min, w_max finite): planes are fixed before
+ *     the data are seen; a plane range [plane_lo, plane_hi) is allowed;
+ *   - n_chan: with WSG_PER_CHANNEL every chunk has n_chan channels (a chunk of
+ *     time of a cube); without it (one image) chunks may differ in n_chan and
+ *     freq_hz (chunks of frequency);
+ *   - the tile size is fixed by the parameters at begin (0: the library choice
+ *     for N and S);
+ *   - the calls on one accumulator and its context must not overlap; the
+ *     context may run other jobs between them (each chunk's binning workspace
+ *     is the context's).
+ * Host chunks are copied to the device on a copy stream of the accumulator:
+ * the copy of one chunk overlaps the scatter and gridding of the previous one
+ * (from pinned host memory the copy runs at full rate).  A chunk's host
+ * buffers may be reused when wsg_accum_add returns.
+ * Errors: WSG_EINVAL (bad parameters, w range not given, n_chan mismatch),
+ * WSG_ENOMEM (stack allocation), WSG_EDEVICE.  An error during add leaves the
+ * accumulator unusable (finish returns WSG_EINVAL); destroy it.
+ */
+typedef struct wsg_accum wsg_accum;
+/* Allocate and clear the w-stack on `stream`.  *out is NULL on error. */
+wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, void *stream,
+                           wsg_accum **out);
+/* Device bytes the accumulator itself holds (stack, occupancy, state). */
+wsg_status wsg_accum_footprint(const wsg_params *p, int32_t n_chan, uint64_t *bytes);
+/* Bin and grid one chunk (may be empty).  Returns once the chunk's work is
+ * enqueued on `stream` (the chunk's record count is read back on the way). */
+wsg_status wsg_accum_add(wsg_accum *a, const wsg_vis *chunk, void *stream);
+/* Transform, w-correct, sum and post-process into image (as wsg_image); stats
+ * (NULL or n_images entries) cover every chunk added: n_records is their sum,
+ * the stage times are 0.  The accumulator can be finished once. */
+wsg_status wsg_accum_finish(wsg_accum *a, double *image, int32_t image_mem, void *stream,
+                            wsg_stats *stats);
+/* Wait for the accumulator's work and free it.  NULL is a no-op. */
+void wsg_accum_destroy(wsg_accum *a);
+
+/* ---------------------------------------------------------------------------
  * Tuning
  * ------------------------------------------------------------------------- */
 /* Time the whole imaging path at each binning tile size (16, 32, 64) on this

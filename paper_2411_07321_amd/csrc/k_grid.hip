@@ -16,6 +16,8 @@
 // Eq. 3), from the tables described with KbTable.
 #include "wsg_internal.h"
 
+#include <algorithm>
+
 namespace wsg {
 
 namespace {
@@ -158,7 +160,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                                                         const uint32_t *__restrict__ item_bin,
                                                         uint32_t chunk,
                                                         const typename RecTraits<T>::Rec *__restrict__ rec,
-                                                        C2<T> *__restrict__ grid, int transposed) {
+                                                        C2<T> *__restrict__ grid, int transposed,
+                                                        int accumulate) {
     constexpr int TP = TT + 1;
     constexpr int H = (SS - 1) / 2;
     // the tile sums many contributions per cell: kept in FP64 for every mesh type,
@@ -169,7 +172,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t b = item_bin[item];
     const uint32_t c = item - item_off[b];
     const uint32_t cnt = counts[b];
-    const bool split = cnt > chunk;
+    // add into the stack (a split bin, or a stack that holds earlier chunks)
+    const bool split = accumulate || cnt > chunk;
     const uint32_t r0 = offsets[b] + c * chunk;
     const uint32_t r1 = offsets[b] + min(cnt, (c + 1) * chunk);
 
@@ -410,22 +414,22 @@ __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__
 template <typename T, int TT, int SS>
 void launch_tile(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
                  const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
-                 uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr) {
+                 uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
     constexpr bool ACC = (sizeof(T) == 4) && SS <= 7;
     if (g.kernel == 1)
         k_grid<T, TT, SS, ACC, 1><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
-                                                                chunk, r, gp, tr);
+                                                                chunk, r, gp, tr, acc);
     else
         k_grid<T, TT, SS, ACC, 0><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
-                                                                chunk, r, gp, tr);
+                                                                chunk, r, gp, tr, acc);
 }
 
 template <typename T, int TT>
 void launch_support(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
                     const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
-                    uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr) {
+                    uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
     switch (g.S) {
-#define WSG_S(ss) case ss: launch_tile<T, TT, ss>(g, grid, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+#define WSG_S(ss) case ss: launch_tile<T, TT, ss>(g, grid, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
     WSG_S(1) WSG_S(3) WSG_S(5) WSG_S(7) WSG_S(9) WSG_S(11) WSG_S(13) WSG_S(15)
 #undef WSG_S
     default: break;
@@ -436,16 +440,16 @@ template <typename T>
 void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
                    const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
                    uint32_t chunk, const void *records, void *grid, bool transposed,
-                   hipStream_t s) {
+                   bool accumulate, hipStream_t s) {
     using Rec = typename RecTraits<T>::Rec;
     const Rec *r = (const Rec *)records;
     C2<T> *gp = (C2<T> *)grid;
-    int tr = transposed ? 1 : 0;
+    int tr = transposed ? 1 : 0, acc = accumulate ? 1 : 0;
     dim3 gd(n_items);
     switch (g.T) {
-    case 16: launch_support<T, 16>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
-    case 32: launch_support<T, 32>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
-    case 64: launch_support<T, 64>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr); break;
+    case 16: launch_support<T, 16>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
+    case 32: launch_support<T, 32>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
+    case 64: launch_support<T, 64>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
     default: break;
     }
 }
@@ -477,6 +481,35 @@ void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint3
 
 int occupancy_words(int NT) { return (NT + 63) / 64; }
 
+namespace {
+
+// Fold one chunk of a chunked job into its accumulator: bins that received records
+// (for the tile occupancy of the final stack), and the chunk's counts, weight sum
+// and plane geometry (the w range is given, so every chunk has the same).
+// Chunks are folded in call order, so the FP64 weight sum is deterministic.
+__global__ void k_accum_chunk(const uint32_t *__restrict__ counts, uint32_t *__restrict__ seen,
+                              size_t n_bins, const ImgState *__restrict__ st, ImgState *acc, int n_img,
+                              const uint32_t *__restrict__ overflow, uint32_t *acc_overflow) {
+    for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins;
+         b += (size_t)gridDim.x * blockDim.x)
+        if (counts[b] != 0u) seen[b] = 1u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < n_img; ++i) {
+            acc[i].n_flagged += st[i].n_flagged;
+            acc[i].n_valid0 += st[i].n_valid0;
+            acc[i].n_used += st[i].n_used;
+            acc[i].sum_w += st[i].sum_w;
+            acc[i].w_min = st[i].w_min;
+            acc[i].w_max = st[i].w_max;
+            acc[i].dw = st[i].dw;
+            acc[i].inv_dw = st[i].inv_dw;
+        }
+        acc_overflow[0] += overflow[0];
+    }
+}
+
+}  // namespace
+
 void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
                       uint16_t *live2, ImgState *st, hipStream_t s) {
     const unsigned n_planes = (unsigned)(g.n_img * g.n_pl);
@@ -487,14 +520,22 @@ void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, 
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
                  const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
                  uint32_t chunk, const void *records, void *grid, bool transposed,
-                 hipStream_t s) {
+                 bool accumulate, hipStream_t s) {
     if (n_items == 0) return;
     if (f64)
         dispatch_grid<double>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
-                              transposed, s);
+                              transposed, accumulate, s);
     else
         dispatch_grid<float>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
-                             transposed, s);
+                             transposed, accumulate, s);
+}
+
+void launch_accum_chunk(const uint32_t *counts, uint32_t *seen, size_t n_bins, const ImgState *st,
+                        ImgState *acc, int n_img, const uint32_t *overflow, uint32_t *acc_overflow,
+                        hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<size_t>((n_bins + 255) / 256, 65535);
+    k_accum_chunk<<<std::max(blocks, 1u), 256, 0, s>>>(counts, seen, n_bins, st, acc, n_img, overflow,
+                                                       acc_overflow);
 }
 
 }  // namespace wsg

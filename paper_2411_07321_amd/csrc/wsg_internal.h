@@ -177,10 +177,17 @@ void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, 
 // zero_empty, those of empty bins (which have no work item).
 void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
                        bool zero_empty, void *grid, bool transposed, hipStream_t s);
+// accumulate: every tile is added into `grid` (which holds earlier chunks) instead
+// of stored; otherwise single-item tiles are stored and split ones added
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
                  const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
                  uint32_t chunk, const void *records, void *grid, bool transposed,
-                 hipStream_t s);
+                 bool accumulate, hipStream_t s);
+// chunked jobs: seen[bin] = 1 where the chunk has records; counts, weight sum and
+// plane geometry of the chunk's state folded into acc; overflow counters summed
+void launch_accum_chunk(const uint32_t *counts, uint32_t *seen, size_t n_bins, const ImgState *st,
+                        ImgState *acc, int n_img, const uint32_t *overflow, uint32_t *acc_overflow,
+                        hipStream_t s);
 
 // transforms.  Pass 1: rows of planes [n][N][N] (in place) into the blocked
 // layout [N/B][N][B]; pass 2: along the other axis.

@@ -314,7 +314,9 @@ struct Plan {
     size_t o_cls_counts;
 };
 
-Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image_out,
+// with_stack false: binning workspace only (chunks of a chunked job, whose stack,
+// occupancy and image live in the accumulator)
+Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
                bool host_out_image) {
     Plan pl{};
     pl.N = p->grid_n;
@@ -357,12 +359,13 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool stage_image
     pl.n_stretch = stretch_threads(v->n_chan, pl.P, pl.n_tb);
     {
         const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.n_pl;
-        pl.o_occ_rows = take(np * nw * 8);
-        pl.o_occ_live1 = take(np * pl.NT * (pl.N / 16) * 4);
-        pl.o_occ_live2 = take(np * (pl.N / 16) * 2);
+        const size_t k = with_stack ? 1 : 0;
+        pl.o_occ_rows = take(k * np * nw * 8);
+        pl.o_occ_live1 = take(k * np * pl.NT * (pl.N / 16) * 4);
+        pl.o_occ_live2 = take(k * np * (pl.N / 16) * 2);
+        pl.o_stack = take(k * np * pl.N * pl.N * (pl.f64 ? 16 : 8));
+        pl.o_image = take(host_out_image ? (size_t)pl.n_img * pl.N * pl.N * 8 : 0);
     }
-    pl.o_stack = take((size_t)pl.n_img * pl.n_pl * pl.N * pl.N * (pl.f64 ? 16 : 8));
-    pl.o_image = take(host_out_image ? (size_t)pl.n_img * pl.N * pl.N * (stage_image_out ? 8 : 8) : 0);
     pl.o_aux = take(0);
     pl.fixed_bytes = off;
     double rep = (double)(tile + pl.S - 1) / tile;
@@ -587,9 +590,9 @@ struct Binned {
 // Stage inputs, validity pass, counting sort and record scatter.  Ends with
 // the records binned; the grid kernel is launched by the caller.
 wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStream_t s, bool image_host,
-                   Binned &b) {
-    int tile = choose_tile(ctx, p, v);
-    b.pl = make_plan(p, v, tile, true, image_host);
+                   Binned &b, int tile_fixed = 0, bool with_stack = true) {
+    int tile = tile_fixed ? tile_fixed : choose_tile(ctx, p, v);
+    b.pl = make_plan(p, v, tile, with_stack, image_host);
     Plan &pl = b.pl;
     if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
     size_t dyn_est = dyn_bytes(pl, pl.records_est, pl.items_est);
@@ -735,7 +738,7 @@ wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, boo
     launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, dense, grid, transposed, s);
     mark(ctx, kMarkZero, s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
-                b.records, grid, transposed, s);
+                b.records, grid, transposed, false, s);
     mark(ctx, kMarkGrid, s);
     if (!dense)
         launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
@@ -811,11 +814,6 @@ wsg_status common_checks(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
     return WSG_OK;
 }
 
-}  // namespace
-
-// ============================================================================
-// C ABI
-// ============================================================================
 // Gridding, both transform passes and the w-correction of a binned job, into the
 // device image img_dev [n_img][N][N].
 wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *img_dev, hipStream_t s) {
@@ -854,6 +852,112 @@ wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *im
     return WSG_OK;
 }
 
+// ---------------------------------------------------------------- chunked jobs
+// The accumulator's own device block: state, bins seen, overflow counter,
+// occupancy bitmaps, the w-stack and (for host images) the image.
+struct AccumLayout {
+    size_t o_state, o_seen, o_overflow, o_rows, o_live1, o_live2, o_stack, o_image, bytes;
+};
+
+AccumLayout accum_layout(const wsg_params *p, int n_img, int tile) {
+    AccumLayout L{};
+    const int N = p->grid_n, NT = N / tile;
+    const int n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    const size_t np = (size_t)n_img * n_pl, n_bins = np * NT * NT;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.o_state = take((size_t)n_img * sizeof(ImgState));
+    L.o_seen = take(n_bins * 4);
+    L.o_overflow = take(4);
+    L.o_rows = take(np * occupancy_words(NT) * 8);
+    L.o_live1 = take(np * NT * (N / 16) * 4);
+    L.o_live2 = take(np * (N / 16) * 2);
+    L.o_stack = take(np * N * N * (f64_mode(p) ? 16 : 8));
+    L.o_image = take((size_t)n_img * N * N * 8);
+    L.bytes = off;
+    return L;
+}
+
+wsg_status check_accum(const wsg_params *p, int32_t n_chan, std::string &why) {
+    wsg_status rc = check_params(p, why);
+    if (rc) return rc;
+    if (n_chan < 1 || n_chan > 4096) { why = "n_chan must be 1 .. 4096"; return WSG_EINVAL; }
+    if ((p->flags & WSG_PER_CHANNEL) && n_chan > 256) { why = "more than 256 channels per cube"; return WSG_EUNSUPPORTED; }
+    if (!range_given(p)) { why = "chunked imaging needs a given w range (w_min, w_max)"; return WSG_EINVAL; }
+    return WSG_OK;
+}
+
+}  // namespace
+
+struct wsg_accum {
+    wsg_ctx *ctx = nullptr;
+    wsg_params p{};
+    int32_t n_chan = 0;
+    int n_img = 0, tile = 0;
+    bool per_channel = false, broken = false, finished = false;
+    JobGeom g{};                   // mesh geometry for the occupancy pass
+    size_t n_bins = 0;
+    AccumLayout L{};
+    char *mem = nullptr;
+    int64_t per_img_elems = 0;     // elements offered to each image, over all chunks
+    int64_t n_records = 0;
+    // host chunks: two device slots filled on the copy stream
+    hipStream_t copy = nullptr;
+    void *slot[2] = {nullptr, nullptr};
+    size_t slot_size[2] = {0, 0};
+    hipEvent_t copied[2] = {nullptr, nullptr}, slot_free[2] = {nullptr, nullptr};
+    int next_slot = 0;
+};
+
+namespace {
+
+// Device copy of a host chunk in the accumulator's next slot, on its copy stream,
+// ordered after the last job that read the slot; the compute stream waits for it.
+wsg_status stage_chunk(wsg_accum *a, const wsg_vis *v, hipStream_t s, wsg_vis *dv, int *used) {
+    wsg_ctx *ctx = a->ctx;
+    const bool f64 = f64_mode(&a->p);
+    const size_t n_elem = (size_t)v->n_rows * v->n_chan;
+    const size_t b_uvw = align_up((size_t)v->n_rows * 24), b_vis = align_up(n_elem * (f64 ? 16 : 8));
+    const size_t b_wts = v->weights ? align_up(n_elem * (f64 ? 8 : 4)) : 0;
+    const size_t b_fl = v->flags ? align_up(n_elem) : 0;
+    const size_t need = b_uvw + b_vis + b_wts + b_fl;
+    const int k = a->next_slot;
+    if (need > a->slot_size[k]) {
+        WSG_HIP(ctx, hipEventSynchronize(a->slot_free[k]));
+        if (a->slot[k]) WSG_HIP(ctx, hipFree(a->slot[k]));
+        a->slot[k] = nullptr;
+        a->slot_size[k] = 0;
+        WSG_HIP(ctx, hipMalloc(&a->slot[k], need));
+        a->slot_size[k] = need;
+    }
+    char *d = (char *)a->slot[k];
+    WSG_HIP(ctx, hipStreamWaitEvent(a->copy, a->slot_free[k], 0));
+    WSG_HIP(ctx, hipMemcpyAsync(d, v->uvw, (size_t)v->n_rows * 24, hipMemcpyHostToDevice, a->copy));
+    WSG_HIP(ctx, hipMemcpyAsync(d + b_uvw, v->vis, n_elem * (f64 ? 16 : 8), hipMemcpyHostToDevice, a->copy));
+    if (v->weights)
+        WSG_HIP(ctx, hipMemcpyAsync(d + b_uvw + b_vis, v->weights, n_elem * (f64 ? 8 : 4),
+                                    hipMemcpyHostToDevice, a->copy));
+    if (v->flags)
+        WSG_HIP(ctx, hipMemcpyAsync(d + b_uvw + b_vis + b_wts, v->flags, n_elem, hipMemcpyHostToDevice,
+                                    a->copy));
+    WSG_HIP(ctx, hipEventRecord(a->copied[k], a->copy));
+    WSG_HIP(ctx, hipStreamWaitEvent(s, a->copied[k], 0));
+    *dv = *v;
+    dv->mem = WSG_MEM_DEVICE;
+    dv->uvw = (const double *)d;
+    dv->vis = d + b_uvw;
+    dv->weights = v->weights ? d + b_uvw + b_vis : nullptr;
+    dv->flags = v->flags ? (const uint8_t *)(d + b_uvw + b_vis + b_wts) : nullptr;
+    *used = k;
+    a->next_slot = k ^ 1;
+    return WSG_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
 extern "C" {
 
 wsg_status wsg_create(int device, wsg_ctx **out) {
@@ -1164,6 +1268,216 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
     return WSG_OK;
 }
 
+// ---------------------------------------------------------------- chunked jobs
+wsg_status wsg_accum_footprint(const wsg_params *p, int32_t n_chan, uint64_t *bytes) {
+    if (!p || !bytes) return WSG_EINVAL;
+    std::string why;
+    wsg_status rc = check_accum(p, n_chan, why);
+    if (rc) return rc;
+    const int n_img = (p->flags & WSG_PER_CHANNEL) ? n_chan : 1;
+    *bytes = accum_layout(p, n_img, p->tile ? p->tile : default_tile(p)).bytes;
+    return WSG_OK;
+}
+
+wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, void *stream,
+                           wsg_accum **out) {
+    if (!out) return WSG_EINVAL;
+    *out = nullptr;
+    wsg_status rc = common_checks(ctx, p, nullptr);
+    if (rc) return rc;
+    std::string why;
+    rc = check_accum(p, n_chan, why);
+    if (rc) return fail(ctx, rc, why);
+    hipStream_t s = pick_stream(ctx, stream);
+    wsg_accum *a = new (std::nothrow) wsg_accum();
+    if (!a) return fail(ctx, WSG_ENOMEM, "accumulator");
+    a->ctx = ctx;
+    a->p = *p;
+    a->n_chan = n_chan;
+    a->per_channel = (p->flags & WSG_PER_CHANNEL) != 0;
+    a->n_img = a->per_channel ? n_chan : 1;
+    a->tile = p->tile ? p->tile : default_tile(p);
+    a->L = accum_layout(p, a->n_img, a->tile);
+    JobGeom &g = a->g;
+    g.N = p->grid_n;
+    g.n_img = a->n_img;
+    g.n_w = p->n_wplanes;
+    g.plane_lo = (p->plane_hi > p->plane_lo) ? p->plane_lo : 0;
+    g.n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    g.S = p->support;
+    g.h = (p->support - 1) / 2;
+    g.T = a->tile;
+    g.NT = g.N / g.T;
+    while ((1 << g.logT) < g.T) ++g.logT;
+    while ((1 << g.logNT) < g.NT) ++g.logNT;
+    a->n_bins = (size_t)a->n_img * g.n_pl * g.NT * g.NT;
+    auto undo = [&](wsg_status st) {
+        wsg_accum_destroy(a);
+        return st;
+    };
+    if (ctx->budget && ctx->fixed.size + ctx->dyn.size + a->L.bytes > ctx->budget)
+        return undo(fail(ctx, WSG_ENOMEM, "accumulator of " + std::to_string(a->L.bytes) +
+                                              " bytes exceeds the context budget"));
+    if (hipStreamCreateWithFlags(&a->copy, hipStreamNonBlocking) != hipSuccess)
+        return undo(fail(ctx, WSG_EDEVICE, "copy stream"));
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&a->copied[k], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&a->slot_free[k], hipEventDisableTiming) != hipSuccess)
+            return undo(fail(ctx, WSG_EDEVICE, "accumulator events"));
+    hipError_t e = hipMalloc((void **)&a->mem, a->L.bytes);
+    if (e != hipSuccess) {
+        a->mem = nullptr;
+        return undo(fail(ctx, e == hipErrorOutOfMemory ? WSG_ENOMEM : WSG_EDEVICE,
+                         std::string("accumulator: ") + hipGetErrorString(e)));
+    }
+    // everything starts at zero except the plane geometry of the state, which the
+    // chunks overwrite with their own (identical) values; here it only keeps an
+    // accumulator without chunks finite
+    std::vector<ImgState> init(a->n_img);
+    for (auto &x : init) {
+        std::memset(&x, 0, sizeof(x));
+        x.w_min = p->w_min;
+        x.w_max = p->w_max;
+        x.dw = (p->w_max - p->w_min) / p->n_wplanes;
+    }
+    if (hipMemsetAsync(a->mem, 0, a->L.bytes, s) != hipSuccess ||
+        hipMemcpyAsync(a->mem + a->L.o_state, init.data(), init.size() * sizeof(ImgState),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return undo(fail(ctx, WSG_EDEVICE, "accumulator initialisation"));
+    *out = a;
+    return WSG_OK;
+}
+
+wsg_status wsg_accum_add(wsg_accum *a, const wsg_vis *v, void *stream) {
+    if (!a) return WSG_EINVAL;
+    wsg_ctx *ctx = a->ctx;
+    if (a->broken || a->finished) return fail(ctx, WSG_EINVAL, "accumulator finished or failed");
+    wsg_status rc = common_checks(ctx, &a->p, v);
+    if (rc) return rc;
+    if (a->per_channel && v->n_chan != a->n_chan)
+        return fail(ctx, WSG_EINVAL, "a chunk of a cube must have the accumulator's n_chan");
+    hipStream_t s = pick_stream(ctx, stream);
+    a->per_img_elems += a->per_channel ? v->n_rows : v->n_rows * (int64_t)v->n_chan;
+    if (v->n_rows == 0) return WSG_OK;
+    wsg_vis dv;
+    const wsg_vis *vd = v;
+    int slot = -1;
+    if (v->mem == WSG_MEM_HOST) {
+        rc = stage_chunk(a, v, s, &dv, &slot);
+        if (rc) { a->broken = true; return rc; }
+        vd = &dv;
+    }
+    Binned b;
+    rc = bin_job(ctx, &a->p, vd, s, false, b, a->tile, false);
+    if (rc) { a->broken = true; return rc; }
+    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk, b.records,
+                a->mem + a->L.o_stack, true, true, s);
+    launch_accum_chunk(b.counts, (uint32_t *)(a->mem + a->L.o_seen), a->n_bins, b.st,
+                       (ImgState *)(a->mem + a->L.o_state), a->n_img, b.overflow,
+                       (uint32_t *)(a->mem + a->L.o_overflow), s);
+    if (slot >= 0) {
+        hipError_t e = hipEventRecord(a->slot_free[slot], s);
+        if (e != hipSuccess) { a->broken = true; return fail(ctx, WSG_EDEVICE, "slot event"); }
+    }
+    a->n_records += b.n_records;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { a->broken = true; return fail(ctx, WSG_EDEVICE, hipGetErrorString(e)); }
+    return WSG_OK;
+}
+
+wsg_status wsg_accum_finish(wsg_accum *a, double *image, int32_t image_mem, void *stream,
+                            wsg_stats *stats) {
+    if (!a) return WSG_EINVAL;
+    wsg_ctx *ctx = a->ctx;
+    if (a->broken || a->finished) return fail(ctx, WSG_EINVAL, "accumulator finished or failed");
+    if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
+    if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    a->finished = true;
+    const wsg_params *p = &a->p;
+    const bool f64 = f64_mode(p), host_img = image_mem == WSG_MEM_HOST;
+    ImgState *st = (ImgState *)(a->mem + a->L.o_state);
+    void *stack = a->mem + a->L.o_stack;
+    double *img_dev = host_img ? (double *)(a->mem + a->L.o_image) : image;
+    const void *tw = nullptr;
+    wsg_status rc = get_twiddle(ctx, p->grid_n, f64, &tw);
+    if (rc) return rc;
+    const double *inv_c = nullptr;
+    rc = get_inv_c(ctx, p, s, &inv_c);
+    if (rc) return rc;
+    launch_post_norm(a->n_img, st, (p->flags & WSG_NORMALIZE) != 0, s);
+    Occupancy occ;
+    occ.rows = (const uint64_t *)(a->mem + a->L.o_rows);
+    occ.live1 = (const uint32_t *)(a->mem + a->L.o_live1);
+    occ.live2 = (const uint16_t *)(a->mem + a->L.o_live2);
+    occ.logT = a->g.logT;
+    occ.nw = occupancy_words(a->g.NT);
+    launch_occupancy(a->g, (const uint32_t *)(a->mem + a->L.o_seen), (uint64_t *)occ.rows,
+                     (uint32_t *)occ.live1, (uint16_t *)occ.live2, st, s);
+    launch_fft_pass1(p->grid_n, f64, stack, (int64_t)a->n_img * a->g.n_pl, tw, occ, s);
+    WcorrArgs w{};
+    w.N = p->grid_n;
+    w.n_img = a->n_img;
+    w.n_pl = a->g.n_pl;
+    w.plane_lo = a->g.plane_lo;
+    w.n_w = p->n_wplanes;
+    w.phase32 = p->precision == WSG_PREC_F32_PHASE32;
+    w.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
+    w.cell = p->cell_rad;
+    w.st = st;
+    w.inv_c = inv_c;
+    w.occ = occ;
+    launch_fft_pass2_wcorr(w, f64, stack, tw, img_dev, s);
+    WSG_HIP(ctx, hipGetLastError());
+    if (host_img) {
+        WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)a->n_img * p->grid_n * p->grid_n * 8,
+                                    hipMemcpyDeviceToHost, s));
+        WSG_HIP(ctx, hipStreamSynchronize(s));
+    }
+    if (!stats) return WSG_OK;
+    rc = ensure_pin(ctx, align_up(4) + (size_t)a->n_img * sizeof(ImgState));
+    if (rc) return rc;
+    char *h = (char *)ctx->pin;
+    WSG_HIP(ctx, hipMemcpyAsync(h, a->mem + a->L.o_overflow, 4, hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipMemcpyAsync(h + align_up(4), st, (size_t)a->n_img * sizeof(ImgState),
+                                hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipStreamSynchronize(s));
+    if (*(const uint32_t *)h != 0)
+        return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
+    const ImgState *hs = (const ImgState *)(h + align_up(4));
+    for (int i = 0; i < a->n_img; ++i) {
+        std::memset(&stats[i], 0, sizeof(wsg_stats));
+        stats[i].n_used = (int64_t)hs[i].n_used;
+        stats[i].n_flagged = (int64_t)hs[i].n_flagged;
+        stats[i].n_dropped = a->per_img_elems - stats[i].n_used - stats[i].n_flagged;
+        stats[i].n_records = a->n_records;
+        stats[i].n_tiles = (int64_t)hs[i].n_tiles;
+        stats[i].n_tile_rows = (int64_t)hs[i].n_tile_rows;
+        stats[i].sum_w = hs[i].sum_w;
+        stats[i].w_min = hs[i].w_min;
+        stats[i].w_max = hs[i].w_max;
+    }
+    return WSG_OK;
+}
+
+void wsg_accum_destroy(wsg_accum *a) {
+    if (!a) return;
+    (void)hipSetDevice(a->ctx->device);
+    if (a->ctx->has_last) (void)hipStreamSynchronize(a->ctx->last_stream);
+    if (a->copy) (void)hipStreamSynchronize(a->copy);
+    for (int k = 0; k < 2; ++k) {
+        if (a->slot_free[k]) (void)hipEventSynchronize(a->slot_free[k]);
+        if (a->slot[k]) (void)hipFree(a->slot[k]);
+        if (a->copied[k]) (void)hipEventDestroy(a->copied[k]);
+        if (a->slot_free[k]) (void)hipEventDestroy(a->slot_free[k]);
+    }
+    if (a->mem) (void)hipFree(a->mem);
+    if (a->copy) (void)hipStreamDestroy(a->copy);
+    delete a;
+}
+
 }  // extern "C"
 
 // device bytes held by a context (its arenas and cached tables), for the server
@@ -1171,5 +1485,6 @@ uint64_t wsg_ctx_device_bytes(const wsg_ctx *ctx) {
     uint64_t b = ctx->fixed.size + ctx->dyn.size;
     for (auto &kv : ctx->twiddles) b += kv.second.size;
     for (auto &kv : ctx->inv_c) b += kv.second.size;
+    for (auto &kv : ctx->kb) b += kv.second.size;
     return b;
 }

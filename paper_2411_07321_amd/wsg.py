@@ -27,7 +27,9 @@ SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_s
            "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image",
            "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune",
            "wsg_server_create", "wsg_server_destroy", "wsg_server_submit", "wsg_server_poll",
-           "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream")
+           "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream",
+           "wsg_accum_begin", "wsg_accum_footprint", "wsg_accum_add", "wsg_accum_finish",
+           "wsg_accum_destroy")
 
 
 class WsgError(RuntimeError):
@@ -134,11 +136,19 @@ def load() -> ctypes.CDLL:
         lib.wsg_trim.argtypes = [P]
         lib.wsg_context_stream.argtypes = [P]
         lib.wsg_context_stream.restype = P
+        lib.wsg_accum_begin.argtypes = [P, ctypes.POINTER(Params), S, P, ctypes.POINTER(P)]
+        lib.wsg_accum_footprint.argtypes = [ctypes.POINTER(Params), S,
+                                            ctypes.POINTER(ctypes.c_uint64)]
+        lib.wsg_accum_add.argtypes = [P, ctypes.POINTER(Vis), P]
+        lib.wsg_accum_finish.argtypes = [P, P, S, P, ctypes.POINTER(Stats)]
+        lib.wsg_accum_destroy.argtypes = [P]
+        lib.wsg_accum_destroy.restype = None
         for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check",
                      "wsg_footprint", "wsg_image", "wsg_stage_grid", "wsg_stage_fft",
                      "wsg_stage_wcorrect", "wsg_autotune", "wsg_server_create",
                      "wsg_server_submit", "wsg_server_poll", "wsg_server_wait",
-                     "wsg_server_memory", "wsg_trim"):
+                     "wsg_server_memory", "wsg_trim", "wsg_accum_begin", "wsg_accum_footprint",
+                     "wsg_accum_add", "wsg_accum_finish"):
             getattr(lib, name).restype = S
         lib.wsg_n_images.restype = S
         _lib = lib
@@ -320,6 +330,63 @@ class Context:
                                  ctypes.byref(best))
         self._check(rc, "wsg_autotune")
         return int(best.value)
+
+
+class Accum:
+    """A chunked imaging job on a context: begin (allocates and clears the w-stack),
+    add chunks of visibilities (time or frequency slices), finish into the image.
+    Needs a given w range.  Use as a context manager or call close()."""
+
+    def __init__(self, ctx: Context, params: Params, n_chan: int, stream=None):
+        h = ctypes.c_void_p()
+        self._ctx = ctx
+        self._params = params
+        self._n_img = n_chan if (params.flags & PER_CHANNEL) else 1
+        rc = load().wsg_accum_begin(ctx._h, ctypes.byref(params), int(n_chan), stream,
+                                    ctypes.byref(h))
+        ctx._check(rc, "wsg_accum_begin")
+        self._h = h
+
+    def add(self, vb: VisBuffers, stream=None):
+        """Bin and grid one chunk; device chunks run on torch's current stream unless a
+        stream is given, host chunks on HIP's null stream."""
+        keep = vb.keep
+        s = _stream_of(next((x for x in keep if x is not None and _is_torch(x)), None), stream)
+        self._ctx._check(load().wsg_accum_add(self._h, ctypes.byref(vb.desc), s), "wsg_accum_add")
+
+    def finish(self, out, stream=None):
+        """Transform, w-correct and sum into `out` ([n_images,N,N] float64, host array or
+        device tensor); returns per-image stats of all chunks."""
+        po, mo = _ptr_mem(out)
+        st_arr = (Stats * self._n_img)()
+        rc = load().wsg_accum_finish(self._h, po, mo, _stream_of(out, stream), st_arr)
+        self._ctx._check(rc, "wsg_accum_finish")
+        return [x.as_dict() for x in st_arr]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wsg_accum_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def accum_footprint(params: Params, n_chan: int) -> int:
+    out = ctypes.c_uint64(0)
+    st = load().wsg_accum_footprint(ctypes.byref(params), int(n_chan), ctypes.byref(out))
+    if st != OK:
+        raise WsgError(st, f"wsg_accum_footprint: {strerror(st)}")
+    return int(out.value)
 
 
 class Server:

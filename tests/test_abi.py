@@ -146,3 +146,21 @@ def test_load_binds_to_torchs_hip_runtime():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "True"
+
+
+def test_accum_footprint_and_rules():
+    """The chunked accumulator holds the w-stack (N_w x N^2 cells) and needs a given w
+    range; its footprint is known before any device work."""
+    ok = _p(w_min=-5.0, w_max=5.0)
+    f = wsg.accum_footprint(ok, 1)
+    assert f >= 8 * 256 * 256 * 16
+    assert wsg.accum_footprint(_p(w_min=-5.0, w_max=5.0, precision="f32_phase64"), 1) < f
+    cube = wsg.accum_footprint(_p(w_min=-5.0, w_max=5.0, per_channel=True), 3)
+    assert cube >= 3 * 8 * 256 * 256 * 16
+    for bad, code in ((_p(), wsg.EINVAL), (_p(w_min=1.0, w_max=0.0), wsg.EINVAL)):
+        with pytest.raises(wsg.WsgError) as e:
+            wsg.accum_footprint(bad, 1)
+        assert e.value.status == code
+    with pytest.raises(wsg.WsgError) as e:
+        wsg.accum_footprint(ok, 0)
+    assert e.value.status == wsg.EINVAL
