@@ -52,6 +52,10 @@ struct wsg_ctx {
     std::map<std::pair<int, int>, DevBuf> twiddles;                       // (N, f64)
     std::map<std::tuple<int, int, int, double>, DevBuf> inv_c;            // (N, S, kernel, shape)
     std::map<std::pair<int, double>, DevBuf> kb;                          // (S, beta)
+    // device blocks of the last finished chunked job (w-stack block and the two
+    // chunk slots), handed to the next one so that a stream of chunked jobs does
+    // not allocate
+    DevBuf acc_spare, slot_spare[2];
     std::map<std::tuple<int, int, int, int, int>, int> tuned;             // -> tile
     // pinned host staging
     void *pin = nullptr;
@@ -899,6 +903,7 @@ struct wsg_accum {
     size_t n_bins = 0;
     AccumLayout L{};
     char *mem = nullptr;
+    size_t mem_size = 0;
     int64_t per_img_elems = 0;     // elements offered to each image, over all chunks
     int64_t n_records = 0;
     // host chunks: two device slots filled on the copy stream
@@ -996,6 +1001,8 @@ void wsg_destroy(wsg_ctx *ctx) {
     for (auto &kv : ctx->twiddles) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->inv_c) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->kb) (void)hipFree(kv.second.ptr);
+    for (DevBuf *d : {&ctx->acc_spare, &ctx->slot_spare[0], &ctx->slot_spare[1]})
+        if (d->ptr) (void)hipFree(d->ptr);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     if (ctx->pin_done) (void)hipEventDestroy(ctx->pin_done);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -1038,6 +1045,10 @@ wsg_status wsg_trim(wsg_ctx *ctx) {
         a->size = 0;
     }
     WSG_HIP(ctx, hipStreamSynchronize(s));
+    for (DevBuf *d : {&ctx->acc_spare, &ctx->slot_spare[0], &ctx->slot_spare[1]}) {
+        if (d->ptr) WSG_HIP(ctx, hipFree(d->ptr));
+        *d = DevBuf{};
+    }
     return WSG_OK;
 }
 
@@ -1324,11 +1335,27 @@ wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, vo
         if (hipEventCreateWithFlags(&a->copied[k], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&a->slot_free[k], hipEventDisableTiming) != hipSuccess)
             return undo(fail(ctx, WSG_EDEVICE, "accumulator events"));
-    hipError_t e = hipMalloc((void **)&a->mem, a->L.bytes);
-    if (e != hipSuccess) {
-        a->mem = nullptr;
-        return undo(fail(ctx, e == hipErrorOutOfMemory ? WSG_ENOMEM : WSG_EDEVICE,
-                         std::string("accumulator: ") + hipGetErrorString(e)));
+    for (int k = 0; k < 2; ++k) {
+        a->slot[k] = ctx->slot_spare[k].ptr;
+        a->slot_size[k] = ctx->slot_spare[k].size;
+        ctx->slot_spare[k] = DevBuf{};
+    }
+    if (ctx->acc_spare.ptr && ctx->acc_spare.size >= a->L.bytes) {
+        a->mem = (char *)ctx->acc_spare.ptr;
+        a->mem_size = ctx->acc_spare.size;
+        ctx->acc_spare = DevBuf{};
+    } else {
+        if (ctx->acc_spare.ptr) {
+            (void)hipFree(ctx->acc_spare.ptr);
+            ctx->acc_spare = DevBuf{};
+        }
+        hipError_t e = hipMalloc((void **)&a->mem, a->L.bytes);
+        if (e != hipSuccess) {
+            a->mem = nullptr;
+            return undo(fail(ctx, e == hipErrorOutOfMemory ? WSG_ENOMEM : WSG_EDEVICE,
+                             std::string("accumulator: ") + hipGetErrorString(e)));
+        }
+        a->mem_size = a->L.bytes;
     }
     // everything starts at zero except the plane geometry of the state, which the
     // chunks overwrite with their own (identical) values; here it only keeps an
@@ -1467,13 +1494,24 @@ void wsg_accum_destroy(wsg_accum *a) {
     (void)hipSetDevice(a->ctx->device);
     if (a->ctx->has_last) (void)hipStreamSynchronize(a->ctx->last_stream);
     if (a->copy) (void)hipStreamSynchronize(a->copy);
+    wsg_ctx *ctx = a->ctx;
     for (int k = 0; k < 2; ++k) {
         if (a->slot_free[k]) (void)hipEventSynchronize(a->slot_free[k]);
-        if (a->slot[k]) (void)hipFree(a->slot[k]);
+        if (a->slot[k]) {
+            if (!ctx->slot_spare[k].ptr)
+                ctx->slot_spare[k] = DevBuf{a->slot[k], a->slot_size[k]};
+            else
+                (void)hipFree(a->slot[k]);
+        }
         if (a->copied[k]) (void)hipEventDestroy(a->copied[k]);
         if (a->slot_free[k]) (void)hipEventDestroy(a->slot_free[k]);
     }
-    if (a->mem) (void)hipFree(a->mem);
+    if (a->mem) {
+        if (!ctx->acc_spare.ptr)
+            ctx->acc_spare = DevBuf{a->mem, a->mem_size};
+        else
+            (void)hipFree(a->mem);
+    }
     if (a->copy) (void)hipStreamDestroy(a->copy);
     delete a;
 }
@@ -1486,5 +1524,6 @@ uint64_t wsg_ctx_device_bytes(const wsg_ctx *ctx) {
     for (auto &kv : ctx->twiddles) b += kv.second.size;
     for (auto &kv : ctx->inv_c) b += kv.second.size;
     for (auto &kv : ctx->kb) b += kv.second.size;
+    b += ctx->acc_spare.size + ctx->slot_spare[0].size + ctx->slot_spare[1].size;
     return b;
 }

@@ -178,3 +178,18 @@ def test_rules(ctx):
     # the context still runs ordinary jobs afterwards
     st = ctx.image(wp, wsg.make_vis(dev(uvw), dev(vis), dev(wts)), out)
     assert st[0]["n_used"] > 0
+
+
+def test_blocks_are_reused_across_jobs(ctx):
+    """Consecutive chunked jobs on one context reuse (or replace) the previous job's
+    w-stack block and chunk slots; every job starts from a clear stack."""
+    for n, nw, rows, host in ((128, 4, 3000, True), (256, 8, 9000, True), (128, 4, 2000, True),
+                              (128, 2, 2500, False)):
+        uvw, vis, wts = synth.random_visibilities(rows, 1, n, 0.2 / n, seed=n + rows, w_extent=50.0)
+        lo, hi = _w_range(uvw)
+        wp, op = both_params(n, nw, 7, 0.2 / n, "f64", w_min=lo, w_max=hi)
+        img, st = _accumulate(ctx, wp, _row_chunks(uvw, vis, wts, [0, rows // 2, rows]), 1, n,
+                              on_device=not host)
+        ref = oracle_image(op, uvw, vis, wts)
+        assert_stats(st, ref["stats"])
+        assert rel(img[0], ref["image"][0]) <= TOL64, (n, nw, rows)
