@@ -107,6 +107,7 @@ class Params:
     per_channel: bool = False
     kernel: str = "gauss"              # "gauss" or "kb" (Kaiser-Bessel)
     kernel_beta: float = 0.0           # Kaiser-Bessel beta; 0 -> kb_default_beta(support)
+    w_fold: bool = False               # grid rows with w < 0 at (-u, -v, -w) with conj(V)
 
 
 @dataclass
@@ -150,6 +151,26 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def fold_w(inp: Inputs) -> Inputs:
+    """w-folding.  The sky is real, so its visibility function is Hermitian:
+    V(-u,-v,-w) = conj V(u,v,w) (Eq. 1).  A row with w < 0 is therefore the same
+    sample as (-u, -v, -w) carrying conj(V) in every channel (f/c > 0 keeps the sign
+    of w), and Re of the image of Eq. 2 is the same for both.  After folding every
+    w is >= 0, so the planes span half the range for symmetric coverage."""
+    neg = inp.uvw[:, 2] < 0.0
+    if not neg.any():
+        return inp
+    uvw = inp.uvw.copy()
+    uvw[neg] = -uvw[neg]
+    vis = inp.vis.copy()
+    vis[neg] = np.conj(vis[neg])
+    return Inputs(uvw, inp.freq_hz, vis, inp.weights, inp.flags)
+
+
+def _prepared(inp: Inputs, prm: Params) -> Inputs:
+    return fold_w(inp) if prm.w_fold else inp
+
+
 # ----------------------------------------------------------------------------
 # O2/O3: data range of w and counts
 # ----------------------------------------------------------------------------
@@ -158,6 +179,7 @@ def w_range(inp: Inputs, prm: Params, chan: int = -1):
     range over valid measurements; (0, 0) when nothing is valid."""
     if math.isfinite(prm.w_min) and math.isfinite(prm.w_max):
         return float(prm.w_min), float(prm.w_max)
+    inp = _prepared(inp, prm)
     lib = _load()
     sc = inp.chan_scale()
     lo, hi = ctypes.c_double(0.0), ctypes.c_double(0.0)
@@ -185,6 +207,7 @@ def grid(inp: Inputs, prm: Params, w_min: float, w_max: float, plane_lo: int = 0
     u index) and the counts (used, flagged, dropped, sum of weights)."""
     if plane_hi is None:
         plane_hi = prm.n_wplanes
+    inp = _prepared(inp, prm)
     lib = _load()
     n = prm.grid_n
     g = np.zeros((plane_hi - plane_lo, n, n), dtype=np.complex128)
@@ -330,6 +353,7 @@ def pixels(inp: Inputs, prm: Params, pix_q, pix_p, chan: int = -1) -> np.ndarray
     (for sampled checks at full size).  complex128 [n_pix]."""
     lib = _load()
     wmin, wmax = w_range(inp, prm, chan)
+    inp = _prepared(inp, prm)
     q = np.ascontiguousarray(pix_q, dtype=np.int32)
     p = np.ascontiguousarray(pix_p, dtype=np.int32)
     out = np.zeros(len(q), dtype=np.complex128)

@@ -411,3 +411,64 @@ def test_kb_pure_fringe_closed_form():
     nm1 = np.sqrt(1 - l[None, :] ** 2 - l[:, None] ** 2) - 1
     ref = np.exp(2j * np.pi * (u * l[None, :] + v * l[:, None] + w * nm1)) * cd[None, :] * cd[:, None]
     assert np.abs(A - ref).max() < 1e-12
+
+
+# ---------------------------------------------------------------- w-folding
+# A real sky has a Hermitian visibility function, V(-u,-v,-w) = conj V(u,v,w) (Eq. 1),
+# so rows with w < 0 may be gridded at (-u,-v,-w) with conj(V): Re of Eq. 2 is unchanged
+# and the planes cover only w >= 0.
+def test_fold_preserves_the_exact_dft(config0):
+    ds = config0
+    sub = slice(0, None, 8)
+    uvw, vis, wts = ds.uvw[sub], ds.vis[sub, 0], ds.weights[sub, 0]
+    f = oracle.fold_w(_inputs(uvw, vis, wts))
+    assert (f.uvw[:, 2] >= 0).all()
+    neg = uvw[:, 2] < 0
+    assert np.array_equal(f.uvw[~neg], uvw[~neg]) and np.array_equal(f.uvw[neg], -uvw[neg])
+    q, p = _inner_pixels(ds.grid_n, 6)
+    De = pinlib.exact_dft(uvw, vis, wts, ds.grid_n, ds.cell_rad, q, p)
+    Df = pinlib.exact_dft(f.uvw, f.vis[:, 0], wts, ds.grid_n, ds.cell_rad, q, p)
+    assert np.abs(Df - De).max() <= 1e-12 * np.abs(De).max()
+
+
+def test_folded_image_against_exact_dft(config0):
+    """The folded image obeys the same two bounds as the plain one (kernel error against
+    the w-quantised transform, quantisation error against the exact transform of the
+    ORIGINAL data), with the folded plane width, about half the plain one here."""
+    ds = config0
+    sub = slice(0, None, 8)
+    uvw, vis, wts = ds.uvw[sub], ds.vis[sub, 0], ds.weights[sub, 0]
+    prm = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, SIG, w_fold=True)
+    out = oracle.image(_inputs(uvw, vis, wts), prm)
+    D = out["image"][0]
+    st = out["stats"][0]
+    assert st["w_min"] >= 0.0
+    plain = oracle.w_range(_inputs(uvw, vis, wts), oracle.Params(ds.grid_n, 1, ds.support,
+                                                                 ds.cell_rad, SIG))
+    dw = (st["w_max"] - st["w_min"]) / ds.n_wplanes
+    assert dw <= 0.55 * (plain[1] - plain[0]) / ds.n_wplanes
+    q, p = _inner_pixels(ds.grid_n, 8)
+    neg = uvw[:, 2] < 0
+    uf = np.where(neg[:, None], -uvw, uvw)
+    vf = np.where(neg, np.conj(vis), vis)
+    Dq = pinlib.quantised_dft(uf, vf, wts, st["w_min"], st["w_max"], ds.n_wplanes, ds.grid_n,
+                              ds.cell_rad, q, p)
+    eps = pinlib.kernel_eps(ds.support, SIG, 0.25)
+    amp = (wts * np.abs(vis)).sum() / wts.sum()
+    assert np.abs(D[q, p] - Dq).max() <= (2 * eps + eps * eps) * amp * 1.1
+    De = pinlib.exact_dft(uvw, vis, wts, ds.grid_n, ds.cell_rad, q, p)
+    l = (p - ds.grid_n / 2) * ds.cell_rad
+    m = (q - ds.grid_n / 2) * ds.cell_rad
+    nm1 = np.abs(np.sqrt(1 - l * l - m * m) - 1)
+    assert np.all(np.abs(Dq - De) <= 2 * np.pi * dw / 2 * nm1 * amp * 1.0001 + 1e-14)
+
+
+def test_fold_without_negative_w_changes_nothing():
+    rng = np.random.default_rng(5)
+    n = 64
+    uvw = np.stack([rng.uniform(-200, 200, 500), rng.uniform(-200, 200, 500),
+                    rng.uniform(0.0, 30.0, 500)], axis=1)
+    vis = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    a = oracle.image(_inputs(uvw, vis), oracle.Params(n, 4, 7, 1.0 / (n * 10), SIG))
+    b = oracle.image(_inputs(uvw, vis), oracle.Params(n, 4, 7, 1.0 / (n * 10), SIG, w_fold=True))
+    assert np.array_equal(a["image"], b["image"])

@@ -88,3 +88,16 @@ def test_kaiser_bessel_mistakes_are_caught():
     }
     for name, bad in slips.items():
         assert np.abs(bad - ref(d)).max() > 1e-6, name
+
+
+def test_fold_without_conjugation_is_caught(config0):
+    """Folding the coordinates but not conjugating the visibility breaks the Hermitian
+    identity that the fold pin checks."""
+    ds = config0
+    sub = slice(0, None, 16)
+    uvw, vis, wts = ds.uvw[sub], ds.vis[sub, 0], ds.weights[sub, 0]
+    q, p = np.array([100, 140, 90]), np.array([120, 70, 160])
+    De = pinlib.exact_dft(uvw, vis, wts, ds.grid_n, ds.cell_rad, q, p)
+    neg = uvw[:, 2] < 0
+    bad = pinlib.exact_dft(np.where(neg[:, None], -uvw, uvw), vis, wts, ds.grid_n, ds.cell_rad, q, p)
+    assert np.abs(bad - De).max() > 1e-3 * np.abs(De).max()
