@@ -89,7 +89,10 @@ enum {
     WSG_GRID_CORRECT = 1u,   /* divide by C(nu_p) C(nu_q)                                    */
     WSG_NORMALIZE = 2u,      /* divide by sum W                                              */
     WSG_PER_CHANNEL = 4u,    /* one image per channel (a cube) instead of one image          */
-    WSG_NAIVE_NM1 = 8u       /* FP32 phase only: sqrt(1-eta)-1 instead of the stable form    */
+    WSG_NAIVE_NM1 = 8u,      /* FP32 phase only: sqrt(1-eta)-1 instead of the stable form    */
+    WSG_W_FOLD = 16u         /* rows with w < 0 are gridded at (-u,-v,-w) with conj(V): the   */
+                             /*   visibilities of a real sky are Hermitian (Eq. 1), so the    */
+                             /*   real image is unchanged and the planes span w >= 0 only    */
 };
 
 typedef struct {

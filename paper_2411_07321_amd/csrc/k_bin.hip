@@ -101,6 +101,11 @@ __device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, cons
     double sc = g.chan_scale[c];
     double u = uvw[3 * r] * sc, v = uvw[3 * r + 1] * sc, w = uvw[3 * r + 2] * sc;
     if (!is_finite(u) || !is_finite(v) || !is_finite(w)) return false;
+    if (g.w_fold && uvw[3 * r + 2] < 0.0) {
+        u = -u;
+        v = -v;
+        w = -w;
+    }
     if (!is_finite(vr) || !is_finite(vi)) return false;
     int i0, j0;
     if (!footprint_fits(mesh_coord(u, g.scale, g.half), g.N, g.h, i0)) return false;
@@ -255,6 +260,7 @@ struct Placed {
     int k;
     int i0, j0;
     double x, y;
+    bool flip;     // folded: the visibility is conjugated
 };
 
 // A valid element inside the w range: its plane, nearest cell and position, from
@@ -264,6 +270,14 @@ __device__ __forceinline__ bool place_vals(const JobGeom &g, const ImgState &s, 
     // every product and difference rounded on its own (no contraction), so that both
     // binning passes, and the oracle, take the same decisions
 #pragma clang fp contract(off)
+    // w-folding: a row with w < 0 is the Hermitian mirror (-u, -v, -w), conj(V); the
+    // negations are exact, so the decisions match those of the unfolded products
+    pl.flip = g.w_fold && wm < 0.0;
+    if (pl.flip) {
+        um = -um;
+        vm = -vm;
+        wm = -wm;
+    }
     double w = wm * sc;
     if (!(w >= s.w_min && w <= s.w_max)) return false;
     double u = um * sc, v = vm * sc;
@@ -543,12 +557,12 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
                 L.fx[q] = fx;
                 L.fy[q] = fy;
                 L.re[q] = wt[k] * vr[k];
-                L.im[q] = wt[k] * vi[k];
+                L.im[q] = pl.flip ? -(wt[k] * vi[k]) : wt[k] * vi[k];
             } else {
                 L.a[q] = quant_frac(fx) | ((uint32_t)li0 << kFracBits);
                 L.b[q] = quant_frac(fy) | ((uint32_t)lj0 << kFracBits);
                 L.re[q] = (float)wt[k] * (float)vr[k];
-                L.im[q] = (float)wt[k] * (float)vi[k];
+                L.im[q] = pl.flip ? -((float)wt[k] * (float)vi[k]) : (float)wt[k] * (float)vi[k];
             }
         }
     }

@@ -97,6 +97,7 @@ struct JobGeom {
     int32_t kb_n;
     const float *kb_poly;     // per-tap polynomials in x = 2f, kKbStride floats per tap
     int32_t range_given;
+    int32_t w_fold;         // rows with w < 0 placed at (-u, -v, -w), visibility conjugated
     double w_min_given, w_max_given;
     const double *chan_scale;  // device [n_chan]: f/c or 1
     // track traversal of the binning passes: rows are viewed as [n_t][P]

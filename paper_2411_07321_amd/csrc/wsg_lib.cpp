@@ -251,7 +251,8 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
             return WSG_EINVAL;
         }
     }
-    if (p->flags & ~(uint32_t)(WSG_GRID_CORRECT | WSG_NORMALIZE | WSG_PER_CHANNEL | WSG_NAIVE_NM1)) {
+    if (p->flags & ~(uint32_t)(WSG_GRID_CORRECT | WSG_NORMALIZE | WSG_PER_CHANNEL | WSG_NAIVE_NM1 |
+                               WSG_W_FOLD)) {
         why = "unknown flag bits";
         return WSG_EINVAL;
     }
@@ -655,6 +656,7 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
         if (rc) return rc;
     }
     g.range_given = range_given(p) ? 1 : 0;
+    g.w_fold = (p->flags & WSG_W_FOLD) ? 1 : 0;
     g.w_min_given = p->w_min;
     g.w_max_given = p->w_max;
     g.chan_scale = (const double *)(fx + pl.o_scale);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libwsg.so")
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PREC = {"f64": 0, "f32_phase64": 1, "f32_phase32": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
-GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1 = 1, 2, 4, 8
+GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1, W_FOLD = 1, 2, 4, 8, 16
 
 # symbols declared in include/wsg.h
 SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_set_budget",
@@ -187,11 +187,12 @@ KERNEL = {"gauss": 0, "kb": 1}
 def make_params(grid_n, n_wplanes, support, cell_rad, precision="f32_phase64", kernel_sigma=0.9,
                 w_min=None, w_max=None, plane_lo=0, plane_hi=0, grid_correct=True,
                 normalize=True, per_channel=False, naive_nm1=False, tile=0, kernel="gauss",
-                kernel_beta=0.0) -> Params:
+                kernel_beta=0.0, w_fold=False) -> Params:
     """kernel: "gauss" (width kernel_sigma) or "kb" (Kaiser-Bessel, shape kernel_beta;
     0 = the library's default for the support)."""
     flags = (GRID_CORRECT if grid_correct else 0) | (NORMALIZE if normalize else 0) | \
-        (PER_CHANNEL if per_channel else 0) | (NAIVE_NM1 if naive_nm1 else 0)
+        (PER_CHANNEL if per_channel else 0) | (NAIVE_NM1 if naive_nm1 else 0) | \
+        (W_FOLD if w_fold else 0)
     return Params(int(grid_n), int(n_wplanes), int(support), PREC[precision], float(cell_rad),
                   float(kernel_sigma), math.nan if w_min is None else float(w_min),
                   math.nan if w_max is None else float(w_max), int(plane_lo), int(plane_hi),
