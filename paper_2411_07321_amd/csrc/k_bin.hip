@@ -17,16 +17,19 @@
 //   k_scatter  compact records into their bins
 //
 // k_count and k_scatter follow tracks: rows are viewed as [time][P] with P
-// the row period (baselines per time slice), and a thread walks one
-// (baseline, channel) through L consecutive time slices.  A track moves
-// slowly across the mesh, so consecutive elements of a thread mostly fall in
-// the same bins: a "run" is a maximal stretch of consecutive elements whose
-// footprints all touch one bin, and each run costs one global atomic instead
-// of one per element (the scatter first sizes the runs of a block of time
-// slices, then reserves their slots).  This matters because the uv coverage is extremely
-// uneven: the short baselines of a dense core all land in the few central
-// tiles, and per-element atomics there serialise.  Records of one run stay
-// contiguous inside their bin.
+// the row period (baselines per time slice); a stretch is one (baseline,
+// channel) track over kStretch consecutive time slices.  A workgroup first
+// reads 16 stretches x 64 time slices with coalesced loads (consecutive
+// threads, consecutive rows of one time slice) and places every element into
+// an LDS table; then each wave takes whole stretches, one time slice per lane.
+// A track moves slowly across the mesh, so the lanes of a wave mostly fall in
+// the same few bins: for each distinct bin the wave counts its lanes with one
+// ballot and takes one global atomic, and the scatter writes the lanes'
+// records to consecutive slots.  This matters because the uv coverage is
+// extremely uneven: the short baselines of a dense core all land in the few
+// central tiles, where per-element atomics would serialise; the atomics are
+// further spread over per-class copies of the counters (workgroup index mod
+// the class count).  Records of one stretch stay contiguous inside their bin.
 #include "wsg_internal.h"
 
 #include <algorithm>
