@@ -73,9 +73,12 @@ def _load():
         lib.oracle_grid.restype = ctypes.c_int
         lib.oracle_grid.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                    P, P]
+                                    ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, P, P]
+        lib.oracle_plane_geometry.restype = None
+        lib.oracle_plane_geometry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, P, P]
         lib.oracle_pixels.restype = ctypes.c_int
         lib.oracle_pixels.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P, P, P,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -108,6 +111,7 @@ class Params:
     kernel: str = "gauss"              # "gauss" or "kb" (Kaiser-Bessel)
     kernel_beta: float = 0.0           # Kaiser-Bessel beta; 0 -> kb_default_beta(support)
     w_fold: bool = False               # grid rows with w < 0 at (-u, -v, -w) with conj(V)
+    w_support: int = 1                 # planes a visibility spreads over (kernel in w)
 
 
 @dataclass
@@ -189,13 +193,13 @@ def w_range(inp: Inputs, prm: Params, chan: int = -1):
     return lo.value, hi.value
 
 
-def plane_w(k: np.ndarray | int, w_min: float, w_max: float, n_w: int):
-    """w of plane k: w_min + (k + 1/2) dw, or w_min when dw = 0 (O3)."""
-    dw = (w_max - w_min) / n_w
+def plane_w(k: np.ndarray | int, w_min: float, w_max: float, n_w: int, w_support: int = 1):
+    """w of plane k: w0 + (k + 1/2) dw, or w0 when dw = 0 (O3; plane_geometry)."""
+    w0, dw = plane_geometry(w_min, w_max, n_w, w_support)
     k = np.asarray(k, dtype=np.float64)
     if dw == 0.0:
-        return np.full_like(k, w_min)
-    return w_min + (k + 0.5) * dw
+        return np.full_like(k, w0)
+    return w0 + (k + 0.5) * dw
 
 
 # ----------------------------------------------------------------------------
@@ -215,8 +219,8 @@ def grid(inp: Inputs, prm: Params, w_min: float, w_max: float, plane_lo: int = 0
     sc = inp.chan_scale()
     rc = lib.oracle_grid(inp.n_rows, inp.n_chan, _ptr(inp.uvw), _ptr(sc), _ptr(inp.vis),
                          _ptr(inp.weights), _ptr(inp.flags), n, prm.n_wplanes, prm.support,
-                         prm.cell_rad, *_kernel_args(prm), w_min, w_max, plane_lo, plane_hi,
-                         chan, _ptr(g), ctypes.byref(cnt))
+                         prm.cell_rad, *_kernel_args(prm), *_w_kernel_args(prm), w_min, w_max,
+                         plane_lo, plane_hi, chan, _ptr(g), ctypes.byref(cnt))
     if rc != 0:
         raise ValueError("oracle_grid: unsupported support")
     return g, {"n_used": cnt.n_used, "n_flagged": cnt.n_flagged, "n_dropped": cnt.n_dropped,
@@ -248,13 +252,13 @@ def n_minus_1(n: int, cell: float):
 
 
 def wcorrect(F: np.ndarray, w_min: float, w_max: float, n_w: int, cell: float,
-             plane_lo: int = 0) -> np.ndarray:
+             plane_lo: int = 0, w_support: int = 1) -> np.ndarray:
     """A[q,p] = sum_k F_k[q,p] exp(+2 pi i w_k (n_pq - 1)); 0 off the sphere."""
     n = F.shape[-1]
     nm1, inside = n_minus_1(n, cell)
     acc = np.zeros((n, n), dtype=np.complex128)
     for kk in range(F.shape[0]):
-        wk = float(plane_w(plane_lo + kk, w_min, w_max, n_w))
+        wk = float(plane_w(plane_lo + kk, w_min, w_max, n_w, w_support))
         acc += F[kk] * np.exp(2j * np.pi * wk * nm1)
     acc[~inside] = 0.0
     return acc
@@ -278,6 +282,26 @@ def _kernel_args(prm: Params) -> tuple[int, float]:
     raise ValueError(f"unknown kernel {prm.kernel!r}")
 
 
+def _w_kernel_args(prm: Params) -> tuple[int, float]:
+    """(w_support, shape) of the kernel in w: the uv kernel's kind over w_support
+    planes (Gaussian: the same sigma in planes; Kaiser-Bessel: the given beta, else
+    the default for w_support)."""
+    if prm.w_support <= 1:
+        return 1, 0.0
+    if prm.kernel == "kb":
+        return prm.w_support, (prm.kernel_beta if prm.kernel_beta > 0
+                               else kb_default_beta(prm.w_support))
+    return prm.w_support, prm.kernel_sigma
+
+
+def plane_geometry(w_min: float, w_max: float, n_w: int, w_support: int = 1):
+    """(w0, dw): plane k sits at w0 + (k + 1/2) dw.  With a kernel in w over
+    w_support = 2 h_w + 1 planes, [w_min, w_max] covers the middle N_w - 2 h_w planes."""
+    w0, dw = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _load().oracle_plane_geometry(w_min, w_max, n_w, w_support, ctypes.byref(w0), ctypes.byref(dw))
+    return w0.value, dw.value
+
+
 def kernel_value(prm: Params, d) -> np.ndarray:
     """G(d) of the gridding kernel (Eq. 3), elementwise over d (cells)."""
     lib = _load()
@@ -298,13 +322,37 @@ def kernel_transform(n: int, support: int, sigma: float, nodes: int = 64, kernel
     return a * (np.cos(2.0 * np.pi * nu[:, None] * d[None, :]) * (wq * f)[None, :]).sum(axis=1)
 
 
-def post(A: np.ndarray, sum_w: float, prm: Params) -> np.ndarray:
-    """D = Re A / (sum W * C(nu_p) C(nu_q)), each factor switchable; 0 if sum W = 0."""
+def w_kernel_transform(nu: np.ndarray, prm: Params, nodes: int = 64) -> np.ndarray:
+    """C_w(nu) = int G_w(d) cos(2 pi nu d) dd over the w support (in planes), by
+    Gauss-Legendre quadrature, at arbitrary nu."""
+    sw, par = _w_kernel_args(prm)
+    x, wq = np.polynomial.legendre.leggauss(nodes)
+    a = sw / 2.0
+    d = a * x
+    lib = _load()
+    kind = 1 if prm.kernel == "kb" else 0
+    f = np.array([lib.oracle_kernel_value(kind, par, sw, float(t)) for t in d])
+    nu = np.asarray(nu, dtype=np.float64)
+    return a * (np.cos(2.0 * np.pi * nu[..., None] * d) * (wq * f)).sum(axis=-1)
+
+
+def post(A: np.ndarray, sum_w: float, prm: Params, w_min: float = 0.0,
+         w_max: float = 0.0) -> np.ndarray:
+    """D = Re A / (sum W * C(nu_p) C(nu_q) [* C_w(dw (n_pq - 1))]), each factor
+    switchable; 0 if sum W = 0.  The C_w factor undoes a kernel in w: summing the
+    planes with their phases turns the visibility's spread over planes into the
+    window's transform at dw (n - 1) (Poisson summation; 1 with w_support 1)."""
     d = A.real.copy()
     if prm.grid_correct:
         c = kernel_transform(prm.grid_n, prm.support, prm.kernel_sigma, kernel=prm.kernel,
                              beta=prm.kernel_beta)
         d /= c[:, None] * c[None, :]
+        if prm.w_support > 1:
+            _, dw = plane_geometry(w_min, w_max, prm.n_wplanes, prm.w_support)
+            if dw > 0.0:
+                nm1, inside = n_minus_1(prm.grid_n, prm.cell_rad)
+                cw = w_kernel_transform(dw * nm1, prm)
+                d = np.where(inside, d / cw, 0.0)
     if prm.normalize:
         if sum_w > 0.0:
             d /= sum_w
@@ -336,12 +384,12 @@ def image(inp: Inputs, prm: Params, plane_chunk: int | None = None, keep_stages:
             F = fft_planes(g)
             if keep_stages and ci == 0 and step == hi - lo:
                 stages = {"grid": g, "planes": F}
-            acc += wcorrect(F, wmin, wmax, prm.n_wplanes, prm.cell_rad, k0)
+            acc += wcorrect(F, wmin, wmax, prm.n_wplanes, prm.cell_rad, k0, prm.w_support)
             del g, F
         if cnt is None:
             _, cnt = grid(inp, prm, wmin, wmax, 0, 0, ch)
         raws.append(acc)
-        imgs.append(post(acc, cnt["sum_w"], prm))
+        imgs.append(post(acc, cnt["sum_w"], prm, wmin, wmax))
         stats.append(dict(cnt, w_min=wmin, w_max=wmax))
     out = {"image": np.stack(imgs), "raw": np.stack(raws), "stats": stats}
     out.update(stages)
@@ -351,6 +399,8 @@ def image(inp: Inputs, prm: Params, plane_chunk: int | None = None, keep_stages:
 def pixels(inp: Inputs, prm: Params, pix_q, pix_p, chan: int = -1) -> np.ndarray:
     """Raw image A at the listed pixels, evaluated directly from the measurements
     (for sampled checks at full size).  complex128 [n_pix]."""
+    if prm.w_support > 1:
+        raise ValueError("the pixel evaluator takes each visibility on its nearest plane only")
     lib = _load()
     wmin, wmax = w_range(inp, prm, chan)
     inp = _prepared(inp, prm)

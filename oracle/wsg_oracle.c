@@ -148,8 +148,27 @@ double oracle_kernel_value(int kind, double par, int support, double d)
 }
 
 /*
- * Eq. 3 on the (u,v) mesh of the nearest w-plane:
- *   g_k[j0+b][i0+a] += W V G(i0+a-x) G(j0+b-y),  a, b in [-h, h].
+ * Plane geometry.  Without a kernel in w (w_support 1) the N_w planes are cells
+ * of width dw = (w_max - w_min)/N_w from w0 = w_min.  With a kernel of
+ * w_support = 2 h_w + 1 planes, the data range [w_min, w_max] covers the middle
+ * N_w - 2 h_w planes and h_w more on each side take the kernel's tails:
+ * dw = (w_max - w_min)/(N_w - 2 h_w), w0 = w_min - h_w dw.  Plane k sits at
+ * w_k = w0 + (k + 1/2) dw (w0 when dw = 0).
+ */
+void oracle_plane_geometry(double w_min, double w_max, int n_w, int w_support, double *w0,
+                           double *dw)
+{
+    int hw = (w_support - 1) / 2;
+    *dw = (w_max - w_min) / (double)(n_w - 2 * hw);
+    *w0 = w_min - (double)hw * *dw;
+}
+
+/*
+ * Eq. 3:
+ *   g_k[j0+b][i0+a] += W V G(i0+a-x) G(j0+b-y) G_w((w_k - w)/dw),
+ * a, b in [-h, h], k = k0 - h_w .. k0 + h_w around the plane k0 whose cell holds
+ * w; G_w is the kernel of the same kind over w_support planes (shape wpar), and
+ * 1 for w_support 1 or dw = 0 (every plane then at w0: the visibility stays on k0).
  * grid: complex128 interleaved [plane_hi-plane_lo][N][N] (row j, column i),
  * accumulated into (the caller zeroes it).  Only planes in [plane_lo,
  * plane_hi) are gridded; the counts cover every plane.
@@ -157,12 +176,15 @@ double oracle_kernel_value(int kind, double par, int support, double d)
 int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
                 const double *vis, const double *weights, const uint8_t *flags,
                 int n, int n_w, int support, double cell, int kernel, double kpar,
+                int w_support, double wpar,
                 double w_min, double w_max, int plane_lo, int plane_hi, int chan,
                 double *grid, oracle_counts *counts)
 {
     int h = (support - 1) / 2;
     double scale = (double)n * cell;
-    double dw = (w_max - w_min) / (double)n_w;
+    double w0, dw;
+    oracle_plane_geometry(w_min, w_max, n_w, w_support, &w0, &dw);
+    int hw = dw == 0.0 ? 0 : (w_support - 1) / 2;
     double gx[64], gy[64];
     oracle_counts cnt = {0, 0, 0, 0.0};
     if (support > 63) return -1;
@@ -183,8 +205,7 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
             if (!(w >= w_min && w <= w_max)) { cnt.n_dropped++; continue; }
             cnt.n_used++;
             cnt.sum_w += wt;
-            int k = plane_of(w, w_min, dw, n_w);
-            if (k < plane_lo || k >= plane_hi) continue;
+            int k0 = plane_of(w, w0, dw, n_w);
             double x, y;
             int64_t i0, j0;
             position(u, v, scale, n, &x, &y);
@@ -194,16 +215,24 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
                 gx[a + h] = oracle_kernel_value(kernel, kpar, support, (double)(i0 + a) - x);
             for (int b = -h; b <= h; ++b)
                 gy[b + h] = oracle_kernel_value(kernel, kpar, support, (double)(j0 + b) - y);
-            double wv_re = wt * vis[2 * rc + 0];
-            double wv_im = wt * vis[2 * rc + 1];
-            double *plane = grid + (size_t)(k - plane_lo) * (size_t)n * (size_t)n * 2;
-            for (int b = -h; b <= h; ++b) {
-                double *row = plane + ((size_t)(j0 + b) * (size_t)n) * 2;
-                for (int a = -h; a <= h; ++a) {
-                    double g = gx[a + h] * gy[b + h];
-                    size_t i = (size_t)(i0 + a) * 2;
-                    row[i + 0] += wv_re * g;
-                    row[i + 1] += wv_im * g;
+            for (int k = k0 - hw; k <= k0 + hw; ++k) {
+                if (k < plane_lo || k >= plane_hi) continue;
+                double gw = 1.0;
+                if (hw > 0) {
+                    double wk = w0 + ((double)k + 0.5) * dw;
+                    gw = oracle_kernel_value(kernel, wpar, w_support, (wk - w) / dw);
+                }
+                double wv_re = wt * vis[2 * rc + 0] * gw;
+                double wv_im = wt * vis[2 * rc + 1] * gw;
+                double *plane = grid + (size_t)(k - plane_lo) * (size_t)n * (size_t)n * 2;
+                for (int b = -h; b <= h; ++b) {
+                    double *row = plane + ((size_t)(j0 + b) * (size_t)n) * 2;
+                    for (int a = -h; a <= h; ++a) {
+                        double g = gx[a + h] * gy[b + h];
+                        size_t i = (size_t)(i0 + a) * 2;
+                        row[i + 0] += wv_re * g;
+                        row[i + 1] += wv_im * g;
+                    }
                 }
             }
         }

@@ -472,3 +472,93 @@ def test_fold_without_negative_w_changes_nothing():
     a = oracle.image(_inputs(uvw, vis), oracle.Params(n, 4, 7, 1.0 / (n * 10), SIG))
     b = oracle.image(_inputs(uvw, vis), oracle.Params(n, 4, 7, 1.0 / (n * 10), SIG, w_fold=True))
     assert np.array_equal(a["image"], b["image"])
+
+
+# ---------------------------------------------------------------- kernel in w
+# Eq. 3's G acts in u, v and w: with w_support = 2 h_w + 1 a visibility adds
+# W V G(u) G(v) G_w((w_k - w)/dw) to the planes k0 - h_w .. k0 + h_w around its own,
+# the data range covering the middle N_w - 2 h_w planes; after the plane sum with
+# the phases of Eq. 2 the image carries C_w(dw (n - 1)), the window's transform,
+# which the grid correction divides out.
+def test_w_kernel_single_visibility_planes():
+    n, cell, S, SW, nw = 64, 1.0 / 100, 7, 5, 9
+    uvw = np.array([[12.34567, -8.7654, 3.21]])
+    vis = np.array([[0.3 - 0.8j]])
+    wts = np.array([[1.7]])
+    w_lo, w_hi = -10.0, 10.0
+    prm = oracle.Params(n, nw, S, cell, SIG, w_support=SW)
+    g, cnt = oracle.grid(_inputs(uvw, vis, wts), prm, w_lo, w_hi)
+    dw = (w_hi - w_lo) / (nw - 4)
+    w0 = w_lo - 2 * dw
+    assert cnt["n_used"] == 1
+    k0 = int(np.floor((3.21 - w0) / dw))
+    x, y = pinlib.positions(uvw, n, cell)
+    i0_, j0 = int(math.floor(x[0] + 0.5)), int(math.floor(y[0] + 0.5))
+    gx = pinlib.gauss(i0_ + np.arange(-3, 4) - x[0], SIG)
+    gy = pinlib.gauss(j0 + np.arange(-3, 4) - y[0], SIG)
+    ref = np.zeros((nw, n, n), complex)
+    for k in range(k0 - 2, k0 + 3):
+        gw = pinlib.gauss((w0 + (k + 0.5) * dw - 3.21) / dw, SIG)
+        ref[k, j0 - 3:j0 + 4, i0_ - 3:i0_ + 4] = 1.7 * vis[0, 0] * gw * np.outer(gy, gx)
+    assert np.abs(g - ref).max() < 1e-15
+    assert np.count_nonzero(np.abs(g).reshape(nw, -1).max(1)) == 5
+
+
+def test_w_kernel_transform_closed_form():
+    prm = oracle.Params(64, 8, 7, 1.0, SIG, w_support=7)
+    nu = np.array([0.0, 0.01, 0.05, 0.13, 0.25, 0.4])
+    ref = pinlib.c_closed_form(nu, 7, SIG)
+    assert np.abs(oracle.w_kernel_transform(nu, prm) - ref).max() <= 1e-13 * ref.max()
+
+
+def test_w_kernel_pure_fringe():
+    """One visibility on a cell: Re A = Re[fringe_uv * Cd(p) Cd(q) *
+    sum_k G_w((w_k - w)/dw) e^{2 pi i w_k (n - 1)}]."""
+    n, cell, S, SW, nw = 64, 1.0 / 128, 7, 5, 10
+    u, v, w = 2.0 * 9, 2.0 * -13, 37.5
+    prm = oracle.Params(n, nw, S, cell, SIG, w_min=-40.0, w_max=40.0, w_support=SW)
+    A = _raw(_inputs(np.array([[u, v, w]]), np.array([[1.0 + 0j]])), prm)
+    c = np.arange(n) - n / 2
+    l = c * cell
+    nu = c / n
+    a = np.arange(-3, 4)
+    cd = (pinlib.gauss(a, SIG)[None, :] * np.cos(2 * np.pi * a[None, :] * nu[:, None])).sum(1)
+    nm1 = np.sqrt(1 - l[None, :] ** 2 - l[:, None] ** 2) - 1
+    dw = 80.0 / (nw - 4)
+    w0 = -40.0 - 2 * dw
+    k0 = int(np.floor((w - w0) / dw))
+    ws = sum(pinlib.gauss((w0 + (k + 0.5) * dw - w) / dw, SIG) *
+             np.exp(2j * np.pi * (w0 + (k + 0.5) * dw) * nm1) for k in range(k0 - 2, k0 + 3))
+    ref = np.exp(2j * np.pi * (u * l[None, :] + v * l[:, None])) * cd[None, :] * cd[:, None] * ws
+    assert np.abs(A - ref).max() < 1e-12
+
+
+def test_w_kernel_approaches_the_exact_transform():
+    """Wide field (0.5 rad), 12 planes over |w| <= 30: with a kernel of 7 planes and its
+    C_w correction the image is far closer to the exact transform than with nearest
+    planes (or than the same stack without the C_w division)."""
+    n, cell = 256, 0.5 / 256
+    rng = np.random.default_rng(71)
+    m = 6000
+    du = 1.0 / (n * cell)
+    uvw = np.stack([rng.uniform(-0.3, 0.3, m) * n * du, rng.uniform(-0.3, 0.3, m) * n * du,
+                    rng.uniform(-30.0, 30.0, m)], axis=1)
+    vis = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    wts = np.ones(m)
+    q = np.array([40, 60, 200, 220, 128, 30, 100, 160])
+    p = np.array([50, 210, 45, 190, 20, 128, 100, 170])
+    De = pinlib.exact_dft(uvw, vis, wts, n, cell, q, p)
+    inp = _inputs(uvw, vis, wts)
+    err = {}
+    for sw in (1, 7):
+        out = oracle.image(inp, oracle.Params(n, 12, 7, cell, SIG, w_support=sw))
+        err[sw] = np.abs(out["image"][0][q, p] - De).max()
+    prm = oracle.Params(n, 12, 7, cell, SIG, w_support=7)
+    out = oracle.image(inp, prm)
+    st = out["stats"][0]
+    # the same stack, divided by the uv correction and sum W only
+    d = out["raw"][0].real / (oracle.kernel_transform(n, 7, SIG)[:, None] *
+                              oracle.kernel_transform(n, 7, SIG)[None, :]) / st["sum_w"]
+    err_no_cw = np.abs(d[q, p] - De).max()
+    assert err[7] < 0.1 * err[1]
+    assert err[7] < 0.1 * err_no_cw

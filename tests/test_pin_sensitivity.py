@@ -58,7 +58,7 @@ def test_wrong_plane_w_is_caught(config0, monkeypatch):
     bound = (2 * eps + eps * eps) * np.abs(vis).mean() * 1.1
     assert np.abs(good["image"][0][q, p] - Dq).max() <= bound
 
-    def lower_edge(k, w_min, w_max, n_w):
+    def lower_edge(k, w_min, w_max, n_w, w_support=1):
         return w_min + np.asarray(k, dtype=np.float64) * (w_max - w_min) / n_w
     monkeypatch.setattr(oracle, "plane_w", lower_edge)
     bad = oracle.image(oracle.Inputs.make(uvw, None, vis, wts), prm)
