@@ -206,6 +206,12 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
             cnt.n_used++;
             cnt.sum_w += wt;
             int k0 = plane_of(w, w0, dw, n_w);
+            /* the kernel's planes must exist: a w at the edge of the range can round
+             * into the padding planes */
+            if (hw > 0) {
+                if (k0 < hw) k0 = hw;
+                if (k0 > n_w - 1 - hw) k0 = n_w - 1 - hw;
+            }
             double x, y;
             int64_t i0, j0;
             position(u, v, scale, n, &x, &y);
