@@ -113,6 +113,13 @@ typedef struct {
                            /*   lacks: WSG_EINVAL).  FP32 meshes take each tap from a fitted   */
                            /*   degree-8 polynomial; a beta it cannot follow within 2e-7 is    */
                            /*   WSG_EUNSUPPORTED there (the FP64 mesh takes any beta)          */
+    int32_t w_support;     /* planes a visibility spreads over (Eq. 3's G in w): 0 or 1 = its */
+                           /*   nearest plane only; odd 3 .. 15: the kernel's kind over that  */
+                           /*   many planes (Gaussian: the same sigma in planes; Kaiser-      */
+                           /*   Bessel: beta, or the default for w_support), the w range       */
+                           /*   covering the middle N_w - 2 h_w planes, and WSG_GRID_CORRECT   */
+                           /*   also divides by its transform at dw (n - 1).  Needs N_w >=    */
+                           /*   w_support and the full plane range                             */
 } wsg_params;
 
 typedef struct {

@@ -240,7 +240,10 @@ __global__ void k_finalize(JobGeom g, ImgState *st) {
     }
     s.w_min = lo;
     s.w_max = hi;
-    s.dw = (hi - lo) / (double)g.n_w;
+    // with a kernel in w over 2 w_h + 1 planes the range covers the middle
+    // N_w - 2 w_h planes, and w_h more on each side take the kernel's tails
+    s.dw = (hi - lo) / (double)(g.n_w - 2 * g.w_h);
+    s.w0 = lo - (double)g.w_h * s.dw;
     s.inv_dw = s.dw > 0.0 ? 1.0 / s.dw : 0.0;
 }
 
@@ -263,6 +266,7 @@ struct Placed {
     int k;
     int i0, j0;
     double x, y;
+    double w;      // w in wavelengths (folded)
     bool flip;     // folded: the visibility is conjugated
 };
 
@@ -288,7 +292,11 @@ __device__ __forceinline__ bool place_vals(const JobGeom &g, const ImgState &s, 
     pl.y = mesh_coord(v, g.scale, g.half);
     pl.i0 = (int)floor(pl.x + 0.5);
     pl.j0 = (int)floor(pl.y + 0.5);
-    pl.k = plane_of(w, s.w_min, s.dw, s.inv_dw, g.n_w);
+    pl.k = plane_of(w, s.w0, s.dw, s.inv_dw, g.n_w);
+    // a kernel in w needs its whole support inside the stack: a w at the very edge
+    // of the range may round into the padding
+    if (g.w_h && s.dw > 0.0) pl.k = min(max(pl.k, g.w_h), g.n_w - 1 - g.w_h);
+    pl.w = w;
     return true;
 }
 
@@ -309,6 +317,9 @@ struct Keys {
 
 
 constexpr uint32_t kNoKey = 0xffffffffu;
+// bit 29 of a packed element: its visibility spreads over the planes of the kernel
+// in w (set only where the image's plane width is not 0)
+constexpr uint32_t kSpread = 1u << 29;
 
 // base bin (lowest tile) in bits 0..26, bit 27: also the tile to the right, bit 28:
 // also the tile above
@@ -442,6 +453,20 @@ __device__ __forceinline__ uint32_t quant_frac(double f) {
 }
 
 // Counting pass: records per bin, into the workgroup's atomic class.
+// Keys of plane offset dk: every bin of the element moved dk planes (a whole
+// plane of tiles per step); none for dk != 0 unless the element spreads.
+__device__ __forceinline__ Keys plane_keys(const Keys &ks, uint32_t pk, int dk, int logNT) {
+    Keys kd = ks;
+    if (dk != 0) {
+        if (pk == kNoKey || !(pk & kSpread)) kd.n = 0;
+        const uint32_t shift = (uint32_t)dk << (2 * logNT);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) kd.k[i] = ks.k[i] + shift;
+    }
+    return kd;
+}
+
+template <bool WK>
 __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *__restrict__ uvw,
                                                        const uint8_t *__restrict__ mask,
                                                        const ImgState *st,
@@ -472,8 +497,10 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
         const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;
-        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl))
+        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl)) {
             pk = pack_placed(g, img, pl);
+            if (WK && pk != kNoKey && st[img].dw > 0.0) pk |= kSpread;
+        }
         s_pk[t * kPitch + s] = pk;
     }
     __syncthreads();
@@ -484,10 +511,15 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
     for (int j = 0; j < kPerWave; ++j) {
         const int s = wave * kPerWave + j;
         Keys ks;
-        unpack_keys(s_pk[lane * kPitch + s], g.NT, ks);
-        for_each_bin(ks, [&](uint32_t bin, unsigned long long m, int leader, bool) {
-            if (lane == leader) atomicAdd(&counts[bin], (uint32_t)__popcll(m));
-        });
+        const uint32_t pk = s_pk[lane * kPitch + s];
+        unpack_keys(pk, g.NT, ks);
+        const int hw = WK ? g.w_h : 0;
+        for (int dk = -hw; dk <= hw; ++dk) {
+            const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
+            for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool) {
+                if (lane == leader) atomicAdd(&counts[bin], (uint32_t)__popcll(m));
+            });
+        }
     }
 }
 
@@ -510,7 +542,26 @@ struct ScatterLds<double> {
     double fx[kTileElems], fy[kTileElems], re[kTileElems], im[kTileElems];
 };
 
+// with a kernel in w, also the element's w and its plane and image (k0 | img << 16)
+template <typename VT, bool WK>
+struct ScatterLdsW : ScatterLds<VT> {};
 template <typename VT>
+struct ScatterLdsW<VT, true> : ScatterLds<VT> {
+    double wv[kTileElems];
+    uint32_t kimg[kTileElems];
+};
+
+// (w_k - w) / dw for plane k, each operation rounded on its own: the Kaiser-Bessel
+// window is cut off at |d| = S_w / 2 with a non-zero value there, and the data's own
+// extreme w values fall exactly on plane edges, so d must round as the method's
+// reference rounds it
+__device__ __forceinline__ double plane_offset(const ImgState &s, int k, double w) {
+#pragma clang fp contract(off)
+    const double wk = s.w0 + ((double)k + 0.5) * s.dw;
+    return (wk - w) / s.dw;
+}
+
+template <typename VT, bool WK>
 __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
                                                          const void *__restrict__ vis,
                                                          const void *__restrict__ wts,
@@ -518,7 +569,7 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
                                                          const ImgState *st, uint32_t *cls_cursor,
                                                          int n_cls, void *__restrict__ records,
                                                          uint32_t capacity, uint32_t *overflow) {
-    __shared__ ScatterLds<VT> L;
+    __shared__ ScatterLdsW<VT, WK> L;
     const int64_t blk = bin_block(blockIdx.x, gridDim.x);
     const int64_t s0 = blk * kBinStretches;
     const StretchPos pos = stretch_pos(g, (uint32_t)(s0 + (int)threadIdx.x % kBinStretches));
@@ -546,8 +597,17 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
         const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;
-        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl))
+        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl)) {
             pk = pack_placed(g, img, pl);
+            if constexpr (WK) {
+                const ImgState &si = st[img];
+                if (pk != kNoKey && si.dw > 0.0) {
+                    pk |= kSpread;
+                    L.wv[t * kPitch + s] = pl.w;
+                    L.kimg[t * kPitch + s] = (uint32_t)pl.k | ((uint32_t)img << 16);
+                }
+            }
+        }
         const int q = t * kPitch + s;
         L.pk[q] = pk;
         if (pk != kNoKey) {
@@ -582,7 +642,17 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
         unpack_keys(pk, g.NT, ks);
         const uint32_t tb0 = pk & tmask;   // lowest tile of the footprint
         const int tx0 = (int)(tb0 & (uint32_t)(g.NT - 1)), ty0 = (int)(tb0 >> g.logNT);
-        for_each_bin(ks, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
+        const int hw = WK ? g.w_h : 0;
+        for (int dk = -hw; dk <= hw; ++dk) {
+        // weight of plane k0 + dk under the kernel in w (1 without one)
+        double gw = 1.0;
+        if constexpr (WK)
+            if (pk != kNoKey && (pk & kSpread)) {
+                const uint32_t ki = L.kimg[q];
+                gw = w_weight(g, plane_offset(st[ki >> 16], (int)(ki & 0xffffu) + dk, L.wv[q]));
+            }
+        const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
+        for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
             uint32_t base = 0u;
             if (lane == leader) base = atomicAdd(&cursor[bin], (uint32_t)__popcll(m));
             base = (uint32_t)__shfl((int)base, leader);
@@ -601,8 +671,8 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
                 RecF64 rec;
                 rec.fx = L.fx[q];
                 rec.fy = L.fy[q];
-                rec.re = L.re[q];
-                rec.im = L.im[q];
+                rec.re = WK ? L.re[q] * gw : L.re[q];
+                rec.im = WK ? L.im[q] * gw : L.im[q];
                 rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
                 rec.lj = (int)(lij >> 16) - (dy << g.logT);
                 ((RecF64 *)records)[slot] = rec;
@@ -613,11 +683,12 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
                          (a & 0xffffffu);
                 rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
                          (b & 0xffffffu);
-                rec.re = L.re[q];
-                rec.im = L.im[q];
+                rec.re = WK ? L.re[q] * (float)gw : L.re[q];
+                rec.im = WK ? L.im[q] * (float)gw : L.im[q];
                 ((RecF32 *)records)[slot] = rec;
             }
         });
+        }
     }
 }
 
@@ -732,7 +803,10 @@ void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, cons
                   uint32_t *cls_counts, int n_cls, hipStream_t s) {
     const unsigned blocks = binning_blocks(g);
     if (blocks == 0) return;
-    k_count<<<blocks, kBinThreads, 0, s>>>(g, uvw, mask, st, cls_counts, n_cls);
+    if (g.w_h > 0)
+        k_count<true><<<blocks, kBinThreads, 0, s>>>(g, uvw, mask, st, cls_counts, n_cls);
+    else
+        k_count<false><<<blocks, kBinThreads, 0, s>>>(g, uvw, mask, st, cls_counts, n_cls);
 }
 
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
@@ -752,12 +826,15 @@ void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const 
                     int n_cls, void *records, uint32_t capacity, uint32_t *overflow, hipStream_t s) {
     const unsigned blocks = binning_blocks(g);
     if (blocks == 0) return;
-    if (f64)
-        k_scatter<double><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
-                                                         records, capacity, overflow);
-    else
-        k_scatter<float><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls,
-                                                        records, capacity, overflow);
+#define WSG_SCATTER(VT, WK)                                                                        \
+    k_scatter<VT, WK><<<blocks, kBinThreads, 0, s>>>(g, uvw, vis, wts, mask, st, cls_cursor, n_cls, \
+                                                     records, capacity, overflow)
+    if (f64) {
+        if (g.w_h > 0) WSG_SCATTER(double, true); else WSG_SCATTER(double, false);
+    } else {
+        if (g.w_h > 0) WSG_SCATTER(float, true); else WSG_SCATTER(float, false);
+    }
+#undef WSG_SCATTER
 }
 
 size_t scan_tmp_elems(size_t n) {

@@ -408,6 +408,23 @@ __device__ __forceinline__ void acc_re(double &acc, C2<T> z, float c, float s) {
     acc += (double)(z.x * c - z.y * s);
 }
 
+// C_w(nu) of the kernel in w by its quadrature table; FP64 cosines for the FP64
+// mode, else the hardware's of the exactly reduced argument in turns
+template <int PM>
+__device__ __forceinline__ double w_transform(const double *__restrict__ cw, int n_cw, double nu) {
+    double c = 0.0;
+    for (int j = 0; j < n_cw; ++j) {
+        const double t = nu * cw[2 * j];
+        if constexpr (PM == 0) {
+            c += cw[2 * j + 1] * cospi(2.0 * t);
+        } else {
+            const double r = t - rint(t);
+            c += cw[2 * j + 1] * (double)__builtin_amdgcn_cosf((float)r);
+        }
+    }
+    return c;
+}
+
 template <typename T, int N, bool PH32>
 __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C2<T> *__restrict__ stack,
                                                                         const C2<T> *__restrict__ tw,
@@ -435,14 +452,14 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
     double acc[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) acc[s] = 0.0;
-    const double w_min = st.w_min, dw = st.dw;
+    const double w0 = st.w0, dw = st.dw;
     uint32_t live_next = 0xffffu;
     if (a.occ.live2 && a.n_pl > 0) live_next = a.occ.live2[(size_t)img * a.n_pl * P + ix.t];
     T *lre = lds + (size_t)ix.r * SH::NPAD;
     T *lim = lds + (size_t)(NTR + ix.r) * SH::NPAD;
     for (int kl = 0; kl < a.n_pl; ++kl) {
         const int k = a.plane_lo + kl;
-        const double wk = (dw == 0.0) ? w_min : w_min + ((double)k + 0.5) * dw;
+        const double wk = (dw == 0.0) ? w0 : w0 + ((double)k + 0.5) * dw;
         const size_t pi = (size_t)img * a.n_pl + kl;
         const C2<T> *Y = stack + pi * N * N;
         // points of rows that pass 1 wrote (all of them for a dense stack; none of a
@@ -478,6 +495,8 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
         const double l = (double)(p - N / 2) * a.cell;
         const bool inside = l * l + m * m < 1.0;
         double d = inside ? acc[s] * inv_row * (a.inv_c ? a.inv_c[p] : 1.0) : 0.0;
+        if (a.cw && inside && dw > 0.0)
+            d /= w_transform<PM>(a.cw, a.n_cw, dw * (double)s_nm1[ix.r * N + p]);
         if ((p + q) & 1) d = -d;
         stg[ix.r * N + p] = d;
     }
@@ -504,13 +523,14 @@ __global__ __launch_bounds__(256) void k_wcorrect(const C2<T> *__restrict__ F, W
     double acc = 0.0;
     for (int kl = 0; kl < a.n_pl; ++kl) {
         const int k = a.plane_lo + kl;
-        const double wk = (st.dw == 0.0) ? st.w_min : st.w_min + ((double)k + 0.5) * st.dw;
+        const double wk = (st.dw == 0.0) ? st.w0 : st.w0 + ((double)k + 0.5) * st.dw;
         C2<T> z = F[(size_t)kl * n2 + pix];
         typename std::conditional<PM == 0, double, float>::type c, s;
         Phase<PM>::screen(nm1, wk, c, s);
         acc_re(acc, z, c, s);
     }
     double d = inside ? acc * st.inv_norm * (a.inv_c ? a.inv_c[p] * a.inv_c[q] : 1.0) : 0.0;
+    if (a.cw && inside && st.dw > 0.0) d /= w_transform<PM>(a.cw, a.n_cw, st.dw * (double)nm1);
     image[pix] = d;
 }
 

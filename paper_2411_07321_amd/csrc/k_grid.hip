@@ -111,17 +111,6 @@ __device__ __forceinline__ void kb_line(float f, const float *__restrict__ poly,
     }
 }
 
-// Kaiser-Bessel value on an FP64 mesh: Horner's rule on the power series in u
-// (0 outside the support, where u < 0).
-__device__ __forceinline__ double kb_value(double d, const double *__restrict__ c, int n, int S) {
-    const double t = 2.0 * d / (double)S;
-    const double u = 1.0 - t * t;
-    if (u < 0.0) return 0.0;
-    double acc = c[n - 1];
-    for (int k = n - 2; k >= 0; --k) acc = fma(acc, u, c[k]);
-    return acc;
-}
-
 __device__ __forceinline__ void bin_coords(const JobGeom &g, uint32_t b, int &img, int &kl, int &ty,
                                            int &tx) {
     uint32_t per_plane = (uint32_t)g.NT * g.NT;
@@ -298,8 +287,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         } else {
 #pragma unroll
             for (int a = 0; a < SS; ++a) {
-                gx[a] = kb_value((T)(a - H) - fx, g.kb_series, g.kb_n, SS);
-                gy[a] = kb_value((T)(a - H) - fy, g.kb_series, g.kb_n, SS);
+                gx[a] = kb_series_value((T)(a - H) - fx, g.kb_series, g.kb_n, SS);
+                gy[a] = kb_series_value((T)(a - H) - fy, g.kb_series, g.kb_n, SS);
             }
         }
 #pragma unroll
@@ -502,6 +491,7 @@ __global__ void k_accum_chunk(const uint32_t *__restrict__ counts, uint32_t *__r
             acc[i].w_min = st[i].w_min;
             acc[i].w_max = st[i].w_max;
             acc[i].dw = st[i].dw;
+            acc[i].w0 = st[i].w0;
             acc[i].inv_dw = st[i].inv_dw;
         }
         acc_overflow[0] += overflow[0];

@@ -58,7 +58,8 @@ struct ImgState {
     unsigned long long n_valid0;             // pass every test but the w range
     unsigned long long n_used;
     double sum_w;
-    double w_min, w_max, dw;                 // plane geometry used by the job
+    double w_min, w_max, dw;                 // data (or given) range of w and plane width
+    double w0;                               // planes sit at w0 + (k + 1/2) dw
     double inv_dw;                           // 1/dw (0 when dw = 0)
     double inv_norm;                         // 1/sum_w (or 1, or 0 for an empty image)
     unsigned long long n_tiles, n_tile_rows; // occupied (plane, tile) / (plane, tile-row)
@@ -72,6 +73,18 @@ struct ImgState {
 // (kKbEven coefficients in x^2) and odd part (kKbOdd coefficients in x^2, times x):
 // tap S-1-a is the same polynomial at -x, so the two share both parts.
 constexpr int kKbMaxSeries = 128;
+
+// Kaiser-Bessel value I0(beta sqrt(u)) / I0(beta), u = 1 - (2d/S)^2, by Horner's rule
+// on its power series c[0 .. n) (0 outside the support, where u < 0).
+__device__ __forceinline__ double kb_series_value(double d, const double *__restrict__ c, int n,
+                                                  int S) {
+    const double t = 2.0 * d / (double)S;
+    const double u = 1.0 - t * t;
+    if (u < 0.0) return 0.0;
+    double acc = c[n - 1];
+    for (int k = n - 2; k >= 0; --k) acc = fma(acc, u, c[k]);
+    return acc;
+}
 constexpr int kKbDeg = 8;
 constexpr int kKbEven = kKbDeg / 2 + 1;
 constexpr int kKbOdd = (kKbDeg + 1) / 2;
@@ -98,6 +111,12 @@ struct JobGeom {
     const float *kb_poly;     // per-tap polynomials in x = 2f, kKbStride floats per tap
     int32_t range_given;
     int32_t w_fold;         // rows with w < 0 placed at (-u, -v, -w), visibility conjugated
+    // kernel in w over 2 w_h + 1 planes (w_h = 0: nearest plane only): Gaussian
+    // exp(-d^2 w_inv2s2), or Kaiser-Bessel from the series kbw_series[0 .. kbw_n)
+    int32_t w_h;
+    double w_inv2s2;
+    const double *kbw_series;
+    int32_t kbw_n;
     double w_min_given, w_max_given;
     const double *chan_scale;  // device [n_chan]: f/c or 1
     // track traversal of the binning passes: rows are viewed as [n_t][P]
@@ -106,6 +125,12 @@ struct JobGeom {
     // track having n_tb such stretches
     int64_t P, n_t, n_tb;
 };
+
+// Weight of plane offset d (in planes, w_k - w over dw) under the kernel in w.
+__device__ __forceinline__ double w_weight(const JobGeom &g, double d) {
+    if (g.kbw_series) return kb_series_value(d, g.kbw_series, g.kbw_n, 2 * g.w_h + 1);
+    return exp(-d * d * g.w_inv2s2);
+}
 
 // Binning stretch: kStretch time slices of one (baseline, channel) track, one per
 // lane of a binning wave (the wavefront size).
@@ -211,9 +236,13 @@ struct WcorrArgs {
     int phase32;             // FP32 phase screen
     int naive_nm1;           // FP32 phase with sqrt(1-eta)-1
     double cell;
-    const ImgState *st;      // per image: w_min, dw, inv_norm
+    const ImgState *st;      // per image: w0, dw, inv_norm
     const double *inv_c;     // [N] 1/C(nu) or NULL for no grid correction
     Occupancy occ;           // what pass 1 wrote (live2 is used)
+    // kernel in w: C_w(nu) = sum_j cw[2j+1] cos(2 pi nu cw[2j]) (quadrature nodes
+    // and weights times the window), divided out at nu = dw (n - 1); NULL: none
+    const double *cw;
+    int n_cw;
 };
 void launch_fft_pass2_wcorr(const WcorrArgs &a, bool f64, const void *planes,
                             const void *twiddle, double *image, hipStream_t s);

@@ -208,6 +208,15 @@ const KbHost &kb_host(int S, double beta) {
     return it->second;
 }
 
+int w_half(const wsg_params *p) { return p->w_support > 1 ? (p->w_support - 1) / 2 : 0; }
+
+// beta of the kernel in w: the given one, else the default for w_support
+double kb_beta_w(const wsg_params *p) {
+    wsg_params q = *p;
+    q.support = p->w_support;
+    return kb_beta(&q);
+}
+
 wsg_status check_params(const wsg_params *p, std::string &why) {
     if (!p) { why = "params is NULL"; return WSG_EINVAL; }
     if (!is_pow2(p->grid_n) || p->grid_n < 4) { why = "grid_n must be a power of two"; return WSG_EINVAL; }
@@ -248,6 +257,22 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
         if (lo < 0 || hi > p->n_wplanes || lo >= hi) { why = "plane range outside [0, n_wplanes)"; return WSG_EINVAL; }
         if (!(lo == 0 && hi == p->n_wplanes) && lo_nan) {
             why = "a plane range needs a given w range";
+            return WSG_EINVAL;
+        }
+    }
+    if (p->w_support < 0 || (p->w_support > 1 && p->w_support % 2 == 0)) {
+        why = "w_support must be 0, 1 or odd";
+        return WSG_EINVAL;
+    }
+    if (p->w_support > kMaxSupport) { why = "w_support above 15"; return WSG_EUNSUPPORTED; }
+    if (p->w_support > 1) {
+        if (p->n_wplanes < p->w_support) { why = "a kernel in w needs n_wplanes >= w_support"; return WSG_EINVAL; }
+        if (!(lo == 0 && hi == 0) && !(lo == 0 && hi == p->n_wplanes)) {
+            why = "a kernel in w needs the full plane range";
+            return WSG_EUNSUPPORTED;
+        }
+        if (p->kernel == WSG_KERNEL_KAISER_BESSEL && !(kb_beta_w(p) > 0.0)) {
+            why = "w_support has no default kernel_beta";
             return WSG_EINVAL;
         }
     }
@@ -374,7 +399,7 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
     pl.o_aux = take(0);
     pl.fixed_bytes = off;
     double rep = (double)(tile + pl.S - 1) / tile;
-    pl.records_est = (size_t)((double)pl.n_elem * rep * rep) + 1024;
+    pl.records_est = (size_t)((double)pl.n_elem * rep * rep * (2 * w_half(p) + 1)) + 1024;
     pl.items_est = pl.n_bins + pl.records_est / kChunk + 1;
     return pl;
 }
@@ -494,10 +519,10 @@ wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const dou
 
 // Device copy of the Kaiser-Bessel tables: kKbMaxSeries doubles of the power series,
 // then the per-tap polynomials.
-wsg_status get_kb(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
-    const double beta = kb_beta(p);
-    const KbHost &h = kb_host(p->support, beta);
-    auto key = std::make_pair((int)p->support, beta);
+wsg_status kb_tables(wsg_ctx *ctx, int S, double beta, const double **series, int32_t *n,
+                     const float **poly) {
+    const KbHost &h = kb_host(S, beta);
+    auto key = std::make_pair(S, beta);
     auto it = ctx->kb.find(key);
     const size_t o_poly = kKbMaxSeries * sizeof(double);
     if (it == ctx->kb.end()) {
@@ -510,9 +535,60 @@ wsg_status get_kb(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
         WSG_HIP(ctx, hipMemcpy(b.ptr, host.data(), b.size, hipMemcpyHostToDevice));
         it = ctx->kb.emplace(key, b).first;
     }
-    g->kb_series = (const double *)it->second.ptr;
-    g->kb_n = (int32_t)h.series.size();
-    g->kb_poly = (const float *)((const char *)it->second.ptr + o_poly);
+    *series = (const double *)it->second.ptr;
+    *n = (int32_t)h.series.size();
+    *poly = (const float *)((const char *)it->second.ptr + o_poly);
+    return WSG_OK;
+}
+
+// Kernel tables of a job: the uv kernel's Kaiser-Bessel tables, and the kernel in w
+wsg_status kernel_tables(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
+    const float *poly = nullptr;
+    if (p->kernel == WSG_KERNEL_KAISER_BESSEL) {
+        wsg_status rc = kb_tables(ctx, p->support, kb_beta(p), &g->kb_series, &g->kb_n, &g->kb_poly);
+        if (rc) return rc;
+    }
+    g->w_h = w_half(p);
+    g->w_inv2s2 = 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma);
+    if (g->w_h > 0 && p->kernel == WSG_KERNEL_KAISER_BESSEL) {
+        wsg_status rc = kb_tables(ctx, p->w_support, kb_beta_w(p), &g->kbw_series, &g->kbw_n, &poly);
+        if (rc) return rc;
+    }
+    return WSG_OK;
+}
+
+// Quadrature table of the kernel in w for its grid correction: C_w(nu) =
+// sum_j cw[2j+1] cos(2 pi nu cw[2j]) by 32-point Gauss-Legendre over the support
+// (the window is analytic there).  NULL without a kernel in w or a grid correction.
+wsg_status get_cw(wsg_ctx *ctx, const wsg_params *p, const double **out, int *n_out) {
+    *out = nullptr;
+    *n_out = 0;
+    if (!(p->flags & WSG_GRID_CORRECT) || w_half(p) == 0) return WSG_OK;
+    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    const double shape = kb ? kb_beta_w(p) : p->kernel_sigma;
+    auto key = std::make_tuple(-1, (int)p->w_support, (int)p->kernel, shape);
+    auto it = ctx->inv_c.find(key);
+    constexpr int M = 32;
+    if (it == ctx->inv_c.end()) {
+        std::vector<double> xs, ws;
+        gauss_legendre(M, xs, ws);
+        const double a = p->w_support / 2.0, i0b = kb ? bessel_i0(shape) : 1.0;
+        const double s2 = 2.0 * p->kernel_sigma * p->kernel_sigma;
+        std::vector<double> t(2 * M);
+        for (int j = 0; j < M; ++j) {
+            const double d = a * xs[j];
+            const double gv = kb ? kb_exact(p->w_support, shape, i0b, d) : std::exp(-d * d / s2);
+            t[2 * j] = d;
+            t[2 * j + 1] = a * ws[j] * gv;
+        }
+        DevBuf b;
+        WSG_HIP(ctx, hipMalloc(&b.ptr, t.size() * sizeof(double)));
+        b.size = t.size() * sizeof(double);
+        WSG_HIP(ctx, hipMemcpy(b.ptr, t.data(), b.size, hipMemcpyHostToDevice));
+        it = ctx->inv_c.emplace(key, b).first;
+    }
+    *out = (const double *)it->second.ptr;
+    *n_out = M;
     return WSG_OK;
 }
 
@@ -651,10 +727,10 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     g.kb_series = nullptr;
     g.kb_n = 0;
     g.kb_poly = nullptr;
-    if (p->kernel == WSG_KERNEL_KAISER_BESSEL) {
-        rc = get_kb(ctx, p, &g);
-        if (rc) return rc;
-    }
+    g.kbw_series = nullptr;
+    g.kbw_n = 0;
+    rc = kernel_tables(ctx, p, &g);
+    if (rc) return rc;
     g.range_given = range_given(p) ? 1 : 0;
     g.w_fold = (p->flags & WSG_W_FOLD) ? 1 : 0;
     g.w_min_given = p->w_min;
@@ -853,6 +929,8 @@ wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *im
     a.st = b.st;
     a.inv_c = inv_c;
     a.occ = occ;
+    rc = get_cw(ctx, p, &a.cw, &a.n_cw);
+    if (rc) return rc;
     launch_fft_pass2_wcorr(a, pl.f64, stack, tw, img_dev, s);
     WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
@@ -1205,7 +1283,8 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
     std::memset(hs, 0, sizeof(ImgState));
     hs->w_min = w_min;
     hs->w_max = w_max;
-    hs->dw = (w_max - w_min) / (double)p->n_wplanes;
+    hs->dw = (w_max - w_min) / (double)(p->n_wplanes - 2 * w_half(p));
+    hs->w0 = w_min - (double)w_half(p) * hs->dw;
     hs->sum_w = sum_w;
     hs->inv_norm = (p->flags & WSG_NORMALIZE) ? (sum_w > 0.0 ? 1.0 / sum_w : 0.0) : 1.0;
     WSG_HIP(ctx, hipMemcpyAsync(st, hs, sizeof(ImgState), hipMemcpyHostToDevice, s));
@@ -1224,6 +1303,8 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
     a.cell = p->cell_rad;
     a.st = st;
     a.inv_c = inv_c;
+    rc = get_cw(ctx, p, &a.cw, &a.n_cw);
+    if (rc) return rc;
     launch_wcorrect(a, f64_mode(p), src, dst, s);
     WSG_HIP(ctx, hipGetLastError());
     if (mem == WSG_MEM_HOST) {
@@ -1367,7 +1448,8 @@ wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, vo
         std::memset(&x, 0, sizeof(x));
         x.w_min = p->w_min;
         x.w_max = p->w_max;
-        x.dw = (p->w_max - p->w_min) / p->n_wplanes;
+        x.dw = (p->w_max - p->w_min) / (p->n_wplanes - 2 * w_half(p));
+        x.w0 = p->w_min - (double)w_half(p) * x.dw;
     }
     if (hipMemsetAsync(a->mem, 0, a->L.bytes, s) != hipSuccess ||
         hipMemcpyAsync(a->mem + a->L.o_state, init.data(), init.size() * sizeof(ImgState),
@@ -1458,6 +1540,8 @@ wsg_status wsg_accum_finish(wsg_accum *a, double *image, int32_t image_mem, void
     w.st = st;
     w.inv_c = inv_c;
     w.occ = occ;
+    rc = get_cw(ctx, p, &w.cw, &w.n_cw);
+    if (rc) return rc;
     launch_fft_pass2_wcorr(w, f64, stack, tw, img_dev, s);
     WSG_HIP(ctx, hipGetLastError());
     if (host_img) {

@@ -45,7 +45,8 @@ class Params(ctypes.Structure):
                 ("w_min", ctypes.c_double), ("w_max", ctypes.c_double),
                 ("plane_lo", ctypes.c_int32), ("plane_hi", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("kernel_beta", ctypes.c_double)]
+                ("kernel", ctypes.c_int32), ("kernel_beta", ctypes.c_double),
+                ("w_support", ctypes.c_int32)]
 
 
 class Vis(ctypes.Structure):
@@ -187,16 +188,17 @@ KERNEL = {"gauss": 0, "kb": 1}
 def make_params(grid_n, n_wplanes, support, cell_rad, precision="f32_phase64", kernel_sigma=0.9,
                 w_min=None, w_max=None, plane_lo=0, plane_hi=0, grid_correct=True,
                 normalize=True, per_channel=False, naive_nm1=False, tile=0, kernel="gauss",
-                kernel_beta=0.0, w_fold=False) -> Params:
+                kernel_beta=0.0, w_fold=False, w_support=1) -> Params:
     """kernel: "gauss" (width kernel_sigma) or "kb" (Kaiser-Bessel, shape kernel_beta;
-    0 = the library's default for the support)."""
+    0 = the library's default for the support).  w_fold: grid rows with w < 0 at their
+    Hermitian mirror.  w_support: planes a visibility spreads over (1: its own)."""
     flags = (GRID_CORRECT if grid_correct else 0) | (NORMALIZE if normalize else 0) | \
         (PER_CHANNEL if per_channel else 0) | (NAIVE_NM1 if naive_nm1 else 0) | \
         (W_FOLD if w_fold else 0)
     return Params(int(grid_n), int(n_wplanes), int(support), PREC[precision], float(cell_rad),
                   float(kernel_sigma), math.nan if w_min is None else float(w_min),
                   math.nan if w_max is None else float(w_max), int(plane_lo), int(plane_hi),
-                  flags, int(tile), KERNEL[kernel], float(kernel_beta))
+                  flags, int(tile), KERNEL[kernel], float(kernel_beta), int(w_support))
 
 
 @dataclass

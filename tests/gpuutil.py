@@ -37,14 +37,14 @@ def cast_inputs(precision, vis, wts):
 def both_params(grid_n, n_wplanes, support, cell_rad, precision="f64", kernel_sigma=0.9,
                 w_min=None, w_max=None, plane_lo=0, plane_hi=0, grid_correct=True,
                 normalize=True, per_channel=False, naive_nm1=False, tile=0, kernel="gauss",
-                kernel_beta=0.0, w_fold=False):
+                kernel_beta=0.0, w_fold=False, w_support=1):
     wp = wsg.make_params(grid_n, n_wplanes, support, cell_rad, precision, kernel_sigma, w_min,
                          w_max, plane_lo, plane_hi, grid_correct, normalize, per_channel,
-                         naive_nm1, tile, kernel, kernel_beta, w_fold)
+                         naive_nm1, tile, kernel, kernel_beta, w_fold, w_support)
     op = oracle.Params(grid_n, n_wplanes, support, cell_rad, kernel_sigma,
                        math.nan if w_min is None else w_min, math.nan if w_max is None else w_max,
                        plane_lo, plane_hi, grid_correct, normalize, per_channel, kernel,
-                       kernel_beta, w_fold)
+                       kernel_beta, w_fold, w_support)
     return wp, op
 
 

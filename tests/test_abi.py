@@ -74,6 +74,14 @@ def _v(n_rows=10, n_chan=1, **kw):
     (dict(kernel="kb", kernel_beta=60.0, precision="f32_phase64"), wsg.EUNSUPPORTED),
     (dict(kernel="kb", kernel_beta=25.0, precision="f32_phase64"), wsg.OK),
     (dict(kernel="kb", support=3, kernel_beta=10.0, precision="f32_phase32"), wsg.EUNSUPPORTED),
+    (dict(w_support=7), wsg.OK),
+    (dict(w_support=7, kernel="kb"), wsg.OK),
+    (dict(w_support=4), wsg.EINVAL),
+    (dict(w_support=-1), wsg.EINVAL),
+    (dict(w_support=17), wsg.EUNSUPPORTED),
+    (dict(w_support=9), wsg.EINVAL),                      # more planes of kernel than planes
+    (dict(w_support=3, plane_lo=2, plane_hi=4, w_min=0.0, w_max=1.0), wsg.EUNSUPPORTED),
+    (dict(w_support=3, plane_lo=0, plane_hi=8, w_min=0.0, w_max=1.0), wsg.OK),
 ])
 def test_parameter_validation(kw, code):
     assert wsg.check(_p(**kw), _v()) == code
