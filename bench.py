@@ -107,6 +107,7 @@ def cpu_baseline(ds_host: dict, params: dict, n_total: int) -> dict:
     n = params["grid_n"]
     prm1 = oracle.Params(n, 1, params["support"], params["cell_rad"], params["kernel_sigma"],
                          kernel=params.get("kernel", "gauss"))
+
     t0 = time.perf_counter()
     wmin, wmax = oracle.w_range(inp, prm1)
     g, cnt = oracle.grid(inp, prm1, wmin, wmax)
@@ -199,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=("gauss", "kb"), default="gauss",
                     help="gridding kernel: Gaussian (sigma 0.9) or Kaiser-Bessel")
+    ap.add_argument("--w-support", type=int, default=1,
+                    help="planes each visibility spreads over (the gridding kernel in w)")
     ap.add_argument("--chunks", type=int, default=0,
                     help="image the workload as a chunked job of this many time chunks "
                          "(wsg_accum_*) instead of one call")
@@ -209,6 +212,8 @@ def main():
                     help="run only a reference elementwise pass of known traffic (2 GiB read, "
                          "2 GiB written per launch) for calibrating rocprofv3 byte counters")
     args = ap.parse_args()
+    if args.w_support > 1:
+        args.no_cpu_baseline = True   # the oracle's rate is taken on the nearest-plane workload
     if args.copy_calibration:
         import torch
         n = 2 ** 29
@@ -236,6 +241,7 @@ def main():
     torch.cuda.synchronize()
     progress(f"inputs ready in {time.perf_counter() - t0:.1f} s: vis {tuple(d['vis'].shape)}")
     d["params"]["kernel"] = args.kernel
+    d["params"]["w_support"] = args.w_support
     prm = wsg.make_params(**d["params"], tile=TILE)
     vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"], d["row_period"])
     n = d["params"]["grid_n"]
@@ -273,6 +279,8 @@ def main():
         f"config1_rows_stride_{args.rows_stride}"
     if args.kernel == "kb":
         workload += "_kaiser_bessel"
+    if args.w_support > 1:
+        workload += f"_w_support{args.w_support}"
     if kname == "k_grid":
         # VALU / LDS-atomic bound: useful arithmetic per launch over the launch time
         flops = GRID_FLOP_PER_VIS * n_used
@@ -303,7 +311,7 @@ def main():
         "config": {"workload": workload, "grid_n": n, "n_wplanes": d["params"]["n_wplanes"],
                    "support": 7, "visibilities": int(d["vis"].numel()), "n_used": n_used,
                    "precision": d["params"]["precision"], "tile": TILE,
-                   "kernel": args.kernel},
+                   "kernel": args.kernel, "w_support": args.w_support},
         "roofline": roof,
         "path_roofline": {"bound": "hbm", "B_alg_bytes": model["B_alg"],
                           "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
