@@ -11,17 +11,21 @@ from tests.gpuutil import DEV, log
 pytestmark = pytest.mark.gpu
 
 
-def test_config1_sampled_pixels():
+@pytest.mark.parametrize("kernel,fold", [("gauss", False), ("kb", True)])
+def test_config1_sampled_pixels(kernel, fold):
+    """The Gaussian of the workload, and the paper's Kaiser-Bessel window with w-folding."""
     import torch
     d = synth.config1_device(DEV)
-    prm = wsg.make_params(**{**d["params"], "grid_correct": False, "normalize": False})
+    prm = wsg.make_params(**{**d["params"], "grid_correct": False, "normalize": False,
+                             "kernel": kernel, "w_fold": fold})
     vb = wsg.make_vis(d["uvw"], d["vis"], d["weights"], None, d["freq_hz"], d["row_period"])
     out = torch.empty((1, 4096, 4096), dtype=torch.float64, device=DEV)
     with wsg.Context(0) as ctx:
         st = ctx.image(prm, vb, out)
     torch.cuda.synchronize()
     img = out[0]
-    log(f"config 1 imaged: {st[0]['n_used']} used, {st[0]['n_dropped']} dropped")
+    log(f"config 1 ({kernel}, fold {fold}) imaged: {st[0]['n_used']} used, "
+        f"{st[0]['n_dropped']} dropped")
     # the 8 brightest sources and 8 random pixels
     sky = d["sky"]
     cell = 0.2 / 4096
@@ -35,7 +39,8 @@ def test_config1_sampled_pixels():
     inp = oracle.Inputs.make(d["uvw"].cpu().numpy(), d["freq_hz"],
                              d["vis"].cpu().numpy().astype(np.complex128),
                              d["weights"].cpu().numpy().astype(np.float64))
-    op = oracle.Params(4096, 64, 7, cell, 0.9, grid_correct=False, normalize=False)
+    op = oracle.Params(4096, 64, 7, cell, 0.9, grid_correct=False, normalize=False,
+                       kernel=kernel, w_fold=fold)
     log("oracle: direct evaluation of 16 pixels")
     ref = oracle.pixels(inp, op, q, p).real
     err = np.abs(got - ref)

@@ -128,3 +128,26 @@ def test_w_kernel_in_chunks_and_degenerate_range(ctx, config0):
     ref = oracle_image(op, uvw, ds.vis, ds.weights)
     assert_stats(st, ref["stats"])
     assert rel(img[0], ref["image"][0]) <= TOL64
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_phase64"])
+def test_w_kernel_stage_wcorrect(ctx, precision):
+    """The w-correction entry point alone with a kernel in w: planes at w0 + (k + 1/2) dw
+    of the padded geometry, and the window's transform divided out per pixel."""
+    import torch
+    n, nw = 256, 9
+    F = synth.random_planes(nw, n, seed=78)
+    cell = 0.35 / n
+    w_min, w_max, sum_w = -20.0, 28.0, 77.25     # dw |n - 1| <= 0.3 over the field
+    wp, op = both_params(n, nw, 7, cell, precision, w_support=5)
+    ctype = torch.complex128 if precision == "f64" else torch.complex64
+    Fd = dev(F).to(ctype)
+    out = torch.empty((n, n), dtype=torch.float64, device=DEV)
+    ctx.stage_wcorrect(wp, Fd, w_min, w_max, sum_w, out)
+    torch.cuda.synchronize()
+    Fin = Fd.cpu().numpy().astype(np.complex128)
+    A = oracle.wcorrect(Fin, w_min, w_max, nw, cell, 0, 5)
+    ref = oracle.post(A, sum_w, op, w_min, w_max)
+    e = rel(out.cpu().numpy(), ref)
+    log(f"w kernel stage wcorrect {precision}: rel err {e:.3e}")
+    assert e <= (TOL64 if precision == "f64" else 1e-6)
