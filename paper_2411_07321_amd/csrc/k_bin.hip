@@ -644,50 +644,50 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double
         const int tx0 = (int)(tb0 & (uint32_t)(g.NT - 1)), ty0 = (int)(tb0 >> g.logNT);
         const int hw = WK ? g.w_h : 0;
         for (int dk = -hw; dk <= hw; ++dk) {
-        // weight of plane k0 + dk under the kernel in w (1 without one)
-        double gw = 1.0;
-        if constexpr (WK)
-            if (pk != kNoKey && (pk & kSpread)) {
-                const uint32_t ki = L.kimg[q];
-                gw = w_weight(g, plane_offset(st[ki >> 16], (int)(ki & 0xffffu) + dk, L.wv[q]));
-            }
-        const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
-        for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
-            uint32_t base = 0u;
-            if (lane == leader) base = atomicAdd(&cursor[bin], (uint32_t)__popcll(m));
-            base = (uint32_t)__shfl((int)base, leader);
-            if (!mine) return;
-            const uint32_t slot = base + lanes_below(m, lane);
-            // the counting pass sized the buffer; a slot beyond it would mean the
-            // two passes disagree: never write there, report it instead
-            if (slot >= capacity) {
-                atomicAdd(overflow, 1u);
-                return;
-            }
-            const uint32_t tt = bin & tmask;
-            const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
-            if constexpr (sizeof(VT) == 8) {
-                const uint32_t lij = L.lij[q];
-                RecF64 rec;
-                rec.fx = L.fx[q];
-                rec.fy = L.fy[q];
-                rec.re = WK ? L.re[q] * gw : L.re[q];
-                rec.im = WK ? L.im[q] * gw : L.im[q];
-                rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
-                rec.lj = (int)(lij >> 16) - (dy << g.logT);
-                ((RecF64 *)records)[slot] = rec;
-            } else {
-                const uint32_t a = L.a[q], b = L.b[q];
-                RecF32 rec;
-                rec.px = (((a >> kFracBits) - ((uint32_t)dx << g.logT) + (uint32_t)g.h) << kFracBits) |
-                         (a & 0xffffffu);
-                rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
-                         (b & 0xffffffu);
-                rec.re = WK ? L.re[q] * (float)gw : L.re[q];
-                rec.im = WK ? L.im[q] * (float)gw : L.im[q];
-                ((RecF32 *)records)[slot] = rec;
-            }
-        });
+            // weight of plane k0 + dk under the kernel in w (1 without one)
+            double gw = 1.0;
+            if constexpr (WK)
+                if (pk != kNoKey && (pk & kSpread)) {
+                    const uint32_t ki = L.kimg[q];
+                    gw = w_weight(g, plane_offset(st[ki >> 16], (int)(ki & 0xffffu) + dk, L.wv[q]));
+                }
+            const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
+            for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
+                uint32_t base = 0u;
+                if (lane == leader) base = atomicAdd(&cursor[bin], (uint32_t)__popcll(m));
+                base = (uint32_t)__shfl((int)base, leader);
+                if (!mine) return;
+                const uint32_t slot = base + lanes_below(m, lane);
+                // the counting pass sized the buffer; a slot beyond it would mean the
+                // two passes disagree: never write there, report it instead
+                if (slot >= capacity) {
+                    atomicAdd(overflow, 1u);
+                    return;
+                }
+                const uint32_t tt = bin & tmask;
+                const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
+                if constexpr (sizeof(VT) == 8) {
+                    const uint32_t lij = L.lij[q];
+                    RecF64 rec;
+                    rec.fx = L.fx[q];
+                    rec.fy = L.fy[q];
+                    rec.re = WK ? L.re[q] * gw : L.re[q];
+                    rec.im = WK ? L.im[q] * gw : L.im[q];
+                    rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
+                    rec.lj = (int)(lij >> 16) - (dy << g.logT);
+                    ((RecF64 *)records)[slot] = rec;
+                } else {
+                    const uint32_t a = L.a[q], b = L.b[q];
+                    RecF32 rec;
+                    rec.px = (((a >> kFracBits) - ((uint32_t)dx << g.logT) + (uint32_t)g.h) << kFracBits) |
+                             (a & 0xffffffu);
+                    rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
+                             (b & 0xffffffu);
+                    rec.re = WK ? L.re[q] * (float)gw : L.re[q];
+                    rec.im = WK ? L.im[q] * (float)gw : L.im[q];
+                    ((RecF32 *)records)[slot] = rec;
+                }
+            });
         }
     }
 }
