@@ -178,17 +178,21 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t q0 = r0 + min(n, threadIdx.x * per);
     const uint32_t q1 = r0 + min(n, (threadIdx.x + 1) * per);
 
-    T ar[ACC ? SS : 1][ACC ? SS : 1], ai[ACC ? SS : 1][ACC ? SS : 1];
-    int cli = INT32_MIN, clj = 0, run = 0;
-    auto flush = [&](int li, int lj) {
+    // register window of a run: W x W cells from the anchor (ax, ay) (the nearest
+    // cell of a record at offset (0, 0), minus H); records whose nearest cell lies at
+    // offset 0 or 1 in each axis join the run, mx / my say whether offset 1 was used
+    constexpr int W = ACC ? SS + 1 : 1;
+    T ar[W][W], ai[W][W];
+    int ax = 0, ay = 0, mx = 0, my = 0, run = 0;
+    auto flush = [&]() {
         if constexpr (ACC) {
 #pragma unroll
-            for (int bb = 0; bb < SS; ++bb) {
-                int j = lj + bb - H;
+            for (int bb = 0; bb < W; ++bb) {
+                int j = ay + bb - H;
 #pragma unroll
-                for (int a = 0; a < SS; ++a) {
-                    int i = li + a - H;
-                    if (j >= 0 && j < TT && i >= 0 && i < TT) {
+                for (int a = 0; a < W; ++a) {
+                    int i = ax + a - H;
+                    if ((bb < SS || my) && (a < SS || mx) && j >= 0 && j < TT && i >= 0 && i < TT) {
                         atomicAdd(&s_re[j * TP + i], (double)ar[bb][a]);
                         atomicAdd(&s_im[j * TP + i], (double)ai[bb][a]);
                     }
@@ -200,9 +204,9 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     };
     if constexpr (ACC) {
 #pragma unroll
-        for (int bb = 0; bb < SS; ++bb)
+        for (int bb = 0; bb < W; ++bb)
 #pragma unroll
-            for (int a = 0; a < SS; ++a) {
+            for (int a = 0; a < W; ++a) {
                 ar[bb][a] = T(0);
                 ai[bb][a] = T(0);
             }
@@ -214,25 +218,40 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
 #pragma unroll
         for (int k = 0; k <= H; ++k) q[k] = __builtin_amdgcn_exp2f(-(float)(k * k) * cl2);
         const float *__restrict__ kbp = g.kb_poly;
-        // A lane whose next record starts a new run (another cell, or kRunCap records
-        // summed) parks until the wave flushes: the wave adds the register sums of
-        // all parked lanes to the tile together once kFlushLanes lanes are parked,
-        // or when no lane can go on, so each pass of 2 S^2 LDS atomics serves many
-        // lanes rather than the one or two whose cell just changed.
+        // A lane whose next record cannot join its run (its cell leaves the 2 x 2
+        // window of nearest cells, or kRunCap records are summed) parks until the wave
+        // flushes: the wave adds the register sums of all parked lanes to the tile
+        // together once kFlushLanes lanes are parked, or when no lane can go on, so
+        // each pass of LDS atomics serves many lanes rather than the one or two whose
+        // run just ended.  A track moves about a cell per record on long baselines,
+        // so a window of two cells per axis roughly halves the runs; a run's anchor
+        // steps one cell down where the record after its first steps down, so the
+        // window faces the track's direction.
         uint32_t pos = q0;
         bool pend = false;
-        RecF32 nx{};
+        RecF32 nx{}, nn{};
         if (pos < q1) nx = rec[pos];
+        if (pos + 1 < q1) nn = rec[pos + 1];
         for (;;) {
             if (pos < q1 && !pend) {
                 const int li = (int)(nx.px >> kFracBits) - H;
                 const int lj = (int)(nx.py >> kFracBits) - H;
-                if (run == 0 || (li == cli && lj == clj && run < kRunCap)) {
+                if (run == 0) {
+                    ax = li;
+                    ay = lj;
+                    if (pos + 1 < q1) {
+                        if ((int)(nn.px >> kFracBits) - H == li - 1) ax = li - 1;
+                        if ((int)(nn.py >> kFracBits) - H == lj - 1) ay = lj - 1;
+                    }
+                }
+                const int dx = li - ax, dy = lj - ay;
+                if ((run == 0 || run < kRunCap) && (dx == 0 || dx == 1) && (dy == 0 || dy == 1)) {
                     int li2, lj2;
                     T fx, fy, re, im;
                     RecTraits<T>::decode(nx, H, li2, lj2, fx, fy, re, im);
                     ++pos;
-                    if (pos < q1) nx = rec[pos];
+                    nx = nn;
+                    if (pos + 1 < q1) nn = rec[pos + 1];
                     T gx[SS], gy[SS];
                     if constexpr (KIND == 0) {
                         gauss_line<SS>(fx, cl2, q, gx);
@@ -241,17 +260,24 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                         kb_line<SS>(fx, kbp, gx);
                         kb_line<SS>(fy, kbp, gy);
                     }
+                    // the footprint's weights placed in the window at offset (dx, dy)
+                    T wx[W], wy[W];
 #pragma unroll
-                    for (int bb = 0; bb < SS; ++bb) {
-                        T wr = re * gy[bb], wi = im * gy[bb];
+                    for (int a = 0; a < W; ++a) {
+                        wx[a] = dx ? (a >= 1 ? gx[a - 1] : T(0)) : (a < SS ? gx[a] : T(0));
+                        wy[a] = dy ? (a >= 1 ? gy[a - 1] : T(0)) : (a < SS ? gy[a] : T(0));
+                    }
 #pragma unroll
-                        for (int a = 0; a < SS; ++a) {
-                            ar[bb][a] += wr * gx[a];
-                            ai[bb][a] += wi * gx[a];
+                    for (int bb = 0; bb < W; ++bb) {
+                        T wr = re * wy[bb], wi = im * wy[bb];
+#pragma unroll
+                        for (int a = 0; a < W; ++a) {
+                            ar[bb][a] += wr * wx[a];
+                            ai[bb][a] += wi * wx[a];
                         }
                     }
-                    cli = li;
-                    clj = lj;
+                    mx |= dx;
+                    my |= dy;
                     ++run;
                     if (pos == q1) pend = true;
                 } else {
@@ -263,8 +289,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             if (pm == 0 && lm == 0) break;
             if (__popcll(pm) >= kFlushLanes || lm == 0) {
                 if (pend) {
-                    flush(cli, clj);
+                    flush();
                     run = 0;
+                    mx = 0;
+                    my = 0;
                     pend = false;
                 }
             }
