@@ -178,12 +178,14 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t q0 = r0 + min(n, threadIdx.x * per);
     const uint32_t q1 = r0 + min(n, (threadIdx.x + 1) * per);
 
-    // register window of a run: W x W cells from the anchor (ax, ay) (the nearest
-    // cell of a record at offset (0, 0), minus H); records whose nearest cell lies at
-    // offset 0 or 1 in each axis join the run, mx / my say whether offset 1 was used
-    constexpr int W = ACC ? SS + 1 : 1;
+    // register window of a run: W x W cells from the anchor (ax, ay) - H, the anchor
+    // being one cell below and left of the run's first nearest cell; records whose
+    // nearest cell lies at offset 0, 1 or 2 from the anchor in each axis join the
+    // run, and [lx, hx] x [ly, hy] are the offsets used (the flush adds only the
+    // window's columns lx .. hx + S - 1 and rows ly .. hy + S - 1)
+    constexpr int W = ACC ? SS + 2 : 1;
     T ar[W][W], ai[W][W];
-    int ax = 0, ay = 0, mx = 0, my = 0, run = 0;
+    int ax = 0, ay = 0, lx = 0, hx = 0, ly = 0, hy = 0, run = 0;
     auto flush = [&]() {
         if constexpr (ACC) {
 #pragma unroll
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
 #pragma unroll
                 for (int a = 0; a < W; ++a) {
                     int i = ax + a - H;
-                    if ((bb < SS || my) && (a < SS || mx) && j >= 0 && j < TT && i >= 0 && i < TT) {
+                    if (bb >= ly && bb < SS + hy && a >= lx && a < SS + hx && j >= 0 && j < TT && i >= 0 && i < TT) {
                         atomicAdd(&s_re[j * TP + i], (double)ar[bb][a]);
                         atomicAdd(&s_im[j * TP + i], (double)ai[bb][a]);
                     }
@@ -218,18 +220,16 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
 #pragma unroll
         for (int k = 0; k <= H; ++k) q[k] = __builtin_amdgcn_exp2f(-(float)(k * k) * cl2);
         const float *__restrict__ kbp = g.kb_poly;
-        // A lane whose next record cannot join its run (its cell leaves the 2 x 2
-        // window of nearest cells, or kRunCap records are summed) parks until the wave
-        // flushes: the wave adds the register sums of all parked lanes to the tile
-        // together once kFlushLanes lanes are parked, or when no lane can go on, so
-        // each pass of LDS atomics serves many lanes rather than the one or two whose
-        // run just ended.  A track moves about a cell per record on long baselines,
-        // so a window of two cells per axis roughly halves the runs; a run's anchor
-        // steps one cell down where the record after its first steps down, so the
-        // window faces the track's direction.
+        // A lane whose next record cannot join its run (its nearest cell leaves the
+        // 3 x 3 block of cells around the run's first, or kRunCap records are summed)
+        // parks until the wave flushes: the wave adds the register sums of all parked
+        // lanes to the tile together once kFlushLanes lanes are parked, or when no
+        // lane can go on, so each pass of LDS atomics serves many lanes rather than
+        // the one or two whose run just ended.  A track moves about a cell per record
+        // on long baselines; the block halves the runs of single cells.
         uint32_t pos = q0;
         bool pend = false;
-        RecF32 nx{}, nn{};
+        RecF32 nx{}, nn{};   // the lane's next two records, loaded ahead
         if (pos < q1) nx = rec[pos];
         if (pos + 1 < q1) nn = rec[pos + 1];
         for (;;) {
@@ -237,15 +237,12 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 const int li = (int)(nx.px >> kFracBits) - H;
                 const int lj = (int)(nx.py >> kFracBits) - H;
                 if (run == 0) {
-                    ax = li;
-                    ay = lj;
-                    if (pos + 1 < q1) {
-                        if ((int)(nn.px >> kFracBits) - H == li - 1) ax = li - 1;
-                        if ((int)(nn.py >> kFracBits) - H == lj - 1) ay = lj - 1;
-                    }
+                    ax = li - 1;
+                    ay = lj - 1;
+                    lx = hx = ly = hy = 1;
                 }
                 const int dx = li - ax, dy = lj - ay;
-                if ((run == 0 || run < kRunCap) && (dx == 0 || dx == 1) && (dy == 0 || dy == 1)) {
+                if (run < kRunCap && dx >= 0 && dx <= 2 && dy >= 0 && dy <= 2) {
                     int li2, lj2;
                     T fx, fy, re, im;
                     RecTraits<T>::decode(nx, H, li2, lj2, fx, fy, re, im);
@@ -264,8 +261,12 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                     T wx[W], wy[W];
 #pragma unroll
                     for (int a = 0; a < W; ++a) {
-                        wx[a] = dx ? (a >= 1 ? gx[a - 1] : T(0)) : (a < SS ? gx[a] : T(0));
-                        wy[a] = dy ? (a >= 1 ? gy[a - 1] : T(0)) : (a < SS ? gy[a] : T(0));
+                        const T x0 = a < SS ? gx[a] : T(0), x1 = (a >= 1 && a <= SS) ? gx[a - 1] : T(0),
+                                x2 = a >= 2 ? gx[a - 2] : T(0);
+                        const T y0 = a < SS ? gy[a] : T(0), y1 = (a >= 1 && a <= SS) ? gy[a - 1] : T(0),
+                                y2 = a >= 2 ? gy[a - 2] : T(0);
+                        wx[a] = dx == 0 ? x0 : (dx == 1 ? x1 : x2);
+                        wy[a] = dy == 0 ? y0 : (dy == 1 ? y1 : y2);
                     }
 #pragma unroll
                     for (int bb = 0; bb < W; ++bb) {
@@ -276,8 +277,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                             ai[bb][a] += wi * wx[a];
                         }
                     }
-                    mx |= dx;
-                    my |= dy;
+                    lx = min(lx, dx);
+                    hx = max(hx, dx);
+                    ly = min(ly, dy);
+                    hy = max(hy, dy);
                     ++run;
                     if (pos == q1) pend = true;
                 } else {
@@ -291,8 +294,6 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 if (pend) {
                     flush();
                     run = 0;
-                    mx = 0;
-                    my = 0;
                     pend = false;
                 }
             }
