@@ -134,11 +134,12 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // Each lane takes a contiguous stretch of the work item's records.  The
 // binning pass keeps the records of one track (one baseline and channel over
 // consecutive times) contiguous inside a bin, and a track moves slowly, so
-// consecutive records of a lane usually have the same nearest cell.  With
-// ACC (complex64 mesh, S <= 7) the lane sums the S x S footprint values of
-// such records in registers and adds them to the LDS tile only when the cell
-// changes, or after kRunCap records (so an FP32 register sum never holds more
-// than kRunCap terms); otherwise every record is added to the tile directly.
+// consecutive records of a lane have nearby nearest cells.  With ACC (complex64
+// mesh, S <= 7) the lane sums the footprint values of such records in an
+// (S+2) x (S+2) register window and adds it to the LDS tile only when a record's
+// nearest cell leaves the 3 x 3 block around the run's first, or after kRunCap
+// records (so an FP32 register sum never holds more than kRunCap terms);
+// otherwise every record is added to the tile directly.
 // (Variants that add the whole footprint from one base address, inside the tile
 // or into an LDS apron, measured slower: bursts of 98 back-to-back FP64 LDS
 // atomics, and an apron that leaves room for one workgroup per CU.)
