@@ -39,7 +39,6 @@ namespace wsg {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBatch = 4;          // elements of a track whose loads are issued together
 
 __device__ __forceinline__ unsigned long long order_key(double d) {
     unsigned long long b = (unsigned long long)__double_as_longlong(d);
@@ -300,11 +299,6 @@ __device__ __forceinline__ bool place_vals(const JobGeom &g, const ImgState &s, 
     return true;
 }
 
-__device__ __forceinline__ bool place(const JobGeom &g, const ImgState &s, const double *uvw,
-                                      int64_t r, int c, Placed &pl) {
-    return place_vals(g, s, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], g.chan_scale[c], pl);
-}
-
 __device__ __forceinline__ int64_t bin_base(const JobGeom &g, int img, int kl) {
     return ((int64_t)img * g.n_pl + kl) << (2 * g.logNT);
 }
@@ -561,8 +555,16 @@ __device__ __forceinline__ double plane_offset(const ImgState &s, int k, double 
     return (wk - w) / s.dw;
 }
 
+// waves per SIMD to plan registers for: the complex64 scatter's LDS leaves room
+// for 7 workgroups per CU, and more waves in flight hide the latency of its slot
+// reservations (4.5 -> 3.95 ms on config 1 against the register count the
+// compiler picks by itself)
 template <typename VT, bool WK>
-__global__ __launch_bounds__(kBinThreads) void k_scatter(JobGeom g, const double *__restrict__ uvw,
+struct ScatterWaves { static constexpr int value = (sizeof(VT) == 4 && !WK) ? 7 : 1; };
+
+template <typename VT, bool WK>
+__global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(ScatterWaves<VT, WK>::value)))
+void k_scatter(JobGeom g, const double *__restrict__ uvw,
                                                          const void *__restrict__ vis,
                                                          const void *__restrict__ wts,
                                                          const uint8_t *__restrict__ mask,
