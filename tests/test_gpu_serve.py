@@ -76,3 +76,22 @@ def test_failure_isolated(pool, monkeypatch):
             else:
                 assert info["status"] == wsg.OK
                 assert rel(out, solo512[i]) <= 1e-6
+
+
+def test_mix_of_kernels_and_plane_mappings(pool):
+    """Jobs in one mix may use different gridding kernels and plane mappings (the
+    Kaiser-Bessel window, w-folding, a kernel in w): each image equals the job alone."""
+    import copy
+    variants = []
+    for i, (kernel, fold, sw) in enumerate((("kb", False, 1), ("gauss", True, 1), ("kb", True, 3))):
+        job = copy.copy(pool[i])
+        job.params = wsg.params_for(pool[i].ds, grid_correct=False, kernel=kernel, w_fold=fold,
+                                    w_support=sw)
+        variants.append(job)
+    solo = [_solo(j) for j in variants]
+    order = np.array([0, 1, 2, 2, 1, 0])
+    r = serve.replay(variants, order, np.zeros(len(order)), n_slots=3,
+                     keep_images=set(range(len(order))))
+    for k, img in r["images"].items():
+        e = rel(img, solo[order[k]])
+        assert e <= 1e-6, (k, e)
