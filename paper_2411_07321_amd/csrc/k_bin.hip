@@ -22,9 +22,10 @@
 // reads 16 stretches x 64 time slices with coalesced loads (consecutive
 // threads, consecutive rows of one time slice) and places every element into
 // an LDS table; then each wave takes whole stretches, one time slice per lane.
-// A track moves slowly across the mesh, so the lanes of a wave mostly fall in
-// the same few bins: for each distinct bin the wave counts its lanes with one
-// ballot and takes one global atomic, and the scatter writes the lanes'
+// A track moves slowly across the mesh, so consecutive lanes of a wave mostly
+// hold the same bins: each run of lanes with the same bin takes one global
+// atomic (the runs of a wave are found with shuffles and two ballots, and all
+// of them issue their atomics together), and the scatter writes a run's
 // records to consecutive slots.  This matters because the uv coverage is
 // extremely uneven: the short baselines of a dense core all land in the few
 // central tiles, where per-element atomics would serialise; the atomics are
@@ -408,37 +409,32 @@ __device__ __forceinline__ void tile_slot(int k, int &t, int &s) {
 }
 static_assert(kBinThreads % kBinStretches == 0, "phase A keeps one stretch per thread");
 
-// For every bin among the lanes' keys (0 to 4 per lane, none repeated within a
-// lane): f(bin, lanes holding it, leader lane, this lane holds it).  Every lane
-// takes every step (the ballots and shuffles need the whole wave).
+// The keys of a wave, slot by slot (a lane's first key, then its second, ...), as
+// runs of consecutive lanes (consecutive time slices of one track) holding the same
+// key.  f(key, len, head_lane, rank, head, mine) is called by every lane for every
+// slot in use: `head` marks a run's first lane, `len` its length there, and `rank`
+// is the lane's position in its run.  All runs of a slot are handled by the same
+// instructions, so a wave takes one atomic round trip per slot, not per bin.
 template <typename F>
-__device__ __forceinline__ void for_each_bin(const Keys &ks, F &&f) {
-    unsigned done = 0u;
-    for (;;) {
-        int first = -1;
+__device__ __forceinline__ void for_each_run(const Keys &ks, int lane, F &&f) {
 #pragma unroll
-        for (int i = 3; i >= 0; --i)
-            if (i < ks.n && !((done >> i) & 1u)) first = i;
-        const unsigned long long hm = __ballot(first >= 0);
-        if (hm == 0ull) break;
-        const int leader = __ffsll((long long)hm) - 1;
-        uint32_t cand = 0u;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (i == first) cand = ks.k[i];
-        const uint32_t bin = (uint32_t)__shfl((int)cand, leader);
-        int hit = -1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (i < ks.n && !((done >> i) & 1u) && ks.k[i] == bin) hit = i;
-        const unsigned long long m = __ballot(hit >= 0);
-        f(bin, m, leader, hit >= 0);
-        if (hit >= 0) done |= 1u << hit;
+    for (int i = 0; i < 4; ++i) {
+        const bool has = i < ks.n;
+        if (__ballot(has) == 0ull) break;   // slots are filled in order
+        const uint32_t key = has ? ks.k[i] : kNoKey;
+        const uint32_t prev = (uint32_t)__shfl_up((int)key, 1);
+        const uint32_t next = (uint32_t)__shfl_down((int)key, 1);
+        const bool head = has && (lane == 0 || prev != key);
+        const bool tail = has && (lane == 63 || next != key);
+        const unsigned long long heads = __ballot(head), tails = __ballot(tail);
+        const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const unsigned long long from = ~((1ull << lane) - 1ull);
+        const unsigned long long hu = heads & upto;
+        const int hl = has && hu ? 63 - __clzll((long long)hu) : lane;
+        const int tl = __ffsll((long long)(tails & from)) - 1;
+        const uint32_t len = head ? (uint32_t)(tl - lane + 1) : 0u;
+        f(key, len, hl, (uint32_t)(lane - hl), head, has);
     }
-}
-
-__device__ __forceinline__ uint32_t lanes_below(unsigned long long m, int lane) {
-    return (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
 // sub-cell offset f in [-1/2, 1/2) as 24-bit fixed point
@@ -510,8 +506,8 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
         const int hw = WK ? g.w_h : 0;
         for (int dk = -hw; dk <= hw; ++dk) {
             const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
-            for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool) {
-                if (lane == leader) atomicAdd(&counts[bin], (uint32_t)__popcll(m));
+            for_each_run(kd, lane, [&](uint32_t bin, uint32_t len, int, uint32_t, bool head, bool) {
+                if (head) atomicAdd(&counts[bin], len);
             });
         }
     }
@@ -654,12 +650,13 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
                     gw = w_weight(g, plane_offset(st[ki >> 16], (int)(ki & 0xffffu) + dk, L.wv[q]));
                 }
             const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
-            for_each_bin(kd, [&](uint32_t bin, unsigned long long m, int leader, bool mine) {
+            for_each_run(kd, lane, [&](uint32_t bin, uint32_t len, int hl, uint32_t rank, bool head,
+                                       bool mine) {
                 uint32_t base = 0u;
-                if (lane == leader) base = atomicAdd(&cursor[bin], (uint32_t)__popcll(m));
-                base = (uint32_t)__shfl((int)base, leader);
+                if (head) base = atomicAdd(&cursor[bin], len);
+                base = (uint32_t)__shfl((int)base, hl);
                 if (!mine) return;
-                const uint32_t slot = base + lanes_below(m, lane);
+                const uint32_t slot = base + rank;
                 // the counting pass sized the buffer; a slot beyond it would mean the
                 // two passes disagree: never write there, report it instead
                 if (slot >= capacity) {
