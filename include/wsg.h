@@ -223,7 +223,7 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
 
 /* ---------------------------------------------------------------------------
  * Chunked imaging: data larger than one call, loaded chunk after chunk by time
- * or by frequency (Sec. 6), onto one resident w-stack
+ * or by frequency (the paper's Discussion, Sec. 5), onto one resident w-stack
  * ------------------------------------------------------------------------- */
 /*
  * An accumulator owns the w-stack of one imaging job (n_images x planes x N x N,
@@ -290,7 +290,10 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
  * so a large job does not block smaller ones behind it.  Admitted jobs run
  * concurrently on their slots' streams; their staging copies, kernels and
  * read-back overlap on the device.  A job that fails (bad parameters, a device
- * error) completes with its error status; the other jobs are unaffected.
+ * error) completes with its error status; the other jobs are unaffected.  (For
+ * checks of that isolation, the environment variable WSG_SERVER_FAIL_GRID_N, read
+ * when the server is created, makes every job of that mesh size fail in its slot
+ * with WSG_EDEVICE before any device work.)
  * Buffers of a job (inputs, freq_hz, image) must stay valid until it is
  * reported done.  A job whose footprint alone exceeds the budget fails with
  * WSG_ENOMEM.

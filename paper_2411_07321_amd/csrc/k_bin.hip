@@ -1,7 +1,7 @@
 // Binning of visibilities by (image, w-plane, uv tile): a counting sort.
 //
-// Sec. 2 of the paper buckets the visibilities of each mesh slab before the
-// convolution ("an array is created for each slab").  Here the buckets are
+// Sec. 2 of the paper groups the visibilities of each mesh slab into a bucket of
+// their own before the convolution.  Here the buckets are
 // square uv tiles of every w-plane, so that the gridding kernel can keep one
 // tile in LDS.  A visibility whose footprint crosses a tile edge is recorded
 // in every tile it touches (at most four); each tile then owns its cells and

@@ -210,6 +210,12 @@ const KbHost &kb_host(int S, double beta) {
 
 int w_half(const wsg_params *p) { return p->w_support > 1 ? (p->w_support - 1) / 2 : 0; }
 
+// Worst-case binning records of n_elem visibilities: a footprint of S <= T + 1 cells
+// touches at most two tiles per axis, on each of the 2 w_h + 1 planes of the kernel in w.
+uint64_t max_records(const wsg_params *p, int64_t n_elem) {
+    return (uint64_t)n_elem * 4u * (uint64_t)(2 * w_half(p) + 1);
+}
+
 // beta of the kernel in w: the given one, else the default for w_support
 double kb_beta_w(const wsg_params *p) {
     wsg_params q = *p;
@@ -298,8 +304,15 @@ wsg_status check_vis(const wsg_params *p, const wsg_vis *v, std::string &why) {
     if (v->mem != WSG_MEM_HOST && v->mem != WSG_MEM_DEVICE) { why = "bad memory space"; return WSG_EINVAL; }
     if (v->n_rows > 0 && (!v->uvw || !v->vis)) { why = "uvw or vis is NULL"; return WSG_EINVAL; }
     int64_t n_elem = v->n_rows * (int64_t)v->n_chan;
-    // records (up to four per visibility) are addressed with 32-bit offsets
     if (n_elem > (int64_t)1 << 29) { why = "more than 2^29 visibilities per call"; return WSG_EUNSUPPORTED; }
+    // binning records are addressed with 32-bit offsets: a visibility makes at most
+    // four (one per uv tile its footprint touches) on each of the w_support planes
+    // it spreads over, and the worst case must stay below 2^32
+    if (max_records(p, n_elem) > (uint64_t)UINT32_MAX) {
+        why = "more than 2^32 - 1 binning records possible (4 x w_support per visibility): split "
+              "the visibilities into chunks";
+        return WSG_EUNSUPPORTED;
+    }
     if ((p->flags & WSG_PER_CHANNEL) && v->n_chan > 256) { why = "more than 256 channels per cube"; return WSG_EUNSUPPORTED; }
     if (v->n_chan > 4096) { why = "more than 4096 channels"; return WSG_EUNSUPPORTED; }
     if (v->freq_hz) {
@@ -1170,10 +1183,6 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
     if (rc) return rc;
     if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
     if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
-    // test hook for failure isolation: jobs of mesh size WSG_FAIL_GRID_N fail on the
-    // host before any device work
-    if (const char *f = std::getenv("WSG_FAIL_GRID_N"))
-        if (std::atoi(f) == p->grid_n) return fail(ctx, WSG_EDEVICE, "failure injected by WSG_FAIL_GRID_N");
     hipStream_t s = pick_stream(ctx, stream);
     bool host_img = image_mem == WSG_MEM_HOST;
     mark(ctx, kMarkStart, s);

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -62,6 +63,9 @@ struct wsg_server {
     std::map<uint64_t, std::shared_ptr<Job>> jobs;
     std::vector<Slot> slots;
     uint64_t peak = 0;
+    // failure isolation checks: jobs of this mesh size fail in their slot before any
+    // device work (WSG_SERVER_FAIL_GRID_N, read once when the server is created; 0: none)
+    int fail_grid_n = 0;
 
     uint64_t held_total() const {
         uint64_t h = 0;
@@ -131,7 +135,10 @@ struct wsg_server {
             wsg_stats st{};
             int n_img = wsg_n_images(&j->p, &j->v);
             std::vector<wsg_stats> all((size_t)std::max(1, n_img));
-            wsg_status rc = wsg_image(s.ctx, &j->p, &j->v, j->image, j->image_mem, wsg_context_stream(s.ctx), all.data());
+            wsg_status rc = (fail_grid_n && j->p.grid_n == fail_grid_n)
+                                ? WSG_EDEVICE
+                                : wsg_image(s.ctx, &j->p, &j->v, j->image, j->image_mem,
+                                            wsg_context_stream(s.ctx), all.data());
             if (rc == WSG_OK) st = all[0];
             double t_end = now_s();
             {
@@ -160,6 +167,7 @@ wsg_status wsg_server_create(int device, int32_t n_slots, uint64_t hbm_budget, w
     if (!srv) return WSG_ENOMEM;
     srv->device = device;
     srv->budget = hbm_budget;
+    if (const char *f = std::getenv("WSG_SERVER_FAIL_GRID_N")) srv->fail_grid_n = std::atoi(f);
     srv->slots.resize((size_t)n_slots);
     for (auto &s : srv->slots) {
         wsg_status rc = wsg_create(device, &s.ctx);

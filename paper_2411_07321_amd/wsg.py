@@ -182,6 +182,47 @@ def _ptr_mem(x):
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
+def _numel(x) -> int:
+    return int(x.numel()) if _is_torch(x) else int(x.size)
+
+
+def _kind(x) -> tuple[str, int]:
+    """('c' complex | 'f' float | 'u' unsigned | 'b' bool | 'i' int, bytes per element)."""
+    if _is_torch(x):
+        dt = x.dtype
+        size = x.element_size()
+        if dt.is_complex:
+            return "c", size
+        if dt.is_floating_point:
+            return "f", size
+        return ("b" if str(dt) == "torch.bool" else ("u" if str(dt) == "torch.uint8" else "i")), size
+    return x.dtype.kind, x.dtype.itemsize
+
+
+def _check_inputs(params: Params, vb: "VisBuffers"):
+    """The library reads vis, weights and flags with the element types of the precision
+    and assumes [n_rows][n_chan] extents (the C ABI carries no sizes): check them here."""
+    uvw, vis, wts, flags = vb.keep[:4]
+    rows, nch = vb.desc.n_rows, vb.desc.n_chan
+    f64 = params.precision == PREC["f64"]
+    if _kind(uvw) != ("f", 8) or _numel(uvw) != 3 * rows:
+        raise ValueError("uvw must be float64 [n_rows, 3]")
+    if _kind(vis) != ("c", 16 if f64 else 8) or _numel(vis) != rows * nch:
+        raise ValueError(f"vis must be {'complex128' if f64 else 'complex64'} [n_rows, n_chan] "
+                         "for this precision")
+    if wts is not None and (_kind(wts) != ("f", 8 if f64 else 4) or _numel(wts) != rows * nch):
+        raise ValueError(f"weights must be {'float64' if f64 else 'float32'} [n_rows, n_chan] "
+                         "for this precision")
+    if flags is not None and (_kind(flags)[1] != 1 or _numel(flags) != rows * nch):
+        raise ValueError("flags must be one byte per element, [n_rows, n_chan]")
+
+
+def _check_out(out, n_elems: int, kind: tuple, what: str):
+    if _kind(out) != kind or _numel(out) < n_elems:
+        raise ValueError(f"{what} must hold at least {n_elems} elements of "
+                         f"{ {('f', 8): 'float64', ('c', 16): 'complex128', ('c', 8): 'complex64'}[kind] }")
+
+
 KERNEL = {"gauss": 0, "kb": 1}
 
 
@@ -227,6 +268,10 @@ def make_vis(uvw, vis, weights=None, flags=None, freq_hz=None, row_period=0) -> 
     d = Vis(int(n_rows), int(n_chan), spaces.pop() if spaces else MEM_HOST, int(row_period), pu,
             None if fq is None else fq.ctypes.data, pv, pw, pf)
     return VisBuffers(d, (uvw, vis, weights, flags, fq))
+
+
+def _mesh_kind(params: Params) -> tuple:
+    return ("c", 16) if params.precision == PREC["f64"] else ("c", 8)
 
 
 def _stream_of(x, stream):
@@ -292,6 +337,8 @@ class Context:
         tensor.  Returns per-image stats (list of dicts) when stats is True."""
         po, mo = _ptr_mem(out)
         n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
+        _check_inputs(params, vb)
+        _check_out(out, max(1, n_img) * params.grid_n ** 2, ("f", 8), "the image")
         st_arr = (Stats * max(1, n_img))() if stats else None
         s = _stream_of(out, stream)
         rc = load().wsg_image(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
@@ -302,6 +349,10 @@ class Context:
     def stage_grid(self, params: Params, vb: VisBuffers, out, stream=None):
         po, mo = _ptr_mem(out)
         n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
+        _check_inputs(params, vb)
+        n_pl = (params.plane_hi - params.plane_lo) if params.plane_hi > params.plane_lo \
+            else params.n_wplanes
+        _check_out(out, max(1, n_img) * n_pl * params.grid_n ** 2, _mesh_kind(params), "the grid")
         st_arr = (Stats * max(1, n_img))()
         rc = load().wsg_stage_grid(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
                                    _stream_of(out, stream), st_arr)
@@ -311,6 +362,7 @@ class Context:
     def stage_fft(self, params: Params, planes, stream=None):
         po, mo = _ptr_mem(planes)
         n = planes.shape[0] if planes.ndim == 3 else 1
+        _check_out(planes, n * params.grid_n ** 2, _mesh_kind(params), "the planes")
         rc = load().wsg_stage_fft(self._h, ctypes.byref(params), po, int(n), mo,
                                   _stream_of(planes, stream))
         self._check(rc, "wsg_stage_fft")
@@ -321,6 +373,8 @@ class Context:
         if mp != mo:
             raise ValueError("planes and image must live in one memory space")
         n = planes.shape[0] if planes.ndim == 3 else 1
+        _check_out(planes, n * params.grid_n ** 2, _mesh_kind(params), "the planes")
+        _check_out(out, params.grid_n ** 2, ("f", 8), "the image")
         rc = load().wsg_stage_wcorrect(self._h, ctypes.byref(params), pp, int(n), float(w_min),
                                        float(w_max), float(sum_w), po, mo,
                                        _stream_of(out, stream))
@@ -355,12 +409,14 @@ class Accum:
         stream is given, host chunks on HIP's null stream."""
         keep = vb.keep
         s = _stream_of(next((x for x in keep if x is not None and _is_torch(x)), None), stream)
+        _check_inputs(self._params, vb)
         self._ctx._check(load().wsg_accum_add(self._h, ctypes.byref(vb.desc), s), "wsg_accum_add")
 
     def finish(self, out, stream=None):
         """Transform, w-correct and sum into `out` ([n_images,N,N] float64, host array or
         device tensor); returns per-image stats of all chunks."""
         po, mo = _ptr_mem(out)
+        _check_out(out, self._n_img * self._params.grid_n ** 2, ("f", 8), "the image")
         st_arr = (Stats * self._n_img)()
         rc = load().wsg_accum_finish(self._h, po, mo, _stream_of(out, stream), st_arr)
         self._ctx._check(rc, "wsg_accum_finish")
@@ -406,6 +462,8 @@ class Server:
     def submit(self, params: Params, vb: VisBuffers, out) -> int:
         """Queue a job; `out` must stay valid until the job is reported done."""
         po, mo = _ptr_mem(out)
+        _check_inputs(params, vb)
+        _check_out(out, max(1, n_images(params, vb)) * params.grid_n ** 2, ("f", 8), "the image")
         t = ctypes.c_uint64(0)
         st = load().wsg_server_submit(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po,
                                       mo, ctypes.byref(t))

@@ -26,6 +26,17 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+# per-pixel bar of the FP32 paths next to the relative L2 one: the largest pixel error
+# against the largest oracle pixel (the precision study measures about 2e-7)
+PEAK32 = 1e-6
+
+
+def peak(a, b):
+    """max |a - b| / max |b|: a bad column or tile row cannot hide in a norm."""
+    mb = np.abs(b).max()
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0))
+
+
 def cast_inputs(precision, vis, wts):
     if precision == "f64":
         return (np.ascontiguousarray(vis, np.complex128),

@@ -172,3 +172,71 @@ def test_accum_footprint_and_rules():
     with pytest.raises(wsg.WsgError) as e:
         wsg.accum_footprint(ok, 0)
     assert e.value.status == wsg.EINVAL
+
+
+def test_record_offsets_guard():
+    """Binning records are addressed with 32-bit offsets; a call whose worst case
+    (4 records per visibility on each of the w_support planes) reaches 2^32 is refused
+    before any device work, and the largest safe call is accepted."""
+    largest = (2 ** 32 - 1) // (4 * 7)
+    uvw = np.zeros((1, 3))
+    vis = np.zeros((1, 1), np.complex128)
+
+    def desc(n_rows):
+        vb = wsg.make_vis(uvw, vis)
+        vb.desc.n_rows = n_rows        # pointers are not dereferenced by the check
+        return vb
+
+    assert wsg.check(_p(w_support=7), desc(2 ** 29)) == wsg.EUNSUPPORTED
+    assert wsg.check(_p(w_support=7), desc(largest + 1)) == wsg.EUNSUPPORTED
+    assert wsg.check(_p(w_support=7), desc(largest)) == wsg.OK
+    assert wsg.check(_p(w_support=3), desc(2 ** 29)) == wsg.EUNSUPPORTED
+    assert wsg.check(_p(), desc(2 ** 29)) == wsg.OK           # 2^31 records at most
+    assert wsg.check(_p(), desc(2 ** 29 + 1)) == wsg.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,vdt,wdt,ok", [
+    ("f64", np.complex128, np.float64, True),
+    ("f64", np.complex64, np.float32, False),
+    ("f64", np.complex128, np.float32, False),
+    ("f32_phase64", np.complex64, np.float32, True),
+    ("f32_phase64", np.complex128, np.float64, False),
+    ("f32_phase32", np.complex64, np.float64, False),
+])
+def test_binding_checks_element_types(prec, vdt, wdt, ok):
+    """The C ABI carries no sizes or element types: the binding refuses buffers whose
+    element type or extent does not match the precision before calling it."""
+    uvw = np.zeros((10, 3))
+    vb = wsg.make_vis(uvw, np.zeros((10, 2), vdt), np.ones((10, 2), wdt))
+    p = _p(precision=prec)
+    if ok:
+        wsg._check_inputs(p, vb)
+    else:
+        with pytest.raises(ValueError):
+            wsg._check_inputs(p, vb)
+
+
+def test_binding_checks_outputs():
+    with pytest.raises(ValueError):
+        wsg._check_out(np.zeros((1, 256, 256), np.float32), 256 * 256, ("f", 8), "the image")
+    with pytest.raises(ValueError):
+        wsg._check_out(np.zeros((1, 255, 256)), 256 * 256, ("f", 8), "the image")
+    wsg._check_out(np.zeros((1, 256, 256)), 256 * 256, ("f", 8), "the image")
+    with pytest.raises(ValueError):
+        wsg._check_inputs(_p(), wsg.make_vis(np.zeros((10, 2)), np.zeros((10, 1), np.complex128)))
+    with pytest.raises(ValueError):
+        wsg._check_inputs(_p(), wsg.make_vis(np.zeros((10, 3)), np.zeros((10, 1), np.complex128),
+                                             None, np.zeros((9, 1), np.uint8)))
+
+
+def test_context_refuses_mismatched_buffers_before_the_call():
+    """A float32 image or complex64 visibilities under the FP64 precision raise ValueError
+    in the binding (no device is touched: the check comes first)."""
+    ctx = wsg.Context.__new__(wsg.Context)      # no device needed for the check
+    ctx._h = None
+    vb = wsg.make_vis(np.zeros((10, 3)), np.zeros((10, 1), np.complex64))
+    with pytest.raises(ValueError):
+        ctx.image(_p(), vb, np.zeros((1, 256, 256)))
+    vb = wsg.make_vis(np.zeros((10, 3)), np.zeros((10, 1), np.complex128))
+    with pytest.raises(ValueError):
+        ctx.image(_p(), vb, np.zeros((1, 256, 256), np.float32))

@@ -8,7 +8,7 @@ import pytest
 
 from paper_2411_07321_amd import synth, wsg
 from tests.gpuutil import (DEV, assert_stats, both_params, cast_inputs, dev, log, oracle_image,
-                           rel)
+                           rel, PEAK32, peak)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,7 @@ def test_time_chunks_f32_with_a_hot_bin(ctx, on_device):
     e = rel(img[0], ref["raw"][0].real)
     log(f"accum f32 1024^2 x 16 on_device={on_device}: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def _channel_data(rows=4000, nch=4, seed=23):

@@ -9,7 +9,7 @@ import oracle
 from paper_2411_07321_amd import synth, wsg
 from tests import pinlib
 from tests.gpuutil import (DEV, assert_stats, both_params, cast_inputs, dev, gpu_image, log,
-                           oracle_image, rel)
+                           oracle_image, rel, PEAK32, peak)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_config0_fold_f32(ctx, config0, precision):
     e = rel(img[0], ref["raw"][0].real)
     log(f"fold config0 {precision}: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def test_fold_stage_grid_and_mesh_edges(ctx):

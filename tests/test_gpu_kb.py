@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2411_07321_amd import synth, wsg
-from tests.gpuutil import DEV, assert_stats, both_params, cast_inputs, dev, gpu_image, log, oracle_image, rel
+from tests.gpuutil import DEV, assert_stats, both_params, cast_inputs, dev, gpu_image, log, oracle_image, rel, PEAK32, peak
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +47,7 @@ def test_config0_kb_f32_raw(ctx, config0, precision):
     e = rel(img[0], ref["raw"][0].real)
     log(f"config0 kb {precision}: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32_phase64"])
@@ -89,6 +90,8 @@ def test_kb_supports(ctx, support, beta, precision):
     e = rel(img[0], ref["raw"][0].real)
     log(f"kb S={support} beta={beta} {precision}: raw rel err {e:.3e}")
     assert e <= (TOL64 if precision == "f64" else TOL32)
+    if precision != "f64":
+        assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def test_kb_f32_ragged_tiles_and_split_bins(ctx):
@@ -107,6 +110,7 @@ def test_kb_f32_ragged_tiles_and_split_bins(ctx):
     e = rel(img[0], ref["raw"][0].real)
     log(f"kb f32 1024^2 x 16 tile 32: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def test_kb_and_gauss_share_a_context(ctx, config0):

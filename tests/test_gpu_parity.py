@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2411_07321_amd import synth, wsg
 from tests.gpuutil import (DEV, assert_stats, both_params, cast_inputs, dev, gpu_image, log,
-                           oracle_image, rel)
+                           oracle_image, rel, PEAK32, peak)
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,7 @@ def test_config0_f32_paths(ctx, config0, precision):
     e = rel(img[0], ref["raw"][0].real)
     log(f"config0 {precision}: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 # ---------------------------------------------------------------- stages
@@ -148,6 +149,7 @@ def test_f32_random_1024_ragged(ctx):
     e = rel(img[0], ref["raw"][0].real)
     log(f"f32 1024^2 x 16, 300001 vis: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 # ---------------------------------------------------------------- edge cases
@@ -229,6 +231,7 @@ def test_tiles_f32(ctx, tile):
     img, st = gpu_image(ctx, wp, uvw, vis, wts)
     ref = oracle_image(op, uvw, vis, wts)
     assert rel(img[0], ref["raw"][0].real) <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def test_split_hot_tiles(ctx):
@@ -248,6 +251,8 @@ def test_split_hot_tiles(ctx):
         e = rel(img[0], ref["raw"][0].real)
         log(f"split hot tiles {prec}: {e:.3e}")
         assert e <= tol
+        if prec != "f64":
+            assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 def test_plane_shards_sum(ctx, config0):

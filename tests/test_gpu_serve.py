@@ -62,7 +62,7 @@ def test_budget_admission(pool):
 
 
 def test_failure_isolated(pool, monkeypatch):
-    monkeypatch.setenv("WSG_FAIL_GRID_N", "1024")
+    monkeypatch.setenv("WSG_SERVER_FAIL_GRID_N", "1024")
     solo512 = {i: _solo(j) for i, j in enumerate(pool) if j.grid_n == 512}
     with wsg.Server(0, 3) as srv:
         tickets = []

@@ -8,7 +8,7 @@ import oracle
 from paper_2411_07321_amd import synth, wsg
 from tests import pinlib
 from tests.gpuutil import (DEV, assert_stats, both_params, cast_inputs, dev, gpu_image, log,
-                           oracle_image, rel)
+                           oracle_image, rel, PEAK32, peak)
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +53,7 @@ def test_config0_w_kernel_f32(ctx, config0, precision):
     e = rel(img[0], ref["raw"][0].real)
     log(f"w kernel S_w=7 config0 {precision}: raw rel err {e:.3e}")
     assert e <= TOL32
+    assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
 @pytest.mark.parametrize("precision,kernel", [("f64", "gauss"), ("f32_phase64", "gauss"),

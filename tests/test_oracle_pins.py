@@ -562,3 +562,54 @@ def test_w_kernel_approaches_the_exact_transform():
     err_no_cw = np.abs(d[q, p] - De).max()
     assert err[7] < 0.1 * err[1]
     assert err[7] < 0.1 * err_no_cw
+
+
+def w_kernel_edge_plane_error(sw):
+    """Largest difference between the oracle's planes and hand-computed ones for the
+    visibilities at the ends of the data's own w range (see test_w_kernel_edge_planes),
+    and the number of planes that hold anything."""
+    n, cell, S, nw = 64, 1.0 / 100, 7, 9
+    hw = (sw - 1) // 2
+    w_lo, w_mid, w_hi = -7.3, 2.0, 11.9
+    # three visibilities on separate cells, so their footprints do not touch
+    uvw = np.array([[-12.25, -8.5, w_lo], [13.5, 9.75, w_hi], [0.5, 0.25, w_mid]])
+    vis = np.array([[0.3 - 0.8j], [1.1 + 0.2j], [-0.4 + 0.5j]])
+    prm = oracle.Params(n, nw, S, cell, SIG, w_support=sw)
+    lo, hi = oracle.w_range(_inputs(uvw, vis), prm)
+    assert (lo, hi) == (w_lo, w_hi)
+    g, cnt = oracle.grid(_inputs(uvw, vis), prm, lo, hi)
+    assert cnt["n_used"] == 3
+    x, y = pinlib.positions(uvw, n, cell)
+    dw = (w_hi - w_lo) / (nw - 2 * hw)
+    expect = {0: (hw, 0.5), 1: (nw - 1 - hw, -0.5)}   # visibility -> (k0, offset of j = 0)
+    err = 0.0
+    for r, (k0, off) in expect.items():
+        i0_, j0 = int(math.floor(x[r] + 0.5)), int(math.floor(y[r] + 0.5))
+        foot = np.outer(pinlib.gauss(j0 + np.arange(-3, 4) - y[r], SIG),
+                        pinlib.gauss(i0_ + np.arange(-3, 4) - x[r], SIG))
+        sl = (slice(j0 - 3, j0 + 4), slice(i0_ - 3, i0_ + 4))
+        for k in range(nw):
+            ref = np.zeros((7, 7), complex)
+            if abs(k - k0) <= hw:
+                # w_k from the geometry written out, as a check of the offset itself
+                wk = w_lo + (k - hw + 0.5) * dw
+                assert abs((wk - uvw[r, 2]) / dw - ((k - k0) + off)) < 1e-12
+                ref = vis[r, 0] * pinlib.gauss((k - k0) + off, SIG) * foot
+            err = max(err, float(np.abs(g[k][sl] - ref).max()))
+    # planes holding anything: every one of the stack, the padding planes holding only
+    # the tails of the edge visibilities
+    return err, int(np.count_nonzero(np.abs(g).reshape(nw, -1).max(1)))
+
+
+@pytest.mark.parametrize("sw", [3, 5])
+def test_w_kernel_edge_planes(sw):
+    """The visibilities at the ends of the data's own w range: the range covers the middle
+    N_w - 2 h_w planes, so the one at w_max lies on the upper edge of plane N_w - h_w and
+    the one at w_min on the lower edge of plane h_w (where rounding may place it one plane
+    lower).  Each must spread over planes k0 - h_w .. k0 + h_w with k0 = N_w - 1 - h_w and
+    k0 = h_w, the kernel's planes staying inside the stack.  Plane geometry by hand:
+    dw = (w_max - w_min)/(N_w - 2 h_w), w_k = w_min + (k - h_w + 1/2) dw, so the offsets
+    (w_k - w)/dw are j - 1/2 at w_max and j + 1/2 at w_min, j = -h_w .. h_w."""
+    err, n_planes = w_kernel_edge_plane_error(sw)
+    assert err < 1e-14
+    assert n_planes == 9

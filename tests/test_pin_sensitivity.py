@@ -101,3 +101,32 @@ def test_fold_without_conjugation_is_caught(config0):
     neg = uvw[:, 2] < 0
     bad = pinlib.exact_dft(np.where(neg[:, None], -uvw, uvw), vis, wts, ds.grid_n, ds.cell_rad, q, p)
     assert np.abs(bad - De).max() > 1e-3 * np.abs(De).max()
+
+
+def _planted_oracle(tmp_path, old: str, new: str):
+    """A copy of the C oracle with one line changed, built with gcc on the CPU."""
+    import subprocess
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "wsg_oracle_planted.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_planted.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared",
+                    "-fPIC", "-o", str(lib), str(path), "-lm"], check=True)
+    return str(lib)
+
+
+def test_w_kernel_edge_clamp_slip_is_caught(tmp_path, monkeypatch):
+    """The clamp that keeps a kernel-in-w visibility's planes inside the stack, planted one
+    plane off (N_w - h_w instead of N_w - 1 - h_w): the edge-plane pin fails."""
+    from tests.test_oracle_pins import w_kernel_edge_plane_error
+    lib = _planted_oracle(tmp_path, "if (k0 > n_w - 1 - hw) k0 = n_w - 1 - hw;",
+                          "if (k0 > n_w - hw) k0 = n_w - hw;")
+    monkeypatch.setattr(oracle, "_LIB_PATH", lib)
+    monkeypatch.setattr(oracle, "_lib", None)
+    try:
+        for sw in (3, 5):
+            err, _ = w_kernel_edge_plane_error(sw)
+            assert err > 1e-2
+    finally:
+        oracle._lib = None
