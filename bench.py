@@ -16,7 +16,11 @@ once by the transform (2 B_grid), the image written once (B_img); binning and
 intermediate passes are implementation overhead and earn nothing.  The gridding
 kernel itself is bound by VALU and LDS atomics, not HBM, and is rated by its
 useful arithmetic (392 flop per visibility: 49 complex multiply-adds) against
-the FP32 vector peak.
+the FP32 vector peak this build can issue (no packed FP32 instructions: 256 CUs x
+4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); the FP64 LDS atomic-add rate
+and the copy bandwidth the device reaches are measured by the library's probes.
+The same JSON line carries the job at the paper's own arithmetic (complex128 mesh
+and transform, FP64 throughout) as "f64_config1".
 """
 from __future__ import annotations
 
@@ -32,7 +36,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector, vendor figure
+FP32_VENDOR_TFLOPS = 157.3     # MI355X FP32 vector, vendor figure (counts packed FP32)
+# FP32 vector issue without packed instructions (the library is built without them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+DTYPE = "c64 mesh+FFT, f64 phase argument with f32 sin/cos, f64 plane sum and image"
 GRID_FLOP_PER_VIS = 392        # 49 complex multiply-adds per visibility
 TILE = 64                      # binning tile of the FP32 mesh (set explicitly)
 STAGES = ("ms_prep", "ms_count", "ms_scatter", "ms_zero", "ms_grid", "ms_occupancy", "ms_fft1",
@@ -94,11 +102,26 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(ds_host: dict, params: dict, n_total: int) -> dict:
     """The FP64 oracle (unchanged) on a bounded sample of the same workload, scaled to the
     whole job: gridding of a row subsample with every measurement on one plane (the
     per-visibility work does not depend on the plane count), plus one plane's transform
-    and w-correction, extrapolated to all visibilities and planes."""
+    and w-correction, extrapolated to all visibilities and planes.  Timed with one
+    thread and with every thread the host gives this process (the oracle's gridding
+    splits the mesh rows over threads; its transform is numpy's, one thread)."""
     import numpy as np
     import oracle
     uvw, vis, wts, freq = ds_host["uvw"], ds_host["vis"], ds_host["weights"], ds_host["freq"]
@@ -107,26 +130,38 @@ def cpu_baseline(ds_host: dict, params: dict, n_total: int) -> dict:
     n = params["grid_n"]
     prm1 = oracle.Params(n, 1, params["support"], params["cell_rad"], params["kernel_sigma"],
                          kernel=params.get("kernel", "gauss"))
-
-    t0 = time.perf_counter()
-    wmin, wmax = oracle.w_range(inp, prm1)
-    g, cnt = oracle.grid(inp, prm1, wmin, wmax)
-    t_grid = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    F = oracle.fft_planes(g)
-    t_fft = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    A = oracle.wcorrect(F, wmin, wmax, 1, params["cell_rad"])
-    D = oracle.post(A, cnt["sum_w"], prm1)
-    t_wc = time.perf_counter() - t0
-    del g, F, A, D
     nw = params["n_wplanes"]
-    t_est = t_grid * (n_total / m_s) + nw * (t_fft + t_wc)
-    return {"value": n_total / t_est, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle, 1 thread: {m_s:,} visibilities (row subsample) gridded on "
-                       f"the {n}^2 mesh in {t_grid:.2f} s, one plane transformed in "
-                       f"{t_fft:.2f} s and w-corrected in {t_wc:.2f} s; extrapolated to "
-                       f"{n_total:,} visibilities and {nw} planes = {t_est:.0f} s per job")}
+    cpu = host_cpu()
+    all_threads = cpu["nproc"]
+    runs = {}
+    for threads in (1, all_threads):
+        oracle.threads(threads)
+        t0 = time.perf_counter()
+        wmin, wmax = oracle.w_range(inp, prm1)
+        g, cnt = oracle.grid(inp, prm1, wmin, wmax)
+        t_grid = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        F = oracle.fft_planes(g)
+        t_fft = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        A = oracle.wcorrect(F, wmin, wmax, 1, params["cell_rad"])
+        D = oracle.post(A, cnt["sum_w"], prm1)
+        t_wc = time.perf_counter() - t0
+        del g, F, A, D
+        t_est = t_grid * (n_total / m_s) + nw * (t_fft + t_wc)
+        runs[threads] = {"value": n_total / t_est, "t_grid": t_grid, "t_fft": t_fft, "t_wc": t_wc,
+                         "t_job_est": t_est}
+        progress(f"oracle, {threads} thread(s): {n_total / t_est:.3e} vis/s")
+    one, full = runs[1], runs[all_threads]
+    return {"value": full["value"], "unit": "visibilities/s", "cores": all_threads, "kind": "oracle",
+            "value_1_thread": one["value"], "host_cpu": cpu,
+            "sample": (f"FP64 oracle on {all_threads} threads ({cpu['model']}; 1 thread: "
+                       f"{one['value']:.3e} vis/s): {m_s:,} visibilities (row subsample) gridded "
+                       f"on the {n}^2 mesh in {full['t_grid']:.2f} s (1 thread {one['t_grid']:.2f} s), "
+                       f"one plane transformed in {full['t_fft']:.2f} s and w-corrected in "
+                       f"{full['t_wc']:.2f} s; extrapolated to {n_total:,} visibilities and {nw} "
+                       f"planes = {full['t_job_est']:.0f} s per job "
+                       f"(1 thread {one['t_job_est']:.0f} s)")}
 
 
 def chunked(args, d, prm, ctx, out):
@@ -176,7 +211,7 @@ def chunked(args, d, prm, ctx, out):
         "metric": "visibilities gridded+imaged/s", "value": n_used / (ms_step * 1e-3),
         "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 mesh+FFT, f64 phase+image",
+        "vs_baseline": None, "dtype": DTYPE,
         "data": "synthetic (seeded, device-generated config-1 interferometer data)",
         "config": {"workload": f"config1_4096sq_64w_2.67e8vis_{len(bounds)}chunks_{where}",
                    "grid_n": d["params"]["grid_n"], "n_wplanes": d["params"]["n_wplanes"],
@@ -190,6 +225,37 @@ def chunked(args, d, prm, ctx, out):
     print(json.dumps(result), flush=True)
 
 
+def f64_job(args, d, n) -> dict:
+    """The same job at the paper's own arithmetic: complex128 visibilities and mesh, FP64
+    transform, phase and image (FP64 weights), binning tile 32 (the library's choice for
+    the FP64 LDS tile).  Its own context; 1 warm-up and 3 timed jobs."""
+    import numpy as np
+    import torch
+    from paper_2411_07321_amd import wsg
+    progress("f64 job: converting inputs")
+    vis = d["vis"].to(torch.complex128)
+    wts = d["weights"].to(torch.float64)
+    prm = wsg.make_params(**{**d["params"], "precision": "f64"})
+    vb = wsg.make_vis(d["uvw"], vis, wts, None, d["freq_hz"], d["row_period"])
+    out = torch.empty((1, n, n), dtype=torch.float64, device=vis.device)
+    with wsg.Context(0) as c:
+        c.set_timing(True)
+        c.image(prm, vb, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [c.image(prm, vb, out)[0] for _ in range(3)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+    del vis, wts
+    torch.cuda.empty_cache()
+    n_used = int(sts[-1]["n_used"])
+    progress(f"f64 job: {ms:.2f} ms/job")
+    return {"ms_per_step": round(ms, 3), "value": n_used / (ms * 1e-3), "unit": "visibilities/s",
+            "dtype": "c128 mesh+FFT, f64 phase and image (the paper's arithmetic)",
+            "tile": int(prm.tile) if prm.tile else 32,
+            "stages_ms": {k: round(float(np.mean([s[k] for s in sts])), 3) for k in STAGES}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +264,8 @@ def main():
     ap.add_argument("--rows-stride", type=int, default=1,
                     help="keep every k-th row (quick runs only; not the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the extra timing of the job at the paper's FP64 arithmetic")
     ap.add_argument("--kernel", choices=("gauss", "kb"), default="gauss",
                     help="gridding kernel: Gaussian (sigma 0.9) or Kaiser-Bessel")
     ap.add_argument("--w-support", type=int, default=1,
@@ -282,12 +350,15 @@ def main():
     if args.w_support > 1:
         workload += f"_w_support{args.w_support}"
     if kname == "k_grid":
-        # VALU / LDS-atomic bound: useful arithmetic per launch over the launch time
+        # VALU / LDS-atomic bound: useful arithmetic per launch over the launch time,
+        # against the FP32 rate without packed instructions
         flops = GRID_FLOP_PER_VIS * n_used
         achieved = flops / (mean[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 2),
-                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "peak": round(FP32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "vendor_peak_packed_fp32": FP32_VENDOR_TFLOPS,
+                "frac_of_vendor_peak": round(achieved / FP32_VENDOR_TFLOPS, 4),
                 "traffic": load_traffic(kname, workload), "avg_ms": round(mean[dom], 3),
                 "alg_flops": flops}
     else:
@@ -306,7 +377,7 @@ def main():
         "metric": "visibilities gridded+imaged/s", "value": n_used / (ms_step * 1e-3),
         "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 mesh+FFT, f64 phase+image",
+        "vs_baseline": None, "dtype": DTYPE,
         "data": "synthetic (seeded, device-generated config-1 interferometer data)",
         "config": {"workload": workload, "grid_n": n, "n_wplanes": d["params"]["n_wplanes"],
                    "support": 7, "visibilities": int(d["vis"].numel()), "n_used": n_used,
@@ -320,6 +391,22 @@ def main():
         "occupancy": {"n_records": job["n_records"], "n_tiles": job["n_tiles"],
                       "n_tile_rows": job["n_tile_rows"]},
     }
+    try:
+        probes = wsg.probe_rates(0, 1 << 31)
+        result["device_probes"] = {
+            "lds_f64_atomic_adds_per_s": probes["lds_f64_adds_per_s"],
+            "copy_GBps": round(probes["copy_bytes_per_s"] / 1e9, 1),
+            "note": "measured by wsg_probe_rates: FP64 LDS atomic adds (no return, no bank "
+                    "conflicts) and a 2 GiB 16-byte streaming copy (read + write bytes)"}
+        result["path_roofline"]["frac_of_measured_copy"] = round(
+            path_gbs / (probes["copy_bytes_per_s"] / 1e9), 4)
+        progress(f"probes: LDS f64 adds {probes['lds_f64_adds_per_s']:.3e}/s, copy "
+                 f"{probes['copy_bytes_per_s'] / 1e9:.0f} GB/s")
+    except wsg.WsgError as e:
+        progress(f"probes failed: {e}")
+    if not args.no_f64:
+        ctx.close()
+        result["f64_config1"] = f64_job(args, d, n)
     if not args.no_cpu_baseline:
         progress("cpu baseline: oracle on a bounded sample")
         k = max(1, d["uvw"].shape[0] // args.cpu_sample_rows)

@@ -70,7 +70,8 @@ enum {
     WSG_ENOMEM = -2,        /* workspace above the context's budget or device memory        */
     WSG_EDEVICE = -3,       /* HIP runtime error (no device, launch failure, ...)           */
     WSG_EBUSY = -4,         /* the context still has enqueued work it must not overlap      */
-    WSG_EUNSUPPORTED = -5   /* valid but outside what this build supports (e.g. N > 4096)   */
+    WSG_EUNSUPPORTED = -5,  /* valid but outside what this build supports (e.g. N > 16384)  */
+    WSG_ECANCELED = -6      /* a submitted job was canceled before it reached the device    */
 };
 
 /* Arithmetic of the mesh, the transform and the phase screen. */
@@ -96,7 +97,7 @@ enum {
 };
 
 typedef struct {
-    int32_t grid_n;        /* N: power of two, 16 .. 4096                                      */
+    int32_t grid_n;        /* N: power of two, 16 .. 16384                                     */
     int32_t n_wplanes;     /* N_w >= 1                                                         */
     int32_t support;       /* S: odd, 1 .. 15, S <= N                                          */
     int32_t precision;     /* WSG_PREC_*                                                       */
@@ -107,7 +108,8 @@ typedef struct {
     int32_t plane_lo;      /* image only planes [plane_lo, plane_hi) of N_w (both 0: all);    */
     int32_t plane_hi;      /*   needs a given w range, so that every shard agrees             */
     uint32_t flags;        /* WSG_GRID_CORRECT | WSG_NORMALIZE | ...                           */
-    int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64     */
+    int32_t tile;          /* uv tile edge for binning: 0 = library choice, else 16/32/64,    */
+                           /*   at least grid_n / 256                                         */
     int32_t kernel;        /* WSG_KERNEL_*                                                     */
     double kernel_beta;    /* Kaiser-Bessel beta (0 .. 64; 0: the default for S, which S = 1  */
                            /*   lacks: WSG_EINVAL).  FP32 meshes take each tap from a fitted   */
@@ -203,6 +205,37 @@ int32_t wsg_n_images(const wsg_params *p, const wsg_vis *v);
  */
 wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
                      double *image, int32_t image_mem, void *stream, wsg_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * The method, asynchronously: jobs submitted to a context
+ * ------------------------------------------------------------------------- */
+/*
+ * wsg_submit validates the job (errors of wsg_check are returned at once) and queues
+ * it; the context runs its submitted jobs one after another, in submission order, on
+ * its own stream (wsg_context_stream), with at most two of them on the device at a
+ * time, so that the host side of the next job overlaps the device work of the
+ * previous one.  Jobs reach the device from wsg_submit, wsg_poll and wsg_wait; nothing
+ * runs in the background.  A job's buffers (inputs, freq_hz excepted: it is copied,
+ * and image) must stay valid until the job is reported done.  A host image makes the
+ * call that puts the job on the device wait for it (the copy out is synchronous).
+ *   wsg_poll: *done = 0 while the job runs; once finished, *done = 1 and the return
+ *             value is the job's own status (stats, NULL or n_images entries, filled
+ *             on success); the ticket is then forgotten.
+ *   wsg_wait: waits for the job, then as wsg_poll with *done = 1.
+ *   wsg_cancel: a job still queued on the host is dropped; wsg_poll / wsg_wait then
+ *             report WSG_ECANCELED.  A job already on the device cannot be canceled
+ *             (WSG_EBUSY); a finished one is left as it is.
+ * Stage times are not measured for submitted jobs (the ms_* fields are 0).  While any
+ * submitted job is unfinished, the other calls on the context (wsg_image, the stages,
+ * the chunked calls, wsg_autotune) fail with WSG_EBUSY.  wsg_destroy drops queued jobs
+ * and waits for those on the device.  An unknown or already reported ticket is
+ * WSG_EINVAL.
+ */
+wsg_status wsg_submit(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                      int32_t image_mem, uint64_t *ticket);
+wsg_status wsg_poll(wsg_ctx *ctx, uint64_t ticket, int32_t *done, wsg_stats *stats);
+wsg_status wsg_wait(wsg_ctx *ctx, uint64_t ticket, wsg_stats *stats);
+wsg_status wsg_cancel(wsg_ctx *ctx, uint64_t ticket);
 
 /* ---------------------------------------------------------------------------
  * Stages, separately (for checking each step)
@@ -315,10 +348,26 @@ wsg_status wsg_server_submit(wsg_server *srv, const wsg_params *p, const wsg_vis
 /* *done = 1 and *info filled once the job has finished (either way). */
 wsg_status wsg_server_poll(wsg_server *srv, uint64_t ticket, int32_t *done, wsg_job_info *info);
 wsg_status wsg_server_wait(wsg_server *srv, uint64_t ticket, wsg_job_info *info);
+/* Drop a job that is still queued (not yet admitted): it is then reported done with
+ * status WSG_ECANCELED.  WSG_EBUSY if a slot already runs it; a finished job is left
+ * as it is. */
+wsg_status wsg_server_cancel(wsg_server *srv, uint64_t ticket);
 /* Current and peak device bytes held by the slots (their workspaces). */
 wsg_status wsg_server_memory(wsg_server *srv, uint64_t *held, uint64_t *peak);
 /* Release the workspace of every idle slot. */
 wsg_status wsg_trim(wsg_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Device probes (measurement of the roofline's peaks; not part of the method)
+ * ------------------------------------------------------------------------- */
+/* Measured on `device` with this library's own kernels, best of three timed launches:
+ *   *lds_f64_adds_per_s: FP64 atomic adds into LDS without a returned value, one
+ *       double per lane, no bank conflicts (the operation of the gridder's flushes);
+ *   *copy_bytes_per_s: bytes read plus written per second by a 16-byte streaming copy
+ *       of copy_bytes bytes (0 skips it; two buffers of that size are allocated).
+ * Outputs may be NULL.  Waits for the device.  WSG_ENOMEM if the buffers do not fit. */
+wsg_status wsg_probe_rates(int device, uint64_t copy_bytes, double *lds_f64_adds_per_s,
+                           double *copy_bytes_per_s);
 
 #ifdef __cplusplus
 }

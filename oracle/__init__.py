@@ -85,6 +85,8 @@ def _load():
                                       ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, P]
         lib.oracle_bessel_i0.restype = ctypes.c_double
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = [ctypes.c_int]
         lib.oracle_bessel_i0.argtypes = [ctypes.c_double]
         lib.oracle_kernel_value.restype = ctypes.c_double
         lib.oracle_kernel_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -415,3 +417,9 @@ def pixels(inp: Inputs, prm: Params, pix_q, pix_p, chan: int = -1) -> np.ndarray
     if rc != 0:
         raise ValueError("oracle_pixels failed")
     return out
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel loops (gridding by row bands, pixel sums); n > 0
+    sets them.  Results do not depend on the count."""
+    return int(_load().oracle_threads(int(n)))

@@ -36,6 +36,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the parallel loops below (n > 0 sets them); returns the count in use. */
+int oracle_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 typedef struct {
     int64_t n_used;     /* measurements that enter the image (all planes)      */
@@ -172,6 +187,10 @@ void oracle_plane_geometry(double w_min, double w_max, int n_w, int w_support, d
  * grid: complex128 interleaved [plane_hi-plane_lo][N][N] (row j, column i),
  * accumulated into (the caller zeroes it).  Only planes in [plane_lo,
  * plane_hi) are gridded; the counts cover every plane.
+ * Threads: the mesh rows are split into one band per thread; every thread walks
+ * all measurements in their order and adds only the footprint rows of its band,
+ * so each cell receives its terms in the same order as with one thread and the
+ * result does not depend on the thread count.
  */
 int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *chan_scale,
                 const double *vis, const double *weights, const uint8_t *flags,
@@ -185,9 +204,17 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
     double w0, dw;
     oracle_plane_geometry(w_min, w_max, n_w, w_support, &w0, &dw);
     int hw = dw == 0.0 ? 0 : (w_support - 1) / 2;
+    if (support > 63) return -1;
+#pragma omp parallel
+    {
+    int band = 0, n_band = 1;
+#ifdef _OPENMP
+    band = omp_get_thread_num();
+    n_band = omp_get_num_threads();
+#endif
+    const int64_t j_lo = (int64_t)n * band / n_band, j_hi = (int64_t)n * (band + 1) / n_band;
     double gx[64], gy[64];
     oracle_counts cnt = {0, 0, 0, 0.0};
-    if (support > 63) return -1;
     for (int64_t r = 0; r < n_rows; ++r) {
         for (int c = 0; c < n_chan; ++c) {
             if (chan >= 0 && c != chan) continue;
@@ -217,6 +244,7 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
             position(u, v, scale, n, &x, &y);
             fits(x, n, h, &i0);
             fits(y, n, h, &j0);
+            if (j0 + h < j_lo || j0 - h >= j_hi) continue;   /* no row of this band */
             for (int a = -h; a <= h; ++a)
                 gx[a + h] = oracle_kernel_value(kernel, kpar, support, (double)(i0 + a) - x);
             for (int b = -h; b <= h; ++b)
@@ -232,6 +260,7 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
                 double wv_im = wt * vis[2 * rc + 1] * gw;
                 double *plane = grid + (size_t)(k - plane_lo) * (size_t)n * (size_t)n * 2;
                 for (int b = -h; b <= h; ++b) {
+                    if (j0 + b < j_lo || j0 + b >= j_hi) continue;
                     double *row = plane + ((size_t)(j0 + b) * (size_t)n) * 2;
                     for (int a = -h; a <= h; ++a) {
                         double g = gx[a + h] * gy[b + h];
@@ -243,7 +272,8 @@ int oracle_grid(int64_t n_rows, int n_chan, const double *uvw, const double *cha
             }
         }
     }
-    if (counts) *counts = cnt;
+    if (band == 0 && counts) *counts = cnt;   /* every band counts every measurement */
+    }
     return 0;
 }
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwsg.so")
-SOURCES = ["k_bin.hip", "k_grid.hip", "k_fft.hip", "wsg_lib.cpp", "wsg_server.cpp"]
+SOURCES = ["k_bin.hip", "k_grid.hip", "k_fft.hip", "k_probe.hip", "wsg_lib.cpp", "wsg_server.cpp"]
 ARCH = os.environ.get("WSG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

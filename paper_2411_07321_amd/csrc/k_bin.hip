@@ -691,14 +691,88 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
     }
 }
 
-__global__ void k_class_totals(const uint32_t *__restrict__ cls_counts, int n_cls, size_t n_bins,
-                               uint32_t *__restrict__ counts) {
+// size class of a work item of n >= 1 records: floor(log2(n))
+__device__ __forceinline__ int item_class(uint32_t n) { return 31 - __clz((int)n); }
+
+// pieces of a bin of cnt records: full pieces of kGridChunk, then the rest
+__device__ __forceinline__ uint32_t bin_pieces(uint32_t cnt) {
+    return (cnt + kGridChunk - 1u) / kGridChunk;
+}
+
+__global__ __launch_bounds__(256) void k_class_totals(const uint32_t *__restrict__ cls_counts,
+                                                      int n_cls, size_t n_bins,
+                                                      uint32_t *__restrict__ counts, WorkTotals *wt) {
+    __shared__ uint32_t s_hist[kItemClasses];
+    if (threadIdx.x < kItemClasses) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n_bins) return;
-    uint32_t t = 0;
-    if (i < n_bins)
-        for (int c = 0; c < n_cls; ++c) t += cls_counts[(size_t)c * n_bins + i];
-    counts[i] = t;   // the entry after the last bin stays 0: its offset is the total
+    if (i <= n_bins) {
+        uint32_t t = 0;
+        if (i < n_bins)
+            for (int c = 0; c < n_cls; ++c) t += cls_counts[(size_t)c * n_bins + i];
+        counts[i] = t;   // the entry after the last bin stays 0: its offset is the total
+        if (t) {
+            const uint32_t np = bin_pieces(t);
+            if (np > 1u) atomicAdd(&s_hist[kItemClasses - 1], np - 1u);
+            atomicAdd(&s_hist[item_class(t - (np - 1u) * kGridChunk)], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kItemClasses && s_hist[threadIdx.x])
+        atomicAdd(&wt->cls_count[threadIdx.x], s_hist[threadIdx.x]);
+}
+
+// Class bases, largest class first; the cursors start at the bases.
+__global__ void k_item_bases(const uint32_t *__restrict__ offsets, size_t n_bins, WorkTotals *wt) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0u;
+    for (int c = kItemClasses - 1; c >= 0; --c) {
+        wt->cls_cursor[c] = run;
+        run += wt->cls_count[c];
+    }
+    wt->n_items = run;
+    wt->n_records = offsets[n_bins];
+    wt->next_item = 0u;
+}
+
+// Every piece of every non-empty bin takes a slot of its class: slots are reserved
+// per workgroup (one global atomic per class) and dealt out through LDS.
+__global__ __launch_bounds__(256) void k_item_place(const uint32_t *__restrict__ counts, size_t n_bins,
+                                                    WorkTotals *wt, uint2 *__restrict__ items) {
+    __shared__ uint32_t s_cnt[kItemClasses], s_base[kItemClasses];
+    if (threadIdx.x < kItemClasses) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t = i < n_bins ? counts[i] : 0u;
+    const uint32_t np = t ? bin_pieces(t) : 0u;
+    const int cl = t ? item_class(t - (np - 1u) * kGridChunk) : 0;
+    uint32_t full_at = 0u, last_at = 0u;
+    if (np > 1u) full_at = atomicAdd(&s_cnt[kItemClasses - 1], np - 1u);
+    if (np) last_at = atomicAdd(&s_cnt[cl], 1u);
+    __syncthreads();
+    if (threadIdx.x < kItemClasses)
+        s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&wt->cls_cursor[threadIdx.x], s_cnt[threadIdx.x])
+                                                 : 0u;
+    __syncthreads();
+    if (!np) return;
+    const uint32_t b = (uint32_t)i;
+    for (uint32_t c = 0; c + 1u < np; ++c)
+        items[s_base[kItemClasses - 1] + full_at + c] = make_uint2(b, c);
+    items[s_base[cl] + last_at] = make_uint2(b, np - 1u);
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_init_state(ImgState *st, int n_img) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_img) return;
+    ImgState z{};
+    z.wmin_key = ~0ull;
+    z.wmax_key = 0ull;
+    st[i] = z;
 }
 
 __global__ void k_class_cursors(const uint32_t *__restrict__ cls_counts, int n_cls, size_t n_bins,
@@ -749,22 +823,6 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t *out, size_t n, const
         if (base + i < n) out[base + i] += add;
 }
 
-__global__ void k_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n, uint32_t chunk) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = counts[i];
-    // an empty bin has no work item: its tile is cleared by the zero pass
-    nchunk[i] = (c + chunk - 1) / chunk;
-}
-
-__global__ void k_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
-                           size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t o = item_off[i];
-    for (uint32_t c = 0; c < nchunk[i]; ++c) item_bin[o + c] = (uint32_t)i;
-}
-
 __global__ void k_post_norm(int n_img, ImgState *st, int normalize) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_img) return;
@@ -809,8 +867,30 @@ void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, cons
 }
 
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
-                         hipStream_t s) {
-    k_class_totals<<<(unsigned)((n_bins + 1 + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, counts);
+                         WorkTotals *wt, hipStream_t s) {
+    k_class_totals<<<(unsigned)((n_bins + 1 + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, counts,
+                                                                        wt);
+}
+
+void launch_item_bases(const uint32_t *offsets, size_t n_bins, WorkTotals *wt, hipStream_t s) {
+    k_item_bases<<<1, 64, 0, s>>>(offsets, n_bins, wt);
+}
+
+void launch_item_place(const uint32_t *counts, size_t n_bins, WorkTotals *wt, uint2 *items,
+                       hipStream_t s) {
+    if (n_bins == 0) return;
+    k_item_place<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(counts, n_bins, wt, items);
+}
+
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    k_fill_u32<<<blocks, 256, 0, s>>>(p, n, v);
+}
+
+void launch_init_state(ImgState *st, int n_img, hipStream_t s) {
+    if (n_img <= 0) return;
+    k_init_state<<<(n_img + 63) / 64, 64, 0, s>>>(st, n_img);
 }
 
 void launch_class_cursors(const uint32_t *cls_counts, int n_cls, size_t n_bins,
@@ -858,16 +938,6 @@ void launch_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp, hip
     k_scan_block<<<(unsigned)nb, 256, 0, s>>>(in, out, n, sums);
     launch_scan(sums, sums_scan, nb, tmp + 2 * nb, s);
     k_scan_add<<<(unsigned)nb, 256, 0, s>>>(out, n, sums_scan);
-}
-
-void launch_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n_bins, uint32_t chunk,
-                   hipStream_t s) {
-    k_chunks<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(counts, nchunk, n_bins, chunk);
-}
-
-void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
-                     size_t n_bins, hipStream_t s) {
-    k_item_map<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(nchunk, item_off, item_bin, n_bins);
 }
 
 void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s) {

@@ -38,28 +38,45 @@ template <typename T> struct BlockRows;
 template <> struct BlockRows<float> { static constexpr int value = 4; };
 template <> struct BlockRows<double> { static constexpr int value = 2; };
 
-// transforms per workgroup: at least B, enough threads for 4 waves when N is small
+// Rows of N >= kBigN points: a workgroup holds at most 1024 threads (one or two
+// rows), and the LDS exchange between stages moves one component at a time (the
+// real parts, then the imaginary ones) through one buffer, as a whole row of
+// complex points would not fit in LDS.
+constexpr int kBigN = 8192;
+
+// transforms per workgroup: at least B, enough threads for 4 waves when N is small,
+// at most 1024 threads
+// B, the rows of a block of the intermediate layout, is BlockRows unless fewer rows
+// fit in one workgroup: pass 1 rewrites a block in place, so all of its rows must be
+// read by one workgroup before any of them is overwritten.
 template <typename T, int N>
 struct Shape {
-    static constexpr int B = BlockRows<T>::value;
     static constexpr int P = N / E;                  // threads per transform
     static constexpr int want = 256 / P;
-    static constexpr int NTR0 = want > B ? want : B;
-    static constexpr int NTR = NTR0 > N ? N : NTR0;  // transforms per workgroup
+    static constexpr int B0 = BlockRows<T>::value;
+    static constexpr int NTR0 = want > B0 ? want : B0;
+    static constexpr int NTR1 = NTR0 > N ? N : NTR0;
+    static constexpr int NTR = NTR1 * P > 1024 ? 1024 / P : NTR1;  // transforms per workgroup
+    static constexpr int B = B0 < NTR ? B0 : NTR;
     static constexpr int THREADS = NTR * P;
     static constexpr int NPAD = N + N / 16;           // LDS row length with padding
+    static constexpr bool SPLIT = N >= kBigN;         // exchange one component at a time
+    static constexpr int LDS_ROWS = SPLIT ? NTR : 2 * NTR;
 };
 
 // pass 2: fewer transforms per workgroup where the FP64 plane sums would not fit in
-// registers next to the points (at most 512 threads for complex64, 256 for complex128)
+// registers next to the points (at most 512 threads for complex64, 256 for complex128,
+// and one row of any N)
 template <typename T, int N>
 struct Shape2 {
-    static constexpr int B = BlockRows<T>::value;
+    static constexpr int B = Shape<T, N>::B;
     static constexpr int P = N / E;
     static constexpr int cap = (sizeof(T) == 4 ? 512 : 256) / P;
     static constexpr int NTR = Shape<T, N>::NTR < cap ? Shape<T, N>::NTR : (cap > 0 ? cap : 1);
     static constexpr int THREADS = NTR * P;
     static constexpr int NPAD = N + N / 16;
+    static constexpr bool SPLIT = N >= kBigN;
+    static constexpr int LDS_ROWS = SPLIT ? NTR : 2 * NTR;
 };
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
@@ -136,7 +153,8 @@ __device__ __forceinline__ void dft_reg(C2<T> *v, int base) {
 // In:  v[m] = X[t + m*P] (m < E).  Out: v[s] = Y[t + s*P].
 // lre/lim: this transform's LDS rows (NPAD elements each).  Every thread of
 // the workgroup must call this together (it contains barriers when N > E).
-template <typename T, int N>
+// SPLIT: lre and lim are one buffer; the components pass through it one after the other.
+template <typename T, int N, bool SPLIT = false>
 __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const C2<T> *__restrict__ tw) {
     constexpr int P = N / E;
     constexpr int R0 = FirstRadix<N>::r;
@@ -149,6 +167,10 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
     int ns = R0;
 #pragma unroll
     for (int st = 1; st < NST; ++st) {
+#pragma unroll
+        for (int comp = 0; comp < (SPLIT ? 2 : 1); ++comp) {
+        // component mask: both at once, or the real (comp 0) then the imaginary parts
+        const bool wr = !SPLIT || comp == 0, wi = !SPLIT || comp == 1;
         __syncthreads();
         if (st == 1) {
 #pragma unroll
@@ -157,8 +179,8 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
 #pragma unroll
                 for (int s = 0; s < R0; ++s) {
                     int idx = lds_pad(j * R0 + s);
-                    lre[idx] = v[u + s * (E / R0)].x;
-                    lim[idx] = v[u + s * (E / R0)].y;
+                    if (wr) lre[idx] = v[u + s * (E / R0)].x;
+                    if (wi) lim[idx] = v[u + s * (E / R0)].y;
                 }
             }
         } else {
@@ -169,15 +191,27 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
 #pragma unroll
             for (int s = 0; s < E; ++s) {
                 int idx = lds_pad(o + s * nsp);
-                lre[idx] = v[s].x;
-                lim[idx] = v[s].y;
+                if (wr) lre[idx] = v[s].x;
+                if (wi) lim[idx] = v[s].y;
             }
         }
         __syncthreads();
+        if constexpr (SPLIT) {
+            // the first round replaces the real parts by their exchanged values; the
+            // imaginary parts stay in their registers, in the old order, for the second
 #pragma unroll
-        for (int s = 0; s < E; ++s) {
-            int idx = lds_pad(t + s * P);
-            v[s] = C2<T>{lre[idx], lim[idx]};
+            for (int s = 0; s < E; ++s) {
+                int idx = lds_pad(t + s * P);
+                if (comp == 0) v[s].x = lre[idx];
+                else v[s].y = lim[idx];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                int idx = lds_pad(t + s * P);
+                v[s] = C2<T>{lre[idx], lim[idx]};
+            }
+        }
         }
         // twiddles e^{+2 pi i (t mod ns) s / (ns E)} = W_N[(t mod ns) * s * N/(ns E)]
         int step = (t % ns) * (N / (ns * E));
@@ -195,13 +229,14 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
                                                                  Occupancy occ) {
     using SH = Shape<T, N>;
     constexpr int B = SH::B, P = SH::P, NTR = SH::NTR;
-    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    __shared__ __align__(16) T lds[SH::LDS_ROWS * SH::NPAD];
     const int tid = threadIdx.x;
     const int r_lo = tid % B;
     const int t = (tid / B) % P;
     const int r_hi = tid / (B * P);
     const int r = r_hi * B + r_lo;
-    const int a = blockIdx.x * NTR + r;
+    const int grp = blockIdx.x;
+    const int a = grp * NTR + r;
     const int pi = blockIdx.y;
     C2<T> *X = planes + (size_t)pi * N * N;
     // sparse stack: a row of an empty tile-row is neither read nor written (pass 2
@@ -213,7 +248,7 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
         const int txr = a >> occ.logT;
         const uint32_t lm = occ.live1[((size_t)pi * NT + txr) * P + t];
         const uint64_t *rows = occ.rows + (size_t)pi * occ.nw;
-        const int a0 = blockIdx.x * NTR;
+        const int a0 = grp * NTR;
         bool any = false;
         for (int tx = a0 >> occ.logT; tx <= (a0 + NTR - 1) >> occ.logT; ++tx)
             any = any || ((rows[tx >> 6] >> (tx & 63)) & 1ull);
@@ -231,8 +266,8 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
         v[m] = z;
     }
     T *lre = lds + (size_t)r * SH::NPAD;
-    T *lim = lds + (size_t)(NTR + r) * SH::NPAD;
-    fft_line<T, N>(v, lre, lim, t, tw);
+    T *lim = SH::SPLIT ? lre : lds + (size_t)(NTR + r) * SH::NPAD;
+    fft_line<T, N, SH::SPLIT>(v, lre, lim, t, tw);
     __syncthreads();   // every load of this region is done before it is overwritten
     C2<T> *Y = X + (size_t)(a / B) * B * N;
     if (row_live) {
@@ -301,14 +336,28 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C
                                                                         const C2<T> *__restrict__ tw) {
     using SH = Shape2<T, N>;
     constexpr int P = SH::P, NTR = SH::NTR;
-    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    __shared__ __align__(16) T lds[SH::LDS_ROWS * SH::NPAD];
     P2Index<T, N> ix(threadIdx.x);
     const int strip = xcd_strip(blockIdx.x, N / NTR);
     const int bcol = strip * NTR + ix.r;
     const C2<T> *Y = in + (size_t)blockIdx.y * N * N;
     C2<T> v[E];
     load_blocked<T, N>(v, Y, ix.t, bcol);
-    fft_line<T, N>(v, lds + (size_t)ix.r * SH::NPAD, lds + (size_t)(NTR + ix.r) * SH::NPAD, ix.t, tw);
+    T *lre = lds + (size_t)ix.r * SH::NPAD;
+    fft_line<T, N, SH::SPLIT>(v, lre, SH::SPLIT ? lre : lds + (size_t)(NTR + ix.r) * SH::NPAD, ix.t, tw);
+    if constexpr (SH::SPLIT) {
+        // one row per workgroup: consecutive threads hold consecutive points, so the
+        // row-major writes are contiguous as they are
+        C2<T> *Z = out + (size_t)blockIdx.y * N * N + (size_t)bcol * N;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            int ap = ix.t + s * P;
+            C2<T> z = v[s];
+            if ((ap + bcol) & 1) z = C2<T>{-z.x, -z.y};
+            Z[ap] = z;
+        }
+        return;
+    }
     // stage through LDS so that the row-major writes are contiguous
     __syncthreads();
     C2<T> *st = (C2<T> *)lds;
@@ -425,6 +474,20 @@ __device__ __forceinline__ double w_transform(const double *__restrict__ cw, int
     return c;
 }
 
+// Layout choices of pass 2 with the w-correction: n - 1 of the workgroup's pixels is
+// kept in an LDS table where it fits next to the exchange buffer, else recomputed per
+// plane; the next plane's points are loaded during the current plane's transform
+// (software pipeline) where the registers allow it (at most 512 threads, N < kBigN).
+template <typename T, int N, int PM>
+struct Wc2 {
+    using SH = Shape2<T, N>;
+    using PR = typename Phase<PM>::R;
+    static constexpr size_t LDS_BYTES = (size_t)SH::LDS_ROWS * SH::NPAD * sizeof(T);
+    static constexpr bool NM1_TABLE = LDS_BYTES + (size_t)SH::NTR * N * sizeof(PR) <= 150 * 1024;
+    static constexpr int NM1_LEN = NM1_TABLE ? SH::NTR * N : 1;
+    static constexpr bool PIPE = SH::THREADS <= 512 && N < kBigN;
+};
+
 template <typename T, int N, bool PH32>
 __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C2<T> *__restrict__ stack,
                                                                         const C2<T> *__restrict__ tw,
@@ -433,76 +496,102 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
     using SH = Shape2<T, N>;
     constexpr int PM = PhaseMode<T, PH32>::value;
     using PR = typename Phase<PM>::R;
+    using WC = Wc2<T, N, PM>;
     constexpr int P = SH::P, NTR = SH::NTR;
-    __shared__ __align__(16) T lds[2 * NTR * SH::NPAD];
+    __shared__ __align__(16) T lds[SH::LDS_ROWS * SH::NPAD];
     // n - 1 of this workgroup's pixels, computed once and read for every plane
-    __shared__ PR s_nm1[NTR * N];
+    __shared__ PR s_nm1[WC::NM1_LEN];
     P2Index<T, N> ix(threadIdx.x);
     const int img = blockIdx.y;
     const int strip = xcd_strip(blockIdx.x, N / NTR);
     const int q = strip * NTR + ix.r;                 // image row handled by this thread
     const ImgState &st = a.st[img];
     const double m = (double)(q - N / 2) * a.cell;
+    auto nm1_of = [&](int s) -> PR {
+        if constexpr (WC::NM1_TABLE) {
+            return s_nm1[ix.r * N + ix.t + s * P];
+        } else {
+            bool in;
+            return Phase<PM>::nm1((double)(ix.t + s * P - N / 2) * a.cell, m, a.naive_nm1, in);
+        }
+    };
+    if constexpr (WC::NM1_TABLE) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-        bool in;
-        const double l = (double)(ix.t + s * P - N / 2) * a.cell;
-        s_nm1[ix.r * N + ix.t + s * P] = Phase<PM>::nm1(l, m, a.naive_nm1, in);
+        for (int s = 0; s < E; ++s) {
+            bool in;
+            const double l = (double)(ix.t + s * P - N / 2) * a.cell;
+            s_nm1[ix.r * N + ix.t + s * P] = Phase<PM>::nm1(l, m, a.naive_nm1, in);
+        }
     }
     double acc[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) acc[s] = 0.0;
     const double w0 = st.w0, dw = st.dw;
-    uint32_t live_next = 0xffffu;
-    if (a.occ.live2 && a.n_pl > 0) live_next = a.occ.live2[(size_t)img * a.n_pl * P + ix.t];
+    // points of rows that pass 1 wrote (all of them for a dense stack; none of a plane
+    // without records, whose transform then only adds zeros), per plane
+    auto live_of = [&](int kl) -> uint32_t {
+        return a.occ.live2 ? (uint32_t)a.occ.live2[((size_t)img * a.n_pl + kl) * P + ix.t] : 0xffffu;
+    };
     T *lre = lds + (size_t)ix.r * SH::NPAD;
-    T *lim = lds + (size_t)(NTR + ix.r) * SH::NPAD;
+    T *lim = SH::SPLIT ? lre : lds + (size_t)(NTR + ix.r) * SH::NPAD;
+    // software pipeline: the points of plane kl + 1 are loaded while plane kl is
+    // transformed (the loads count on the vector-memory counter, the exchanges of the
+    // transform on the LDS counter, so neither waits for the other); the mask of plane
+    // kl + 2 is fetched one step earlier still
+    C2<T> vn[WC::PIPE ? E : 1];
+    uint32_t live_next = a.n_pl > 1 ? live_of(1) : 0u;
+    if constexpr (WC::PIPE)
+        if (a.n_pl > 0) load_blocked_live<T, N>(vn, stack + (size_t)img * a.n_pl * N * N, ix.t, q, live_of(0), tw);
     for (int kl = 0; kl < a.n_pl; ++kl) {
         const int k = a.plane_lo + kl;
         const double wk = (dw == 0.0) ? w0 : w0 + ((double)k + 0.5) * dw;
         const size_t pi = (size_t)img * a.n_pl + kl;
-        const C2<T> *Y = stack + pi * N * N;
-        // points of rows that pass 1 wrote (all of them for a dense stack; none of a
-        // plane without records, whose transform then only adds zeros).  The mask
-        // of the next plane is fetched now, so that the loads of this iteration
-        // wait on nothing.
-        uint32_t live = 0xffffu;
-        if (a.occ.live2) {
-            live = live_next;
-            if (kl + 1 < a.n_pl) live_next = a.occ.live2[(pi + 1) * P + ix.t];
-        }
         C2<T> v[E];
-        load_blocked_live<T, N>(v, Y, ix.t, q, live, tw);
-        fft_line<T, N>(v, lre, lim, ix.t, tw);
-        // (n - 1 comes from LDS: holding it for all E pixels in registers would not
-        // fit next to the points and the FP64 sums)
+        if constexpr (WC::PIPE) {
+#pragma unroll
+            for (int mm = 0; mm < E; ++mm) v[mm] = vn[mm];
+            if (kl + 1 < a.n_pl) {
+                const uint32_t live = live_next;
+                if (kl + 2 < a.n_pl) live_next = live_of(kl + 2);
+                load_blocked_live<T, N>(vn, stack + (pi + 1) * N * N, ix.t, q, live, tw);
+            }
+        } else {
+            load_blocked_live<T, N>(v, stack + pi * N * N, ix.t, q, live_of(kl), tw);
+        }
+        fft_line<T, N, SH::SPLIT>(v, lre, lim, ix.t, tw);
+        // (n - 1 comes from LDS or is recomputed: holding it for all E pixels in
+        // registers would not fit next to the points and the FP64 sums)
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            const PR nm1 = s_nm1[ix.r * N + ix.t + s * P];
+            const PR nm1 = nm1_of(s);
             typename std::conditional<PM == 0, double, float>::type c, sn;
             Phase<PM>::screen(nm1, wk, c, sn);
             acc_re(acc[s], v[s], c, sn);
         }
     }
-    // post factors and the output sign (-1)^(p+q); stage through LDS for
-    // contiguous row writes
+    // post factors and the output sign (-1)^(p+q); stage through LDS for contiguous
+    // row writes (with one row per workgroup, consecutive threads already hold
+    // consecutive pixels)
     const double inv_row = st.inv_norm * (a.inv_c ? a.inv_c[q] : 1.0);
-    __syncthreads();
+    constexpr bool STAGE = WC::LDS_BYTES >= (size_t)NTR * N * sizeof(double) && NTR > 1;
+    if constexpr (STAGE) __syncthreads();
     double *stg = (double *)lds;
+    double *D = image + (size_t)img * N * N + (size_t)strip * NTR * N;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         int p = ix.t + s * P;
         const double l = (double)(p - N / 2) * a.cell;
         const bool inside = l * l + m * m < 1.0;
         double d = inside ? acc[s] * inv_row * (a.inv_c ? a.inv_c[p] : 1.0) : 0.0;
-        if (a.cw && inside && dw > 0.0)
-            d /= w_transform<PM>(a.cw, a.n_cw, dw * (double)s_nm1[ix.r * N + p]);
+        if (a.cw && inside && dw > 0.0) d /= w_transform<PM>(a.cw, a.n_cw, dw * (double)nm1_of(s));
         if ((p + q) & 1) d = -d;
-        stg[ix.r * N + p] = d;
+        if constexpr (STAGE) stg[ix.r * N + p] = d;
+        else D[(size_t)ix.r * N + p] = d;
     }
-    __syncthreads();
-    double *D = image + (size_t)img * N * N + (size_t)strip * NTR * N;
-    for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = stg[i];
+    if constexpr (STAGE) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = stg[i];
+    }
 }
 
 // ---------------------------------------------------------------- w-correction alone
@@ -573,11 +662,10 @@ void pass2_wcorr_n(const WcorrArgs &a, const void *stack, const void *tw, double
         k_pass2_wcorr<T, N, false><<<grid, SH::THREADS, 0, s>>>((const C2<T> *)stack, (const C2<T> *)tw, a, image);
 }
 
-#define WSG_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define WSG_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
 
 }  // namespace
 
-int fft_block_rows(bool f64) { return f64 ? BlockRows<double>::value : BlockRows<float>::value; }
 
 void launch_fft_pass1(int N, bool f64, void *planes, int64_t n_planes, const void *twiddle,
                       const Occupancy &occ, hipStream_t s) {

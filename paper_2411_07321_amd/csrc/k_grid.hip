@@ -143,24 +143,35 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
 // (Variants that add the whole footprint from one base address, inside the tile
 // or into an LDS apron, measured slower: bursts of 98 back-to-back FP64 LDS
 // atomics, and an apron that leaves room for one workgroup per CU.)
+//
+// The launch is persistent: each workgroup takes the next item of the work list
+// (largest items first) until the list is exhausted, so the count of items never
+// has to come back to the host.
 template <typename T, int TT, int SS, bool ACC, int KIND>
 __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t *__restrict__ counts,
                                                         const uint32_t *__restrict__ offsets,
-                                                        const uint32_t *__restrict__ item_off,
-                                                        const uint32_t *__restrict__ item_bin,
-                                                        uint32_t chunk,
+                                                        const uint2 *__restrict__ items,
+                                                        WorkTotals *wt,
                                                         const typename RecTraits<T>::Rec *__restrict__ rec,
                                                         C2<T> *__restrict__ grid, int transposed,
                                                         int accumulate) {
     constexpr int TP = TT + 1;
     constexpr int H = (SS - 1) / 2;
+    constexpr uint32_t chunk = kGridChunk;
     // the tile sums many contributions per cell: kept in FP64 for every mesh type,
     // rounded once when the cell is stored
     __shared__ double s_re[TT * TP];
     __shared__ double s_im[TT * TP];
-    const uint32_t item = blockIdx.x;
-    const uint32_t b = item_bin[item];
-    const uint32_t c = item - item_off[b];
+    __shared__ uint32_t s_item;
+    const uint32_t n_items = wt->n_items;
+    for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&wt->next_item, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= n_items) break;   // the same for every thread of the workgroup
+    const uint2 it = items[item];
+    const uint32_t b = it.x;
+    const uint32_t c = it.y;
     const uint32_t cnt = counts[b];
     // add into the stack (a split bin, or a stack that holds earlier chunks)
     const bool split = accumulate || cnt > chunk;
@@ -355,6 +366,9 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             grid[idx] = C2<T>{vr, vi};
         }
     }
+    // every read of the tile and of s_item is done before the next item clears them
+    __syncthreads();
+    }
 }
 
 template <typename T, int TT>
@@ -431,24 +445,22 @@ __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__
 }
 
 template <typename T, int TT, int SS>
-void launch_tile(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
-                 const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
-                 uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
+void launch_tile(const JobGeom &g, unsigned n_wg, hipStream_t s, const uint32_t *counts,
+                 const uint32_t *offsets, const uint2 *items, WorkTotals *wt,
+                 const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
     constexpr bool ACC = (sizeof(T) == 4) && SS <= 7;
     if (g.kernel == 1)
-        k_grid<T, TT, SS, ACC, 1><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
-                                                                chunk, r, gp, tr, acc);
+        k_grid<T, TT, SS, ACC, 1><<<n_wg, kGridThreads, 0, s>>>(g, counts, offsets, items, wt, r, gp, tr, acc);
     else
-        k_grid<T, TT, SS, ACC, 0><<<grid, kGridThreads, 0, s>>>(g, counts, offsets, item_off, item_bin,
-                                                                chunk, r, gp, tr, acc);
+        k_grid<T, TT, SS, ACC, 0><<<n_wg, kGridThreads, 0, s>>>(g, counts, offsets, items, wt, r, gp, tr, acc);
 }
 
 template <typename T, int TT>
-void launch_support(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *counts,
-                    const uint32_t *offsets, const uint32_t *item_off, const uint32_t *item_bin,
-                    uint32_t chunk, const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
+void launch_support(const JobGeom &g, unsigned n_wg, hipStream_t s, const uint32_t *counts,
+                    const uint32_t *offsets, const uint2 *items, WorkTotals *wt,
+                    const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
     switch (g.S) {
-#define WSG_S(ss) case ss: launch_tile<T, TT, ss>(g, grid, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
+#define WSG_S(ss) case ss: launch_tile<T, TT, ss>(g, n_wg, s, counts, offsets, items, wt, r, gp, tr, acc); break;
     WSG_S(1) WSG_S(3) WSG_S(5) WSG_S(7) WSG_S(9) WSG_S(11) WSG_S(13) WSG_S(15)
 #undef WSG_S
     default: break;
@@ -457,18 +469,16 @@ void launch_support(const JobGeom &g, dim3 grid, hipStream_t s, const uint32_t *
 
 template <typename T>
 void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
-                   const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
-                   uint32_t chunk, const void *records, void *grid, bool transposed,
-                   bool accumulate, hipStream_t s) {
+                   const uint2 *items, WorkTotals *wt, unsigned n_wg, const void *records,
+                   void *grid, bool transposed, bool accumulate, hipStream_t s) {
     using Rec = typename RecTraits<T>::Rec;
     const Rec *r = (const Rec *)records;
     C2<T> *gp = (C2<T> *)grid;
     int tr = transposed ? 1 : 0, acc = accumulate ? 1 : 0;
-    dim3 gd(n_items);
     switch (g.T) {
-    case 16: launch_support<T, 16>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
-    case 32: launch_support<T, 32>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
-    case 64: launch_support<T, 64>(g, gd, s, counts, offsets, item_off, item_bin, chunk, r, gp, tr, acc); break;
+    case 16: launch_support<T, 16>(g, n_wg, s, counts, offsets, items, wt, r, gp, tr, acc); break;
+    case 32: launch_support<T, 32>(g, n_wg, s, counts, offsets, items, wt, r, gp, tr, acc); break;
+    case 64: launch_support<T, 64>(g, n_wg, s, counts, offsets, items, wt, r, gp, tr, acc); break;
     default: break;
     }
 }
@@ -508,7 +518,7 @@ namespace {
 // Chunks are folded in call order, so the FP64 weight sum is deterministic.
 __global__ void k_accum_chunk(const uint32_t *__restrict__ counts, uint32_t *__restrict__ seen,
                               size_t n_bins, const ImgState *__restrict__ st, ImgState *acc, int n_img,
-                              const uint32_t *__restrict__ overflow, uint32_t *acc_overflow) {
+                              const WorkTotals *__restrict__ wt, uint32_t *acc_totals) {
     for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins;
          b += (size_t)gridDim.x * blockDim.x)
         if (counts[b] != 0u) seen[b] = 1u;
@@ -524,7 +534,12 @@ __global__ void k_accum_chunk(const uint32_t *__restrict__ counts, uint32_t *__r
             acc[i].w0 = st[i].w0;
             acc[i].inv_dw = st[i].inv_dw;
         }
-        acc_overflow[0] += overflow[0];
+        // acc_totals: [0] scatter overflow, [1..2] records of all chunks (low, high word)
+        acc_totals[0] += wt->overflow;
+        const unsigned long long r =
+            ((unsigned long long)acc_totals[2] << 32 | acc_totals[1]) + wt->n_records;
+        acc_totals[1] = (uint32_t)r;
+        acc_totals[2] = (uint32_t)(r >> 32);
     }
 }
 
@@ -538,24 +553,33 @@ void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, 
 }
 
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
-                 const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
-                 uint32_t chunk, const void *records, void *grid, bool transposed,
-                 bool accumulate, hipStream_t s) {
-    if (n_items == 0) return;
+                 const uint2 *items, WorkTotals *wt, unsigned n_wg, const void *records, void *grid,
+                 bool transposed, bool accumulate, hipStream_t s) {
+    if (n_wg == 0) return;
     if (f64)
-        dispatch_grid<double>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
-                              transposed, accumulate, s);
+        dispatch_grid<double>(g, counts, offsets, items, wt, n_wg, records, grid, transposed, accumulate, s);
     else
-        dispatch_grid<float>(g, counts, offsets, item_off, item_bin, n_items, chunk, records, grid,
-                             transposed, accumulate, s);
+        dispatch_grid<float>(g, counts, offsets, items, wt, n_wg, records, grid, transposed, accumulate, s);
+}
+
+// Resident workgroups per CU: the FP64 LDS tile, 2 x T x (T+1) x 8 bytes, limits them
+// (two for T = 64, eight for T <= 32, with four waves each); a launch of that many
+// per CU keeps every CU busy until the list runs dry.
+unsigned grid_workgroups(bool f64, int T, size_t max_items, int n_cu) {
+    (void)f64;
+    const size_t lds = 2u * (size_t)T * (T + 1) * 8u + 64u;
+    size_t per_cu = std::min<size_t>((size_t)(160 * 1024) / lds, 8);
+    per_cu = std::max<size_t>(per_cu, 1);
+    const size_t want = per_cu * (size_t)std::max(n_cu, 1);
+    return (unsigned)std::min(want, std::max<size_t>(max_items, 1));
 }
 
 void launch_accum_chunk(const uint32_t *counts, uint32_t *seen, size_t n_bins, const ImgState *st,
-                        ImgState *acc, int n_img, const uint32_t *overflow, uint32_t *acc_overflow,
+                        ImgState *acc, int n_img, const WorkTotals *wt, uint32_t *acc_totals,
                         hipStream_t s) {
     const unsigned blocks = (unsigned)std::min<size_t>((n_bins + 255) / 256, 65535);
-    k_accum_chunk<<<std::max(blocks, 1u), 256, 0, s>>>(counts, seen, n_bins, st, acc, n_img, overflow,
-                                                       acc_overflow);
+    k_accum_chunk<<<std::max(blocks, 1u), 256, 0, s>>>(counts, seen, n_bins, st, acc, n_img, wt,
+                                                       acc_totals);
 }
 
 }  // namespace wsg

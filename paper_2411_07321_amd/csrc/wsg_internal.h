@@ -9,7 +9,7 @@
 namespace wsg {
 
 constexpr double kSpeedOfLight = 299792458.0;
-constexpr int kMaxN = 4096;
+constexpr int kMaxN = 16384;
 constexpr int kMinN = 16;
 constexpr int kMaxSupport = 15;
 
@@ -156,20 +156,42 @@ void launch_finalize_range(const JobGeom &g, ImgState *st, hipStream_t s);
 // records per (image, plane, tile) bin, per atomic class
 void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, const ImgState *st,
                   uint32_t *cls_counts, int n_cls, hipStream_t s);
-// counts[bin] = sum over classes (counts[n_bins] = 0)
+// Gridding work list.  A work item is one non-empty bin, or one piece of `chunk`
+// records of a bin holding more.  Items are listed largest first by size class
+// (floor(log2(records of the item)), kItemClasses classes as items hold at most
+// kGridChunk = 2^15 records), so that the persistent gridder starts the longest items
+// first and the end of its launch is not held up by one late large tile.  Everything
+// here is built on the device: the job needs no host round trip between binning and
+// gridding.
+constexpr uint32_t kGridChunk = 32768;
+constexpr int kItemClasses = 16;
+struct WorkTotals {
+    uint32_t n_records;                  // records of the job (the last bin offset)
+    uint32_t n_items;                    // work items in the list
+    uint32_t next_item;                  // queue head of the persistent gridder
+    uint32_t overflow;                   // scatter slots beyond the record buffer (must stay 0)
+    uint32_t cls_count[kItemClasses];    // items per size class
+    uint32_t cls_cursor[kItemClasses];   // placement cursors, then ends of the classes
+};
+// counts[bin] = sum over classes (counts[n_bins] = 0), and the item count of every
+// size class into wt->cls_count (which must start at 0)
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
-                         hipStream_t s);
+                         WorkTotals *wt, hipStream_t s);
+// class bases (largest class first), n_items, n_records = offsets[n_bins], queue head 0
+void launch_item_bases(const uint32_t *offsets, size_t n_bins, WorkTotals *wt, hipStream_t s);
+// items[slot] = (bin, piece) for every piece of every non-empty bin
+void launch_item_place(const uint32_t *counts, size_t n_bins, WorkTotals *wt, uint2 *items,
+                       hipStream_t s);
+// fill n words with v (a kernel, not a memset node, so the job can be captured in a graph)
+void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+// ImgState of n_img images at the start of a job: empty w range keys, zero counters
+void launch_init_state(ImgState *st, int n_img, hipStream_t s);
 // cls_cursor[c][bin] = offsets[bin] + records of classes < c in the bin
 void launch_class_cursors(const uint32_t *cls_counts, int n_cls, size_t n_bins,
                           const uint32_t *offsets, uint32_t *cls_cursor, hipStream_t s);
 // exclusive scan of n entries (u32) into out; tmp holds >= scan_tmp_elems(n) u32
 size_t scan_tmp_elems(size_t n);
 void launch_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp, hipStream_t s);
-// chunks per bin for the gridding work list, then item -> bin map
-void launch_chunks(const uint32_t *counts, uint32_t *nchunk, size_t n_bins, uint32_t chunk,
-                   hipStream_t s);
-void launch_item_map(const uint32_t *nchunk, const uint32_t *item_off, uint32_t *item_bin,
-                     size_t n_bins, hipStream_t s);
 // records beyond `capacity` are not written; each such slot increments *overflow
 void launch_scatter(const JobGeom &g, const double *uvw, const void *vis, const void *wts,
                     bool f64, const uint8_t *mask, const ImgState *st, uint32_t *cls_cursor,
@@ -204,15 +226,18 @@ void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, 
 void launch_zero_tiles(const JobGeom &g, bool f64, const uint32_t *counts, uint32_t chunk,
                        bool zero_empty, void *grid, bool transposed, hipStream_t s);
 // accumulate: every tile is added into `grid` (which holds earlier chunks) instead
-// of stored; otherwise single-item tiles are stored and split ones added
+// of stored; otherwise single-item tiles are stored and split ones added.
+// n_wg persistent workgroups take the items of the work list in order from
+// wt->next_item until wt->n_items (both on the device).
 void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint32_t *offsets,
-                 const uint32_t *item_off, const uint32_t *item_bin, uint32_t n_items,
-                 uint32_t chunk, const void *records, void *grid, bool transposed,
-                 bool accumulate, hipStream_t s);
+                 const uint2 *items, WorkTotals *wt, unsigned n_wg, const void *records,
+                 void *grid, bool transposed, bool accumulate, hipStream_t s);
+// workgroups of the persistent gridder worth launching for at most max_items items
+unsigned grid_workgroups(bool f64, int T, size_t max_items, int n_cu);
 // chunked jobs: seen[bin] = 1 where the chunk has records; counts, weight sum and
 // plane geometry of the chunk's state folded into acc; overflow counters summed
 void launch_accum_chunk(const uint32_t *counts, uint32_t *seen, size_t n_bins, const ImgState *st,
-                        ImgState *acc, int n_img, const uint32_t *overflow, uint32_t *acc_overflow,
+                        ImgState *acc, int n_img, const WorkTotals *wt, uint32_t *acc_totals,
                         hipStream_t s);
 
 // transforms.  Pass 1: rows of planes [n][N][N] (in place) into the blocked
@@ -252,6 +277,10 @@ void launch_wcorrect(const WcorrArgs &a, bool f64, const void *planes, double *i
 // transpose each N x N complex plane (for the row-major stage entry point)
 void launch_transpose(int N, bool f64, const void *in, void *out, int64_t n_planes,
                       hipStream_t s);
-int fft_block_rows(bool f64);   // B of the blocked layout
+
+// device probes (k_probe.hip)
+void launch_probe_lds_add(int blocks, int iters, double *out, hipStream_t s);
+int probe_lds_add_threads();
+void launch_probe_copy(const void *in, void *out, size_t bytes, int n_cu, hipStream_t s);
 
 }  // namespace wsg

@@ -1,11 +1,13 @@
 // Host side of the w-stacking library: the C ABI of include/wsg.h.
 //
-// A job runs as one chain of kernels on one stream:
-//   [H2D of host inputs] -> prep -> finalize -> count -> scan -> (read the
-//   record total: the only host wait inside a job) -> scatter -> grid ->
-//   transform pass 1 -> transform pass 2 + w-correction + post -> [D2H]
-// Workspace lives in two device arenas per context that only grow, so a
-// steady stream of jobs allocates nothing after the first of its size.
+// A job runs as one chain of kernels on one stream, with no host wait inside:
+//   [H2D of host inputs] -> prep -> finalize -> count -> scan -> work list ->
+//   scatter -> grid (persistent, largest items first) -> transform pass 1 ->
+//   transform pass 2 + w-correction + post -> [D2H]
+// The record buffer is sized for the worst case (four tiles per visibility and
+// plane), so nothing the counting pass finds has to come back to the host.
+// Workspace lives in one device arena per context that only grows, so a steady
+// stream of jobs allocates nothing after the first of its size.
 #include "wsg_internal.h"
 #include "../../include/wsg.h"
 
@@ -14,7 +16,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -25,7 +29,7 @@ using namespace wsg;
 
 namespace {
 
-constexpr uint32_t kChunk = 32768;       // records per gridding work item
+constexpr uint32_t kChunk = kGridChunk;  // records per gridding work item
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -42,16 +46,32 @@ struct DevBuf {
 
 }  // namespace
 
+namespace {
+// A job submitted to a context (wsg_submit): queued on the host, then enqueued on the
+// context's stream, then finished.
+struct AsyncJob;
+// Pinned landing place of one enqueued job's totals and states, and its end event.
+struct AsyncSlot {
+    void *pin = nullptr;
+    size_t size = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+};
+constexpr int kAsyncDepth = 2;   // jobs of one context on the device at a time
+}  // namespace
+
 struct wsg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;
     uint64_t budget = 0;
-    Arena fixed, dyn;
+    Arena fixed;
+    int n_cu = 256;                      // compute units of the device
     // cached tables
     std::map<std::pair<int, int>, DevBuf> twiddles;                       // (N, f64)
     std::map<std::tuple<int, int, int, double>, DevBuf> inv_c;            // (N, S, kernel, shape)
     std::map<std::pair<int, double>, DevBuf> kb;                          // (S, beta)
+    std::map<std::tuple<int, int, double>, DevBuf> cw;                    // (S_w, kernel, shape)
     // device blocks of the last finished chunked job (w-stack block and the two
     // chunk slots), handed to the next one so that a stream of chunked jobs does
     // not allocate
@@ -65,6 +85,10 @@ struct wsg_ctx {
     // stage timing: events recorded at the stage boundaries of wsg_image
     int timing = 0;
     hipEvent_t tev[10] = {};
+    // submitted jobs (wsg_submit), oldest first, until reported by wsg_poll / wsg_wait
+    std::deque<std::shared_ptr<AsyncJob>> async_jobs;
+    uint64_t next_ticket = 1;
+    AsyncSlot aslot[kAsyncDepth];
     hipStream_t last_stream = nullptr;   // stream of the previous call (arena users);
     bool has_last = false;               // NULL is a real stream (the null stream)
 };
@@ -223,10 +247,18 @@ double kb_beta_w(const wsg_params *p) {
     return kb_beta(&q);
 }
 
+// smallest tile edge for a mesh of N cells: at most 256 tiles per axis
+int min_tile(int N) { return std::max(16, N / 256); }
+
+int default_tile(const wsg_params *p) {
+    int t = std::max(f64_mode(p) ? 32 : 64, min_tile(p->grid_n));
+    return std::min(t, p->grid_n);
+}
+
 wsg_status check_params(const wsg_params *p, std::string &why) {
     if (!p) { why = "params is NULL"; return WSG_EINVAL; }
     if (!is_pow2(p->grid_n) || p->grid_n < 4) { why = "grid_n must be a power of two"; return WSG_EINVAL; }
-    if (p->grid_n < kMinN || p->grid_n > kMaxN) { why = "grid_n outside 16..4096"; return WSG_EUNSUPPORTED; }
+    if (p->grid_n < kMinN || p->grid_n > kMaxN) { why = "grid_n outside 16..16384"; return WSG_EUNSUPPORTED; }
     if (p->n_wplanes < 1) { why = "n_wplanes < 1"; return WSG_EINVAL; }
     if (p->support < 1 || (p->support % 2) == 0 || p->support > p->grid_n) {
         why = "support must be odd, >= 1 and <= grid_n";
@@ -294,6 +326,8 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
         }
         // the LDS tile holds FP64 sums: 64 x 64 cells is the largest that fits
         if (p->tile == 128) { why = "tile 128 does not fit the FP64 LDS tile"; return WSG_EUNSUPPORTED; }
+        // the tile bitmaps of a plane hold at most 256 x 256 tiles
+        if (p->tile < min_tile(p->grid_n)) { why = "tile below grid_n / 256"; return WSG_EUNSUPPORTED; }
     }
     return WSG_OK;
 }
@@ -322,16 +356,12 @@ wsg_status check_vis(const wsg_params *p, const wsg_vis *v, std::string &why) {
     int n_img = n_images(p, v);
     int n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
     if ((size_t)n_img * n_pl > 65535) { why = "more than 65535 planes in one stack"; return WSG_EUNSUPPORTED; }
-    int tile = p->tile ? p->tile : std::min(f64_mode(p) ? 32 : 64, p->grid_n);
+    int tile = p->tile ? p->tile : default_tile(p);
     size_t nt = (size_t)(p->grid_n / tile);
     if ((size_t)n_img * n_pl * nt * nt > ((size_t)1 << 27)) { why = "more than 2^27 (plane, tile) bins"; return WSG_EUNSUPPORTED; }
     return WSG_OK;
 }
 
-int default_tile(const wsg_params *p) {
-    int t = f64_mode(p) ? 32 : 64;
-    return std::min(t, p->grid_n);
-}
 
 int decade(int64_t n) {
     int d = 0;
@@ -348,10 +378,10 @@ struct Plan {
     size_t vis_sz, wt_sz;
     // byte offsets in the fixed arena
     size_t o_uvw, o_vis, o_wts, o_flags, o_scale, o_mask, o_state, o_counts, o_offsets,
-        o_cursor, o_nchunk, o_itemoff, o_scan, o_tot, o_occ_rows, o_occ_live1, o_occ_live2,
+        o_cursor, o_scan, o_wt, o_items, o_records, o_occ_rows, o_occ_live1, o_occ_live2,
         o_stack, o_image,
         o_aux, fixed_bytes;
-    size_t records_est, items_est;
+    size_t max_records, max_items;
     int64_t P, n_t, n_tb, n_stretch;   // binning traversal (see JobGeom)
     int n_cls;                         // atomic classes of the binning passes
     size_t o_cls_counts;
@@ -392,10 +422,13 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
     pl.n_cls = binning_classes(pl.n_bins);
     pl.o_cls_counts = take((size_t)pl.n_cls * pl.n_bins * 4);
     pl.o_cursor = take((size_t)pl.n_cls * pl.n_bins * 4);
-    pl.o_nchunk = take(nb1 * 4);
-    pl.o_itemoff = take(nb1 * 4);
     pl.o_scan = take(scan_tmp_elems(nb1) * 4);
-    pl.o_tot = take(16);
+    pl.o_wt = take(sizeof(WorkTotals));
+    // worst case: every visibility touches four tiles on each plane of the kernel in w
+    pl.max_records = (size_t)max_records(p, pl.n_elem);
+    pl.max_items = pl.n_bins + pl.max_records / kChunk + 1;
+    pl.o_items = take(pl.max_items * sizeof(uint2));
+    pl.o_records = take(pl.max_records * (pl.f64 ? sizeof(RecF64) : sizeof(RecF32)));
     pl.P = (v->row_period > 1 && v->row_period <= pl.n_rows) ? v->row_period : 1;
     pl.n_t = pl.n_rows > 0 ? (pl.n_rows + pl.P - 1) / pl.P : 0;
     pl.n_tb = (pl.n_t + kStretch - 1) / kStretch;
@@ -411,25 +444,16 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
     }
     pl.o_aux = take(0);
     pl.fixed_bytes = off;
-    double rep = (double)(tile + pl.S - 1) / tile;
-    pl.records_est = (size_t)((double)pl.n_elem * rep * rep * (2 * w_half(p) + 1)) + 1024;
-    pl.items_est = pl.n_bins + pl.records_est / kChunk + 1;
     return pl;
-}
-
-size_t rec_size(bool f64) { return f64 ? sizeof(RecF64) : sizeof(RecF32); }
-
-size_t dyn_bytes(const Plan &pl, size_t records, size_t items) {
-    return align_up(records * rec_size(pl.f64)) + align_up(items * 4);
 }
 
 // Grow an arena (never shrinks here).  The old block is released and the new one
 // allocated in stream order on `s`, so other contexts' work is not waited for;
 // work of this context on other streams is finished first.
-wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, size_t other_in_use, hipStream_t s) {
+wsg_status ensure_arena(wsg_ctx *ctx, Arena &a, size_t bytes, hipStream_t s) {
     if (bytes <= a.size) return WSG_OK;
-    if (ctx->budget && bytes + other_in_use > ctx->budget)
-        return fail(ctx, WSG_ENOMEM, "workspace of " + std::to_string(bytes + other_in_use) +
+    if (ctx->budget && bytes > ctx->budget)
+        return fail(ctx, WSG_ENOMEM, "workspace of " + std::to_string(bytes) +
                                          " bytes exceeds the context budget");
     if (ctx->has_last && ctx->last_stream != s) WSG_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
     if (a.ptr) {
@@ -491,66 +515,163 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
     }
 }
 
-wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const double **out) {
-    *out = nullptr;
-    if (!(p->flags & WSG_GRID_CORRECT)) return WSG_OK;
-    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
-    const double shape = kb ? kb_beta(p) : p->kernel_sigma;
-    auto key = std::make_tuple(p->grid_n, p->support, (int)p->kernel, shape);
-    auto it = ctx->inv_c.find(key);
-    if (it == ctx->inv_c.end()) {
-        // C(nu) = int_{-S/2}^{S/2} G(d) cos(2 pi nu d) dd by 64-point Gauss-Legendre
-        // quadrature (both kernels are analytic on the support)
-        int N = p->grid_n;
-        std::vector<double> xs, ws;
-        gauss_legendre(64, xs, ws);
-        double a = p->support / 2.0, s2 = 2.0 * p->kernel_sigma * p->kernel_sigma;
-        const double i0b = kb ? bessel_i0(shape) : 1.0;
-        const double two_pi = 6.283185307179586476925286766559;
-        std::vector<double> gk(xs.size());
-        for (size_t k = 0; k < xs.size(); ++k) {
-            double d = a * xs[k];
-            gk[k] = kb ? kb_exact(p->support, shape, i0b, d) : std::exp(-d * d / s2);
-        }
-        std::vector<double> h(N);
-        for (int i = 0; i < N; ++i) {
-            double nu = (double)(i - N / 2) / N;
-            double c = 0.0;
-            for (size_t k = 0; k < xs.size(); ++k) c += ws[k] * gk[k] * std::cos(two_pi * nu * a * xs[k]);
-            h[i] = 1.0 / (a * c);
-        }
-        DevBuf b;
-        WSG_HIP(ctx, hipMalloc(&b.ptr, N * sizeof(double)));
-        b.size = N * sizeof(double);
-        WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
-        it = ctx->inv_c.emplace(key, b).first;
-    }
-    (void)s;
-    *out = (const double *)it->second.ptr;
-    return WSG_OK;
+// Host copies of the device tables, built once per process and kept until it ends
+// (both the context caches and the no-allocation entry point copy from them).
+template <typename K>
+const std::vector<char> &memo_table(std::map<K, std::vector<char>> &memo, const K &key,
+                                    std::vector<char> (*build)(const K &)) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = memo.find(key);
+    if (it == memo.end()) it = memo.emplace(key, build(key)).first;
+    return it->second;
 }
 
-// Device copy of the Kaiser-Bessel tables: kKbMaxSeries doubles of the power series,
-// then the per-tap polynomials.
-wsg_status kb_tables(wsg_ctx *ctx, int S, double beta, const double **series, int32_t *n,
-                     const float **poly) {
-    const KbHost &h = kb_host(S, beta);
-    auto key = std::make_pair(S, beta);
-    auto it = ctx->kb.find(key);
-    const size_t o_poly = kKbMaxSeries * sizeof(double);
-    if (it == ctx->kb.end()) {
-        std::vector<char> host(o_poly + h.poly.size() * sizeof(float), 0);
-        std::memcpy(host.data(), h.series.data(), h.series.size() * sizeof(double));
-        std::memcpy(host.data() + o_poly, h.poly.data(), h.poly.size() * sizeof(float));
+// 1/C(nu_i), i = 0..N-1, nu_i = (i - N/2)/N, with C(nu) = int_{-S/2}^{S/2} G(d)
+// cos(2 pi nu d) dd by 64-point Gauss-Legendre quadrature (both kernels are analytic
+// on the support).  Key: (N, S, kernel, sigma or beta).
+using InvCKey = std::tuple<int, int, int, double>;
+std::vector<char> build_inv_c(const InvCKey &k) {
+    const int N = std::get<0>(k), S = std::get<1>(k);
+    const bool kb = std::get<2>(k) == WSG_KERNEL_KAISER_BESSEL;
+    const double shape = std::get<3>(k);
+    std::vector<double> xs, ws;
+    gauss_legendre(64, xs, ws);
+    const double a = S / 2.0, s2 = 2.0 * shape * shape;
+    const double i0b = kb ? bessel_i0(shape) : 1.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    std::vector<double> gk(xs.size());
+    for (size_t j = 0; j < xs.size(); ++j) {
+        const double d = a * xs[j];
+        gk[j] = kb ? kb_exact(S, shape, i0b, d) : std::exp(-d * d / s2);
+    }
+    std::vector<char> out((size_t)N * sizeof(double));
+    double *h = (double *)out.data();
+    for (int i = 0; i < N; ++i) {
+        const double nu = (double)(i - N / 2) / N;
+        double c = 0.0;
+        for (size_t j = 0; j < xs.size(); ++j) c += ws[j] * gk[j] * std::cos(two_pi * nu * a * xs[j]);
+        h[i] = 1.0 / (a * c);
+    }
+    return out;
+}
+
+// Quadrature table of the kernel in w for its grid correction: C_w(nu) =
+// sum_j cw[2j+1] cos(2 pi nu cw[2j]) by kCwNodes-point Gauss-Legendre over the
+// support (the window is analytic there).  Key: (w_support, kernel, sigma or beta).
+constexpr int kCwNodes = 32;
+using CwKey = std::tuple<int, int, double>;
+std::vector<char> build_cw(const CwKey &k) {
+    const int Sw = std::get<0>(k);
+    const bool kb = std::get<1>(k) == WSG_KERNEL_KAISER_BESSEL;
+    const double shape = std::get<2>(k);
+    std::vector<double> xs, ws;
+    gauss_legendre(kCwNodes, xs, ws);
+    const double a = Sw / 2.0, i0b = kb ? bessel_i0(shape) : 1.0;
+    const double s2 = 2.0 * shape * shape;
+    std::vector<char> out(2 * kCwNodes * sizeof(double));
+    double *t = (double *)out.data();
+    for (int j = 0; j < kCwNodes; ++j) {
+        const double d = a * xs[j];
+        const double gv = kb ? kb_exact(Sw, shape, i0b, d) : std::exp(-d * d / s2);
+        t[2 * j] = d;
+        t[2 * j + 1] = a * ws[j] * gv;
+    }
+    return out;
+}
+
+// Twiddles e^{+2 pi i m / N}, m < N, in the mesh's complex type.  Key: (N, f64).
+using TwKey = std::pair<int, int>;
+std::vector<char> build_twiddle(const TwKey &k) {
+    const int N = k.first;
+    const bool f64 = k.second != 0;
+    const double two_pi = 6.283185307179586476925286766559;
+    std::vector<char> out((size_t)2 * N * (f64 ? 8 : 4));
+    for (int m = 0; m < N; ++m) {
+        const double c = std::cos(two_pi * m / N), sn = std::sin(two_pi * m / N);
+        if (f64) {
+            ((double *)out.data())[2 * m] = c;
+            ((double *)out.data())[2 * m + 1] = sn;
+        } else {
+            ((float *)out.data())[2 * m] = (float)c;
+            ((float *)out.data())[2 * m + 1] = (float)sn;
+        }
+    }
+    return out;
+}
+
+// Kaiser-Bessel tables as the kernels read them: kKbMaxSeries doubles of the power
+// series, then the per-tap polynomials.  Key: (S, beta).
+constexpr size_t kKbPolyOffset = kKbMaxSeries * sizeof(double);
+using KbKey = std::pair<int, double>;
+std::vector<char> build_kb_bytes(const KbKey &k) {
+    const KbHost &h = kb_host(k.first, k.second);
+    std::vector<char> out(kKbPolyOffset + h.poly.size() * sizeof(float), 0);
+    std::memcpy(out.data(), h.series.data(), h.series.size() * sizeof(double));
+    std::memcpy(out.data() + kKbPolyOffset, h.poly.data(), h.poly.size() * sizeof(float));
+    return out;
+}
+
+InvCKey inv_c_key(const wsg_params *p) {
+    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    return InvCKey(p->grid_n, p->support, (int)p->kernel, kb ? kb_beta(p) : p->kernel_sigma);
+}
+CwKey cw_key(const wsg_params *p) {
+    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    return CwKey(p->w_support, (int)p->kernel, kb ? kb_beta_w(p) : p->kernel_sigma);
+}
+
+const std::vector<char> &host_inv_c(const wsg_params *p) {
+    static std::map<InvCKey, std::vector<char>> memo;
+    return memo_table(memo, inv_c_key(p), build_inv_c);
+}
+const std::vector<char> &host_cw(const wsg_params *p) {
+    static std::map<CwKey, std::vector<char>> memo;
+    return memo_table(memo, cw_key(p), build_cw);
+}
+const std::vector<char> &host_twiddle(int N, bool f64) {
+    static std::map<TwKey, std::vector<char>> memo;
+    return memo_table(memo, TwKey(N, f64 ? 1 : 0), build_twiddle);
+}
+const std::vector<char> &host_kb(int S, double beta) {
+    static std::map<KbKey, std::vector<char>> memo;
+    return memo_table(memo, KbKey(S, beta), build_kb_bytes);
+}
+
+bool needs_inv_c(const wsg_params *p) { return (p->flags & WSG_GRID_CORRECT) != 0; }
+bool needs_cw(const wsg_params *p) { return (p->flags & WSG_GRID_CORRECT) && w_half(p) > 0; }
+
+// device copy of a host table, cached in the context under `key`
+template <typename M, typename K>
+wsg_status cached_device(wsg_ctx *ctx, M &cache, const K &key, const std::vector<char> &host,
+                         const void **out) {
+    auto it = cache.find(key);
+    if (it == cache.end()) {
         DevBuf b;
         WSG_HIP(ctx, hipMalloc(&b.ptr, host.size()));
         b.size = host.size();
         WSG_HIP(ctx, hipMemcpy(b.ptr, host.data(), b.size, hipMemcpyHostToDevice));
-        it = ctx->kb.emplace(key, b).first;
+        it = cache.emplace(key, b).first;
     }
-    *series = (const double *)it->second.ptr;
-    *n = (int32_t)h.series.size();
-    *poly = (const float *)((const char *)it->second.ptr + o_poly);
+    *out = it->second.ptr;
+    return WSG_OK;
+}
+
+wsg_status get_inv_c(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, const double **out) {
+    (void)s;
+    *out = nullptr;
+    if (!needs_inv_c(p)) return WSG_OK;
+    return cached_device(ctx, ctx->inv_c, inv_c_key(p), host_inv_c(p), (const void **)out);
+}
+
+wsg_status kb_tables(wsg_ctx *ctx, int S, double beta, const double **series, int32_t *n,
+                     const float **poly) {
+    const void *d = nullptr;
+    wsg_status rc = cached_device(ctx, ctx->kb, std::make_pair(S, beta), host_kb(S, beta), &d);
+    if (rc) return rc;
+    *series = (const double *)d;
+    *n = (int32_t)kb_host(S, beta).series.size();
+    *poly = (const float *)((const char *)d + kKbPolyOffset);
     return WSG_OK;
 }
 
@@ -561,8 +682,6 @@ wsg_status kernel_tables(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
         wsg_status rc = kb_tables(ctx, p->support, kb_beta(p), &g->kb_series, &g->kb_n, &g->kb_poly);
         if (rc) return rc;
     }
-    g->w_h = w_half(p);
-    g->w_inv2s2 = 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma);
     if (g->w_h > 0 && p->kernel == WSG_KERNEL_KAISER_BESSEL) {
         wsg_status rc = kb_tables(ctx, p->w_support, kb_beta_w(p), &g->kbw_series, &g->kbw_n, &poly);
         if (rc) return rc;
@@ -570,70 +689,19 @@ wsg_status kernel_tables(wsg_ctx *ctx, const wsg_params *p, JobGeom *g) {
     return WSG_OK;
 }
 
-// Quadrature table of the kernel in w for its grid correction: C_w(nu) =
-// sum_j cw[2j+1] cos(2 pi nu cw[2j]) by 32-point Gauss-Legendre over the support
-// (the window is analytic there).  NULL without a kernel in w or a grid correction.
+// NULL without a kernel in w or a grid correction
 wsg_status get_cw(wsg_ctx *ctx, const wsg_params *p, const double **out, int *n_out) {
     *out = nullptr;
     *n_out = 0;
-    if (!(p->flags & WSG_GRID_CORRECT) || w_half(p) == 0) return WSG_OK;
-    const bool kb = p->kernel == WSG_KERNEL_KAISER_BESSEL;
-    const double shape = kb ? kb_beta_w(p) : p->kernel_sigma;
-    auto key = std::make_tuple(-1, (int)p->w_support, (int)p->kernel, shape);
-    auto it = ctx->inv_c.find(key);
-    constexpr int M = 32;
-    if (it == ctx->inv_c.end()) {
-        std::vector<double> xs, ws;
-        gauss_legendre(M, xs, ws);
-        const double a = p->w_support / 2.0, i0b = kb ? bessel_i0(shape) : 1.0;
-        const double s2 = 2.0 * p->kernel_sigma * p->kernel_sigma;
-        std::vector<double> t(2 * M);
-        for (int j = 0; j < M; ++j) {
-            const double d = a * xs[j];
-            const double gv = kb ? kb_exact(p->w_support, shape, i0b, d) : std::exp(-d * d / s2);
-            t[2 * j] = d;
-            t[2 * j + 1] = a * ws[j] * gv;
-        }
-        DevBuf b;
-        WSG_HIP(ctx, hipMalloc(&b.ptr, t.size() * sizeof(double)));
-        b.size = t.size() * sizeof(double);
-        WSG_HIP(ctx, hipMemcpy(b.ptr, t.data(), b.size, hipMemcpyHostToDevice));
-        it = ctx->inv_c.emplace(key, b).first;
-    }
-    *out = (const double *)it->second.ptr;
-    *n_out = M;
+    if (!needs_cw(p)) return WSG_OK;
+    wsg_status rc = cached_device(ctx, ctx->cw, cw_key(p), host_cw(p), (const void **)out);
+    if (rc) return rc;
+    *n_out = kCwNodes;
     return WSG_OK;
 }
 
 wsg_status get_twiddle(wsg_ctx *ctx, int N, bool f64, const void **out) {
-    auto key = std::make_pair(N, f64 ? 1 : 0);
-    auto it = ctx->twiddles.find(key);
-    if (it == ctx->twiddles.end()) {
-        const double two_pi = 6.283185307179586476925286766559;
-        DevBuf b;
-        if (f64) {
-            std::vector<double> h(2 * N);
-            for (int m = 0; m < N; ++m) {
-                h[2 * m] = std::cos(two_pi * m / N);
-                h[2 * m + 1] = std::sin(two_pi * m / N);
-            }
-            b.size = h.size() * sizeof(double);
-            WSG_HIP(ctx, hipMalloc(&b.ptr, b.size));
-            WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> h(2 * N);
-            for (int m = 0; m < N; ++m) {
-                h[2 * m] = (float)std::cos(two_pi * m / N);
-                h[2 * m + 1] = (float)std::sin(two_pi * m / N);
-            }
-            b.size = h.size() * sizeof(float);
-            WSG_HIP(ctx, hipMalloc(&b.ptr, b.size));
-            WSG_HIP(ctx, hipMemcpy(b.ptr, h.data(), b.size, hipMemcpyHostToDevice));
-        }
-        it = ctx->twiddles.emplace(key, b).first;
-    }
-    *out = it->second.ptr;
-    return WSG_OK;
+    return cached_device(ctx, ctx->twiddles, std::make_pair(N, f64 ? 1 : 0), host_twiddle(N, f64), out);
 }
 
 int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
@@ -641,7 +709,7 @@ int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
     auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
                                decade(v->n_rows * (int64_t)v->n_chan));
     auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end()) return std::min(it->second, p->grid_n);
+    if (it != ctx->tuned.end()) return std::min(std::max(it->second, min_tile(p->grid_n)), p->grid_n);
     return default_tile(p);
 }
 
@@ -674,50 +742,19 @@ struct Binned {
     const void *vis, *wts;
     const uint8_t *flags;
     ImgState *st;
-    uint32_t *counts, *offsets, *cursor, *nchunk, *itemoff, *item_bin;
+    uint32_t *counts, *offsets, *cursor;
+    WorkTotals *wt;        // record and item totals, work queue head, overflow counter
+    uint2 *items;          // gridding work list
     void *records;
-    uint32_t n_items;
-    uint32_t n_records;
-    uint32_t *overflow;    // device counter of records the scatter could not place
 };
 
-// Stage inputs, validity pass, counting sort and record scatter.  Ends with
-// the records binned; the grid kernel is launched by the caller.
-wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStream_t s, bool image_host,
-                   Binned &b, int tile_fixed = 0, bool with_stack = true) {
-    int tile = tile_fixed ? tile_fixed : choose_tile(ctx, p, v);
-    b.pl = make_plan(p, v, tile, with_stack, image_host);
-    Plan &pl = b.pl;
-    if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
-    size_t dyn_est = dyn_bytes(pl, pl.records_est, pl.items_est);
-    if (ctx->budget && pl.fixed_bytes + dyn_est > ctx->budget)
-        return fail(ctx, WSG_ENOMEM, "job footprint " + std::to_string(pl.fixed_bytes + dyn_est) +
-                                         " bytes exceeds the context budget");
-    wsg_status rc = ensure_arena(ctx, ctx->fixed, pl.fixed_bytes, ctx->dyn.size, s);
-    if (rc) return rc;
-    char *fx = (char *)ctx->fixed.ptr;
-    b.fx = fx;
-    // inputs
-    if (v->mem == WSG_MEM_HOST) {
-        if (pl.n_rows > 0) {
-            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_uvw, v->uvw, (size_t)pl.n_rows * 24, hipMemcpyHostToDevice, s));
-            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_vis, v->vis, (size_t)pl.n_elem * pl.vis_sz, hipMemcpyHostToDevice, s));
-            if (v->weights)
-                WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_wts, v->weights, (size_t)pl.n_elem * pl.wt_sz, hipMemcpyHostToDevice, s));
-            if (v->flags)
-                WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_flags, v->flags, (size_t)pl.n_elem, hipMemcpyHostToDevice, s));
-        }
-        b.uvw = (const double *)(fx + pl.o_uvw);
-        b.vis = fx + pl.o_vis;
-        b.wts = v->weights ? fx + pl.o_wts : nullptr;
-        b.flags = v->flags ? (const uint8_t *)(fx + pl.o_flags) : nullptr;
-    } else {
-        b.uvw = v->uvw;
-        b.vis = v->vis;
-        b.wts = v->weights;
-        b.flags = v->flags;
-    }
-    JobGeom &g = b.g;
+wsg_status bin_device(wsg_ctx *ctx, const wsg_params *p, Binned &b, uint8_t *mask,
+                      uint32_t *scan_tmp, hipStream_t s);
+
+// Geometry of a job: everything the binning and gridding kernels need except the
+// device pointers (inputs, workspace, kernel tables).
+void job_geom(const wsg_params *p, const wsg_vis *v, const Plan &pl, JobGeom &g) {
+    g = JobGeom{};
     g.n_rows = pl.n_rows;
     g.n_chan = v->n_chan;
     g.n_img = pl.n_img;
@@ -729,100 +766,115 @@ wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStrea
     g.h = (pl.S - 1) / 2;
     g.T = pl.T;
     g.NT = pl.NT;
-    g.logT = 0;
     while ((1 << g.logT) < g.T) ++g.logT;
-    g.logNT = 0;
     while ((1 << g.logNT) < g.NT) ++g.logNT;
     g.scale = (double)pl.N * p->cell_rad;
     g.half = 0.5 * (double)pl.N;
     g.kernel = p->kernel;
     g.inv2s2 = p->kernel == WSG_KERNEL_GAUSSIAN ? 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma) : 0.0;
-    g.kb_series = nullptr;
-    g.kb_n = 0;
-    g.kb_poly = nullptr;
-    g.kbw_series = nullptr;
-    g.kbw_n = 0;
-    rc = kernel_tables(ctx, p, &g);
-    if (rc) return rc;
+    g.w_h = w_half(p);
+    g.w_inv2s2 = 1.0 / (2.0 * p->kernel_sigma * p->kernel_sigma);
     g.range_given = range_given(p) ? 1 : 0;
     g.w_fold = (p->flags & WSG_W_FOLD) ? 1 : 0;
     g.w_min_given = p->w_min;
     g.w_max_given = p->w_max;
-    g.chan_scale = (const double *)(fx + pl.o_scale);
     // track traversal: P = row period (1 without the hint), kStretch time slices
     // per thread
     g.P = pl.P;
     g.n_t = pl.n_t;
     g.n_tb = pl.n_tb;
+}
 
-    b.st = (ImgState *)(fx + pl.o_state);
-    b.counts = (uint32_t *)(fx + pl.o_counts);
-    b.offsets = (uint32_t *)(fx + pl.o_offsets);
-    b.cursor = (uint32_t *)(fx + pl.o_cursor);
-    b.nchunk = (uint32_t *)(fx + pl.o_nchunk);
-    b.itemoff = (uint32_t *)(fx + pl.o_itemoff);
-    uint32_t *scan_tmp = (uint32_t *)(fx + pl.o_scan);
-    uint8_t *mask = (uint8_t *)(fx + pl.o_mask);
-
-    // state: keys start at +inf / -inf, counters at 0
-    std::vector<ImgState> init(pl.n_img);
-    for (auto &x : init) {
-        std::memset(&x, 0, sizeof(x));
-        x.wmin_key = ~0ull;
-        x.wmax_key = 0ull;
+// Workspace pointers of a job laid out by its plan from `base`; device inputs are
+// used in place, host inputs from their staging areas in the workspace.
+void bind_workspace(Binned &b, char *base, const wsg_vis *v) {
+    const Plan &pl = b.pl;
+    b.fx = base;
+    if (v->mem == WSG_MEM_HOST) {
+        b.uvw = (const double *)(base + pl.o_uvw);
+        b.vis = base + pl.o_vis;
+        b.wts = v->weights ? base + pl.o_wts : nullptr;
+        b.flags = v->flags ? (const uint8_t *)(base + pl.o_flags) : nullptr;
+    } else {
+        b.uvw = v->uvw;
+        b.vis = v->vis;
+        b.wts = v->weights;
+        b.flags = v->flags;
     }
-    // per-channel scale and initial state through the pinned staging block
-    // (ensure_pin first waits for the previous copy out of it)
-    rc = ensure_pin(ctx, init.size() * sizeof(ImgState) + (size_t)v->n_chan * 8 + 64);
+    b.g.chan_scale = (const double *)(base + pl.o_scale);
+    b.st = (ImgState *)(base + pl.o_state);
+    b.counts = (uint32_t *)(base + pl.o_counts);
+    b.offsets = (uint32_t *)(base + pl.o_offsets);
+    b.cursor = (uint32_t *)(base + pl.o_cursor);
+    b.wt = (WorkTotals *)(base + pl.o_wt);
+    b.items = (uint2 *)(base + pl.o_items);
+    b.records = base + pl.o_records;
+}
+
+// Stage inputs, validity pass, counting sort and record scatter.  Ends with
+// the records binned; the grid kernel is launched by the caller.
+wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStream_t s, bool image_host,
+                   Binned &b, int tile_fixed = 0, bool with_stack = true) {
+    int tile = tile_fixed ? tile_fixed : choose_tile(ctx, p, v);
+    b.pl = make_plan(p, v, tile, with_stack, image_host);
+    Plan &pl = b.pl;
+    if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
+    if (ctx->budget && pl.fixed_bytes > ctx->budget)
+        return fail(ctx, WSG_ENOMEM, "job footprint " + std::to_string(pl.fixed_bytes) +
+                                         " bytes exceeds the context budget");
+    wsg_status rc = ensure_arena(ctx, ctx->fixed, pl.fixed_bytes, s);
+    if (rc) return rc;
+    char *fx = (char *)ctx->fixed.ptr;
+    job_geom(p, v, pl, b.g);
+    bind_workspace(b, fx, v);
+    if (v->mem == WSG_MEM_HOST && pl.n_rows > 0) {
+        WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_uvw, v->uvw, (size_t)pl.n_rows * 24, hipMemcpyHostToDevice, s));
+        WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_vis, v->vis, (size_t)pl.n_elem * pl.vis_sz, hipMemcpyHostToDevice, s));
+        if (v->weights)
+            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_wts, v->weights, (size_t)pl.n_elem * pl.wt_sz, hipMemcpyHostToDevice, s));
+        if (v->flags)
+            WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_flags, v->flags, (size_t)pl.n_elem, hipMemcpyHostToDevice, s));
+    }
+    rc = kernel_tables(ctx, p, &b.g);
+    if (rc) return rc;
+    // per-channel scale through the pinned staging block (ensure_pin first waits for
+    // the previous copy out of it); state and counters are set by kernels
+    rc = ensure_pin(ctx, (size_t)v->n_chan * 8 + 64);
     if (rc) return rc;
     double *hs = (double *)ctx->pin;
     for (int c = 0; c < v->n_chan; ++c) hs[c] = v->freq_hz ? v->freq_hz[c] / kSpeedOfLight : 1.0;
-    std::memcpy((char *)ctx->pin + align_up((size_t)v->n_chan * 8), init.data(), init.size() * sizeof(ImgState));
     WSG_HIP(ctx, hipMemcpyAsync(fx + pl.o_scale, hs, (size_t)v->n_chan * 8, hipMemcpyHostToDevice, s));
-    WSG_HIP(ctx, hipMemcpyAsync(b.st, (char *)ctx->pin + align_up((size_t)v->n_chan * 8),
-                                init.size() * sizeof(ImgState), hipMemcpyHostToDevice, s));
     WSG_HIP(ctx, hipEventRecord(ctx->pin_done, s));
-    uint32_t *cls_counts = (uint32_t *)(fx + pl.o_cls_counts);
-    WSG_HIP(ctx, hipMemsetAsync(cls_counts, 0, (size_t)pl.n_cls * pl.n_bins * 4, s));
+    return bin_device(ctx, p, b, (uint8_t *)(fx + pl.o_mask), (uint32_t *)(fx + pl.o_scan), s);
+}
 
+// The binning chain on the device: validity, counting sort, work list, scatter.
+// Enqueue only; every size it needs is the plan's worst case.
+wsg_status bin_device(wsg_ctx *ctx, const wsg_params *p, Binned &b, uint8_t *mask,
+                      uint32_t *scan_tmp, hipStream_t s) {
+    const Plan &pl = b.pl;
+    const JobGeom &g = b.g;
+    uint32_t *cls_counts = (uint32_t *)(b.fx + pl.o_cls_counts);
+    launch_init_state(b.st, pl.n_img, s);
+    launch_fill_u32(cls_counts, (size_t)pl.n_cls * pl.n_bins, 0u, s);
+    launch_fill_u32((uint32_t *)b.wt, sizeof(WorkTotals) / 4, 0u, s);
     launch_prep(g, pl.f64, b.uvw, b.vis, b.wts, b.flags, mask, b.st, s);
     launch_finalize_range(g, b.st, s);
     mark(ctx, kMarkPrep, s);
     launch_count(g, b.uvw, mask, b.st, cls_counts, pl.n_cls, s);
-    launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, s);
+    launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, b.wt, s);
     launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
     // offsets over n_bins + 1 entries: the last one is the record total
     launch_scan(b.counts, b.offsets, pl.n_bins + 1, scan_tmp, s);
-    launch_chunks(b.counts, b.nchunk, pl.n_bins, kChunk, s);
-    WSG_HIP(ctx, hipMemsetAsync(b.nchunk + pl.n_bins, 0, 4, s));
-    launch_scan(b.nchunk, b.itemoff, pl.n_bins + 1, scan_tmp, s);
+    launch_item_bases(b.offsets, pl.n_bins, b.wt, s);
+    launch_item_place(b.counts, pl.n_bins, b.wt, b.items, s);
     launch_class_cursors(cls_counts, pl.n_cls, pl.n_bins, b.offsets, b.cursor, s);
-    // totals: records = offsets[n_bins], items = itemoff[n_bins]
-    uint32_t *tot = (uint32_t *)(fx + pl.o_tot);
-    WSG_HIP(ctx, hipMemcpyAsync(tot, b.offsets + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
-    WSG_HIP(ctx, hipMemcpyAsync(tot + 1, b.itemoff + pl.n_bins, 4, hipMemcpyDeviceToDevice, s));
     mark(ctx, kMarkCount, s);
-    rc = ensure_pin(ctx, 64);
-    if (rc) return rc;
-    uint32_t *htot = (uint32_t *)ctx->pin;
-    WSG_HIP(ctx, hipMemcpyAsync(htot, tot, 8, hipMemcpyDeviceToHost, s));
-    WSG_HIP(ctx, hipStreamSynchronize(s));
-    b.n_records = htot[0];
-    b.n_items = htot[1];
-
-    size_t need = dyn_bytes(pl, b.n_records, b.n_items);
-    rc = ensure_arena(ctx, ctx->dyn, need, ctx->fixed.size, s);
-    if (rc) return rc;
-    char *dy = (char *)ctx->dyn.ptr;
-    b.records = dy;
-    b.item_bin = (uint32_t *)(dy + align_up((size_t)b.n_records * rec_size(pl.f64)));
     mark(ctx, kMarkScatterStart, s);
-    launch_item_map(b.nchunk, b.itemoff, b.item_bin, pl.n_bins, s);
-    b.overflow = tot + 2;
-    WSG_HIP(ctx, hipMemsetAsync(b.overflow, 0, 4, s));
     launch_scatter(g, b.uvw, b.vis, b.wts, pl.f64, mask, b.st, b.cursor, pl.n_cls, b.records,
-                   b.n_records, b.overflow, s);
+                   (uint32_t)pl.max_records, &b.wt->overflow, s);
     mark(ctx, kMarkScatter, s);
+    WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
 }
 
@@ -832,8 +884,9 @@ wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, boo
                        hipStream_t s) {
     launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, dense, grid, transposed, s);
     mark(ctx, kMarkZero, s);
-    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk,
-                b.records, grid, transposed, false, s);
+    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.items, b.wt,
+                grid_workgroups(b.pl.f64, b.pl.T, b.pl.max_items, ctx->n_cu), b.records, grid,
+                transposed, false, s);
     mark(ctx, kMarkGrid, s);
     if (!dense)
         launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
@@ -844,17 +897,11 @@ wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, boo
     return WSG_OK;
 }
 
-wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream_t s,
-                      wsg_stats *stats, bool timed) {
-    if (!stats) return WSG_OK;
-    {
-        wsg_status rc = ensure_pin(ctx, 64);
-        if (rc) return rc;
-        WSG_HIP(ctx, hipMemcpyAsync(ctx->pin, b.overflow, 4, hipMemcpyDeviceToHost, s));
-        WSG_HIP(ctx, hipStreamSynchronize(s));
-        if (*(const uint32_t *)ctx->pin != 0)
-            return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
-    }
+// Per-image stats from the job's totals and states read back to the host.
+wsg_status fill_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, const WorkTotals &ht,
+                      const ImgState *hs, wsg_stats *stats, bool timed) {
+    if (ht.overflow != 0)
+        return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
     float t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (timed) {
         WSG_HIP(ctx, hipEventSynchronize(ctx->tev[kMarkEnd]));
@@ -866,18 +913,12 @@ wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream
         for (int i = 0; i < 9; ++i)
             WSG_HIP(ctx, hipEventElapsedTime(&t[i], ctx->tev[pairs[i][0]], ctx->tev[pairs[i][1]]));
     }
-    size_t bytes = (size_t)b.pl.n_img * sizeof(ImgState);
-    wsg_status rc = ensure_pin(ctx, bytes);
-    if (rc) return rc;
-    WSG_HIP(ctx, hipMemcpyAsync(ctx->pin, b.st, bytes, hipMemcpyDeviceToHost, s));
-    WSG_HIP(ctx, hipStreamSynchronize(s));
-    const ImgState *hs = (const ImgState *)ctx->pin;
     int64_t per_img = (b.pl.n_img > 1) ? v->n_rows : v->n_rows * (int64_t)v->n_chan;
     for (int i = 0; i < b.pl.n_img; ++i) {
         stats[i].n_used = (int64_t)hs[i].n_used;
         stats[i].n_flagged = (int64_t)hs[i].n_flagged;
         stats[i].n_dropped = per_img - stats[i].n_used - stats[i].n_flagged;
-        stats[i].n_records = (int64_t)b.n_records;
+        stats[i].n_records = (int64_t)ht.n_records;
         stats[i].n_tiles = (int64_t)hs[i].n_tiles;
         stats[i].n_tile_rows = (int64_t)hs[i].n_tile_rows;
         stats[i].sum_w = hs[i].sum_w;
@@ -896,8 +937,27 @@ wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream
     return WSG_OK;
 }
 
+// Waits for the job and fills stats (NULL: returns at once), through the pinned block.
+wsg_status read_stats(wsg_ctx *ctx, const Binned &b, const wsg_vis *v, hipStream_t s,
+                      wsg_stats *stats, bool timed) {
+    if (!stats) return WSG_OK;
+    const size_t o_st = align_up(sizeof(WorkTotals));
+    const size_t bytes = (size_t)b.pl.n_img * sizeof(ImgState);
+    wsg_status rc = ensure_pin(ctx, o_st + bytes);
+    if (rc) return rc;
+    WSG_HIP(ctx, hipMemcpyAsync(ctx->pin, b.wt, sizeof(WorkTotals), hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipMemcpyAsync((char *)ctx->pin + o_st, b.st, bytes, hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipStreamSynchronize(s));
+    return fill_stats(ctx, b, v, *(const WorkTotals *)ctx->pin,
+                      (const ImgState *)((const char *)ctx->pin + o_st), stats, timed);
+}
+
+bool async_pending(const wsg_ctx *ctx);
+
 wsg_status common_checks(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
     if (!ctx) return WSG_EINVAL;
+    if (async_pending(ctx))
+        return fail(ctx, WSG_EBUSY, "the context has submitted jobs that are not finished");
     std::string why;
     wsg_status rc = check_params(p, why);
     if (rc) return fail(ctx, rc, why);
@@ -911,16 +971,27 @@ wsg_status common_checks(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
 
 // Gridding, both transform passes and the w-correction of a binned job, into the
 // device image img_dev [n_img][N][N].
-wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *img_dev, hipStream_t s) {
+// Device tables of the transform and the w-correction.
+struct Tables {
+    const void *tw = nullptr;          // twiddles of length N
+    const double *inv_c = nullptr;     // 1/C(nu) or NULL (no grid correction)
+    const double *cw = nullptr;        // kernel-in-w quadrature or NULL
+    int n_cw = 0;
+};
+
+wsg_status ctx_tables(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, Tables &t) {
+    wsg_status rc = get_twiddle(ctx, p->grid_n, f64_mode(p), &t.tw);
+    if (rc) return rc;
+    rc = get_inv_c(ctx, p, s, &t.inv_c);
+    if (rc) return rc;
+    return get_cw(ctx, p, &t.cw, &t.n_cw);
+}
+
+wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *img_dev,
+                        const Tables &t, hipStream_t s) {
     const Plan &pl = b.pl;
     void *stack = b.fx + pl.o_stack;
-    const void *tw = nullptr;
-    wsg_status rc = get_twiddle(ctx, pl.N, pl.f64, &tw);
-    if (rc) return rc;
-    const double *inv_c = nullptr;
-    rc = get_inv_c(ctx, p, s, &inv_c);
-    if (rc) return rc;
-    rc = grid_binned(ctx, b, stack, true, false, s);
+    wsg_status rc = grid_binned(ctx, b, stack, true, false, s);
     if (rc) return rc;
     Occupancy occ;
     occ.rows = (const uint64_t *)(b.fx + pl.o_occ_rows);
@@ -928,7 +999,7 @@ wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *im
     occ.live2 = (const uint16_t *)(b.fx + pl.o_occ_live2);
     occ.logT = b.g.logT;
     occ.nw = occupancy_words(pl.NT);
-    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, tw, occ, s);
+    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, t.tw, occ, s);
     mark(ctx, kMarkFft1, s);
     WcorrArgs a{};
     a.N = pl.N;
@@ -940,13 +1011,149 @@ wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *im
     a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
     a.cell = p->cell_rad;
     a.st = b.st;
-    a.inv_c = inv_c;
+    a.inv_c = t.inv_c;
     a.occ = occ;
-    rc = get_cw(ctx, p, &a.cw, &a.n_cw);
-    if (rc) return rc;
-    launch_fft_pass2_wcorr(a, pl.f64, stack, tw, img_dev, s);
+    a.cw = t.cw;
+    a.n_cw = t.n_cw;
+    launch_fft_pass2_wcorr(a, pl.f64, stack, t.tw, img_dev, s);
     WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
+}
+
+// The whole method for one job, enqueued on `s` (no host wait except for a host
+// image, whose copy out waits for the job).
+wsg_status enqueue_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                         int32_t image_mem, hipStream_t s, Binned &b) {
+    if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
+    if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
+    const bool host_img = image_mem == WSG_MEM_HOST;
+    mark(ctx, kMarkStart, s);
+    wsg_status rc = bin_job(ctx, p, v, s, host_img, b);
+    if (rc) return rc;
+    const Plan &pl = b.pl;
+    double *img_dev = host_img ? (double *)(b.fx + pl.o_image) : image;
+    Tables tb;
+    rc = ctx_tables(ctx, p, s, tb);
+    if (rc) return rc;
+    rc = image_binned(ctx, p, b, img_dev, tb, s);
+    if (rc) return rc;
+    if (host_img)
+        WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)pl.n_img * pl.N * pl.N * 8, hipMemcpyDeviceToHost, s));
+    mark(ctx, kMarkEnd, s);
+    return WSG_OK;
+}
+
+// ---------------------------------------------------------------- submitted jobs
+struct AsyncJob {
+    uint64_t ticket = 0;
+    enum { kQueued, kOnDevice, kFinished } state = kQueued;
+    wsg_params p{};
+    wsg_vis v{};
+    std::vector<double> freq;        // the job's own copy of freq_hz
+    double *image = nullptr;
+    int32_t image_mem = WSG_MEM_DEVICE;
+    int slot = -1;
+    Binned b{};
+    wsg_status status = WSG_OK;
+    std::vector<wsg_stats> stats;
+};
+
+bool async_pending(const wsg_ctx *ctx) {
+    for (const auto &j : ctx->async_jobs)
+        if (j->state != AsyncJob::kFinished) return true;
+    return false;
+}
+
+std::shared_ptr<AsyncJob> find_job(wsg_ctx *ctx, uint64_t ticket) {
+    for (auto &j : ctx->async_jobs)
+        if (j->ticket == ticket) return j;
+    return nullptr;
+}
+
+// A job on the device has ended (its event has completed): fill its stats.
+void finish_async(wsg_ctx *ctx, AsyncJob &j) {
+    AsyncSlot &sl = ctx->aslot[j.slot];
+    const size_t o_st = align_up(sizeof(WorkTotals));
+    j.stats.assign((size_t)std::max(1, j.b.pl.n_img), wsg_stats{});
+    j.status = fill_stats(ctx, j.b, &j.v, *(const WorkTotals *)sl.pin,
+                          (const ImgState *)((const char *)sl.pin + o_st), j.stats.data(), false);
+    sl.busy = false;
+    j.slot = -1;
+    j.state = AsyncJob::kFinished;
+}
+
+// Enqueue queued jobs while the device holds fewer than kAsyncDepth of this context's.
+void pump_async(wsg_ctx *ctx) {
+    for (auto &jp : ctx->async_jobs) {
+        AsyncJob &j = *jp;
+        if (j.state != AsyncJob::kQueued) continue;
+        int k = -1;
+        for (int i = 0; i < kAsyncDepth; ++i)
+            if (!ctx->aslot[i].busy) { k = i; break; }
+        if (k < 0) return;
+        AsyncSlot &sl = ctx->aslot[k];
+        const size_t o_st = align_up(sizeof(WorkTotals));
+        const int n_img = n_images(&j.p, &j.v);
+        const size_t need = o_st + (size_t)n_img * sizeof(ImgState);
+        hipStream_t s = pick_stream(ctx, ctx->stream);
+        wsg_status rc = WSG_OK;
+        if (need > sl.size) {
+            if (sl.pin) (void)hipHostFree(sl.pin);
+            sl.pin = nullptr;
+            sl.size = 0;
+            if (hipHostMalloc(&sl.pin, need, hipHostMallocDefault) != hipSuccess)
+                rc = fail(ctx, WSG_ENOMEM, "pinned stats block");
+            else
+                sl.size = need;
+        }
+        if (rc == WSG_OK) rc = enqueue_image(ctx, &j.p, &j.v, j.image, j.image_mem, s, j.b);
+        if (rc == WSG_OK &&
+            (hipMemcpyAsync(sl.pin, j.b.wt, sizeof(WorkTotals), hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipMemcpyAsync((char *)sl.pin + o_st, j.b.st, (size_t)n_img * sizeof(ImgState),
+                            hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipEventRecord(sl.done, s) != hipSuccess))
+            rc = fail(ctx, WSG_EDEVICE, "enqueueing the stats of a submitted job");
+        if (rc != WSG_OK) {
+            j.status = rc;
+            j.state = AsyncJob::kFinished;
+            continue;
+        }
+        sl.busy = true;
+        j.slot = k;
+        j.state = AsyncJob::kOnDevice;
+    }
+}
+
+// Finish every job on the device whose work has ended (wait: the oldest one at least).
+wsg_status progress_async(wsg_ctx *ctx, bool wait_oldest) {
+    for (auto &jp : ctx->async_jobs) {
+        if (jp->state != AsyncJob::kOnDevice) continue;
+        hipEvent_t e = ctx->aslot[jp->slot].done;
+        if (wait_oldest) {
+            WSG_HIP(ctx, hipEventSynchronize(e));
+            wait_oldest = false;
+        } else {
+            const hipError_t q = hipEventQuery(e);
+            if (q == hipErrorNotReady) break;   // later jobs of the stream are not done either
+            if (q != hipSuccess) return fail(ctx, WSG_EDEVICE, hipGetErrorString(q));
+        }
+        finish_async(ctx, *jp);
+    }
+    pump_async(ctx);
+    return WSG_OK;
+}
+
+// Report a finished job once, then forget it.
+wsg_status report_async(wsg_ctx *ctx, const std::shared_ptr<AsyncJob> &j, wsg_stats *stats) {
+    if (stats && j->status == WSG_OK)
+        std::memcpy(stats, j->stats.data(), j->stats.size() * sizeof(wsg_stats));
+    for (auto it = ctx->async_jobs.begin(); it != ctx->async_jobs.end(); ++it)
+        if (*it == j) {
+            ctx->async_jobs.erase(it);
+            break;
+        }
+    if (j->status != WSG_OK && j->status != WSG_ECANCELED) ctx->last_error = "submitted job failed";
+    return j->status;
 }
 
 // ---------------------------------------------------------------- chunked jobs
@@ -965,7 +1172,7 @@ AccumLayout accum_layout(const wsg_params *p, int n_img, int tile) {
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.o_state = take((size_t)n_img * sizeof(ImgState));
     L.o_seen = take(n_bins * 4);
-    L.o_overflow = take(4);
+    L.o_overflow = take(16);   // overflow counter, records of all chunks (64 bits)
     L.o_rows = take(np * occupancy_words(NT) * 8);
     L.o_live1 = take(np * NT * (N / 16) * 4);
     L.o_live2 = take(np * (N / 16) * 2);
@@ -998,7 +1205,6 @@ struct wsg_accum {
     char *mem = nullptr;
     size_t mem_size = 0;
     int64_t per_img_elems = 0;     // elements offered to each image, over all chunks
-    int64_t n_records = 0;
     // host chunks: two device slots filled on the copy stream
     hipStream_t copy = nullptr;
     void *slot[2] = {nullptr, nullptr};
@@ -1068,6 +1274,12 @@ wsg_status wsg_create(int device, wsg_ctx **out) {
     wsg_ctx *ctx = new (std::nothrow) wsg_ctx();
     if (!ctx) return WSG_ENOMEM;
     ctx->device = device;
+    {
+        int n_cu = 0;
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            n_cu > 0)
+            ctx->n_cu = n_cu;
+    }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->pin_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
@@ -1088,12 +1300,17 @@ void wsg_destroy(wsg_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->has_last && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
+    ctx->async_jobs.clear();   // queued jobs are dropped; the device has finished the others
+    for (auto &sl : ctx->aslot) {
+        if (sl.pin) (void)hipHostFree(sl.pin);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
     if (ctx->fixed.ptr) (void)hipFreeAsync(ctx->fixed.ptr, ctx->stream);
-    if (ctx->dyn.ptr) (void)hipFreeAsync(ctx->dyn.ptr, ctx->stream);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &kv : ctx->twiddles) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->inv_c) (void)hipFree(kv.second.ptr);
     for (auto &kv : ctx->kb) (void)hipFree(kv.second.ptr);
+    for (auto &kv : ctx->cw) (void)hipFree(kv.second.ptr);
     for (DevBuf *d : {&ctx->acc_spare, &ctx->slot_spare[0], &ctx->slot_spare[1]})
         if (d->ptr) (void)hipFree(d->ptr);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
@@ -1114,6 +1331,7 @@ const char *wsg_strerror(wsg_status s) {
     case WSG_EDEVICE: return "HIP device error";
     case WSG_EBUSY: return "context busy";
     case WSG_EUNSUPPORTED: return "unsupported by this build";
+    case WSG_ECANCELED: return "job canceled before it started";
     default: return "unknown status";
     }
 }
@@ -1132,11 +1350,8 @@ wsg_status wsg_trim(wsg_ctx *ctx) {
     if (!ctx) return WSG_EINVAL;
     WSG_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->has_last ? ctx->last_stream : ctx->stream;
-    for (Arena *a : {&ctx->fixed, &ctx->dyn}) {
-        if (a->ptr) WSG_HIP(ctx, hipFreeAsync(a->ptr, s));
-        a->ptr = nullptr;
-        a->size = 0;
-    }
+    if (ctx->fixed.ptr) WSG_HIP(ctx, hipFreeAsync(ctx->fixed.ptr, s));
+    ctx->fixed = Arena{};
     WSG_HIP(ctx, hipStreamSynchronize(s));
     for (DevBuf *d : {&ctx->acc_spare, &ctx->slot_spare[0], &ctx->slot_spare[1]}) {
         if (d->ptr) WSG_HIP(ctx, hipFree(d->ptr));
@@ -1173,7 +1388,7 @@ wsg_status wsg_footprint(const wsg_params *p, const wsg_vis *v, uint64_t *bytes)
     if (rc) return rc;
     int tile = p->tile ? p->tile : default_tile(p);
     Plan pl = make_plan(p, v, tile, true, false);
-    *bytes = pl.fixed_bytes + dyn_bytes(pl, pl.records_est, pl.items_est);
+    *bytes = pl.fixed_bytes;
     return WSG_OK;
 }
 
@@ -1181,24 +1396,79 @@ wsg_status wsg_image(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double
                      int32_t image_mem, void *stream, wsg_stats *stats) {
     wsg_status rc = common_checks(ctx, p, v);
     if (rc) return rc;
+    hipStream_t s = pick_stream(ctx, stream);
+    Binned b;
+    rc = enqueue_image(ctx, p, v, image, image_mem, s, b);
+    if (rc) return rc;
+    if (!stats && image_mem == WSG_MEM_HOST) WSG_HIP(ctx, hipStreamSynchronize(s));
+    return read_stats(ctx, b, v, s, stats, ctx->timing != 0);
+}
+
+wsg_status wsg_submit(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                      int32_t image_mem, uint64_t *ticket) {
+    if (!ctx || !ticket) return WSG_EINVAL;
+    *ticket = 0;
+    std::string why;
+    wsg_status rc = check_params(p, why);
+    if (!rc) rc = check_vis(p, v, why);
+    if (rc) return fail(ctx, rc, why);
     if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
     if (image_mem != WSG_MEM_HOST && image_mem != WSG_MEM_DEVICE) return fail(ctx, WSG_EINVAL, "bad image memory space");
-    hipStream_t s = pick_stream(ctx, stream);
-    bool host_img = image_mem == WSG_MEM_HOST;
-    mark(ctx, kMarkStart, s);
-    Binned b;
-    rc = bin_job(ctx, p, v, s, host_img, b);
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    for (auto &sl : ctx->aslot)
+        if (!sl.done) WSG_HIP(ctx, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    auto j = std::make_shared<AsyncJob>();
+    j->ticket = ctx->next_ticket++;
+    j->p = *p;
+    j->v = *v;
+    if (v->freq_hz) {
+        j->freq.assign(v->freq_hz, v->freq_hz + v->n_chan);
+        j->v.freq_hz = j->freq.data();
+    }
+    j->image = image;
+    j->image_mem = image_mem;
+    ctx->async_jobs.push_back(j);
+    pump_async(ctx);
+    *ticket = j->ticket;
+    return WSG_OK;
+}
+
+wsg_status wsg_poll(wsg_ctx *ctx, uint64_t ticket, int32_t *done, wsg_stats *stats) {
+    if (!ctx || !done) return WSG_EINVAL;
+    *done = 0;
+    std::shared_ptr<AsyncJob> j = find_job(ctx, ticket);
+    if (!j) return fail(ctx, WSG_EINVAL, "unknown ticket");
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    wsg_status rc = progress_async(ctx, false);
     if (rc) return rc;
-    const Plan &pl = b.pl;
-    double *img_dev = host_img ? (double *)(b.fx + pl.o_image) : image;
-    rc = image_binned(ctx, p, b, img_dev, s);
-    if (rc) return rc;
-    WSG_HIP(ctx, hipGetLastError());
-    if (host_img)
-        WSG_HIP(ctx, hipMemcpyAsync(image, img_dev, (size_t)pl.n_img * pl.N * pl.N * 8, hipMemcpyDeviceToHost, s));
-    mark(ctx, kMarkEnd, s);
-    if (!stats && host_img) WSG_HIP(ctx, hipStreamSynchronize(s));
-    return read_stats(ctx, b, v, s, stats, ctx->timing != 0);
+    if (j->state != AsyncJob::kFinished) return WSG_OK;
+    *done = 1;
+    return report_async(ctx, j, stats);
+}
+
+wsg_status wsg_wait(wsg_ctx *ctx, uint64_t ticket, wsg_stats *stats) {
+    if (!ctx) return WSG_EINVAL;
+    std::shared_ptr<AsyncJob> j = find_job(ctx, ticket);
+    if (!j) return fail(ctx, WSG_EINVAL, "unknown ticket");
+    WSG_HIP(ctx, hipSetDevice(ctx->device));
+    while (j->state != AsyncJob::kFinished) {
+        wsg_status rc = progress_async(ctx, true);
+        if (rc) return rc;
+    }
+    return report_async(ctx, j, stats);
+}
+
+wsg_status wsg_cancel(wsg_ctx *ctx, uint64_t ticket) {
+    if (!ctx) return WSG_EINVAL;
+    std::shared_ptr<AsyncJob> j = find_job(ctx, ticket);
+    if (!j) return fail(ctx, WSG_EINVAL, "unknown ticket");
+    if (j->state == AsyncJob::kOnDevice)
+        return fail(ctx, WSG_EBUSY, "the job is already on the device");
+    if (j->state == AsyncJob::kQueued) {
+        j->status = WSG_ECANCELED;
+        j->state = AsyncJob::kFinished;
+    }
+    return WSG_OK;
 }
 
 wsg_status wsg_stage_grid(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, void *grid,
@@ -1236,7 +1506,7 @@ wsg_status wsg_stage_fft(wsg_ctx *ctx, const wsg_params *p, void *planes, int64_
     bool f64 = f64_mode(p);
     size_t bytes = (size_t)n_planes * N * N * cplx_size(p);
     size_t need = (mem == WSG_MEM_HOST ? 2 : 1) * align_up(bytes);
-    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size, s);
+    rc = ensure_arena(ctx, ctx->fixed, need, s);
     if (rc) return rc;
     char *fx = (char *)ctx->fixed.ptr;
     void *src = planes;
@@ -1275,7 +1545,7 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
     size_t pbytes = (size_t)n_planes * N * N * cplx_size(p);
     size_t ibytes = (size_t)N * N * 8;
     size_t need = align_up(sizeof(ImgState)) + (mem == WSG_MEM_HOST ? align_up(pbytes) + align_up(ibytes) : 0);
-    rc = ensure_arena(ctx, ctx->fixed, need, ctx->dyn.size, s);
+    rc = ensure_arena(ctx, ctx->fixed, need, s);
     if (rc) return rc;
     char *fx = (char *)ctx->fixed.ptr;
     ImgState *st = (ImgState *)fx;
@@ -1332,7 +1602,7 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
     float best_ms = 1e30f;
     int best = default_tile(p);
     for (int t : cands) {
-        if (t > p->grid_n) continue;
+        if (t > p->grid_n || t < min_tile(p->grid_n)) continue;
         wsg_params q = *p;
         q.tile = t;
         float acc = 0.f;
@@ -1343,7 +1613,10 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
             Binned b;
             rc = bin_job(ctx, &q, v, s, true, b);
             if (rc) return rc;
-            rc = image_binned(ctx, &q, b, (double *)(b.fx + b.pl.o_image), s);
+            Tables tb;
+            rc = ctx_tables(ctx, &q, s, tb);
+            if (rc) return rc;
+            rc = image_binned(ctx, &q, b, (double *)(b.fx + b.pl.o_image), tb, s);
             if (rc) return rc;
             WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
             WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
@@ -1369,6 +1642,68 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
     }
     if (best_tile) *best_tile = best;
     return WSG_OK;
+}
+
+// ---------------------------------------------------------------- device probes
+wsg_status wsg_probe_rates(int device, uint64_t copy_bytes, double *lds_f64_adds_per_s,
+                           double *copy_bytes_per_s) {
+    if (lds_f64_adds_per_s) *lds_f64_adds_per_s = 0.0;
+    if (copy_bytes_per_s) *copy_bytes_per_s = 0.0;
+    if (hipSetDevice(device) != hipSuccess) return WSG_EDEVICE;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
+        return WSG_EDEVICE;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void *a = nullptr, *b = nullptr;
+    wsg_status rc = WSG_OK;
+    auto best_ms = [&](auto launch) -> float {
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            (void)hipEventRecord(e0, s);
+            launch();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best = std::min(best, ms);   // the first launch warms up
+        }
+        return best;
+    };
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        rc = WSG_EDEVICE;
+    } else {
+        // LDS: 8 workgroups per CU, 4 x 2048 adds per lane
+        const int blocks = n_cu * 8, iters = 2048, thr = probe_lds_add_threads();
+        if (hipMalloc(&a, (size_t)blocks * thr * sizeof(double)) != hipSuccess) {
+            rc = WSG_ENOMEM;
+        } else {
+            const float ms = best_ms([&] { launch_probe_lds_add(blocks, iters, (double *)a, s); });
+            if (hipGetLastError() != hipSuccess) rc = WSG_EDEVICE;
+            else if (lds_f64_adds_per_s) *lds_f64_adds_per_s = (double)blocks * thr * 4.0 * iters / (ms * 1e-3);
+            (void)hipFree(a);
+            a = nullptr;
+        }
+        const size_t bytes = (size_t)copy_bytes & ~(size_t)255;
+        if (rc == WSG_OK && bytes > 0) {
+            if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess ||
+                hipMemsetAsync(a, 0, bytes, s) != hipSuccess) {
+                rc = WSG_ENOMEM;
+            } else {
+                const float ms = best_ms([&] { launch_probe_copy(a, b, bytes, n_cu, s); });
+                if (hipGetLastError() != hipSuccess) rc = WSG_EDEVICE;
+                else if (copy_bytes_per_s) *copy_bytes_per_s = 2.0 * (double)bytes / (ms * 1e-3);
+            }
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    return rc;
 }
 
 // ---------------------------------------------------------------- chunked jobs
@@ -1418,7 +1753,7 @@ wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, vo
         wsg_accum_destroy(a);
         return st;
     };
-    if (ctx->budget && ctx->fixed.size + ctx->dyn.size + a->L.bytes > ctx->budget)
+    if (ctx->budget && ctx->fixed.size + a->L.bytes > ctx->budget)
         return undo(fail(ctx, WSG_ENOMEM, "accumulator of " + std::to_string(a->L.bytes) +
                                               " bytes exceeds the context budget"));
     if (hipStreamCreateWithFlags(&a->copy, hipStreamNonBlocking) != hipSuccess)
@@ -1491,16 +1826,16 @@ wsg_status wsg_accum_add(wsg_accum *a, const wsg_vis *v, void *stream) {
     Binned b;
     rc = bin_job(ctx, &a->p, vd, s, false, b, a->tile, false);
     if (rc) { a->broken = true; return rc; }
-    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.itemoff, b.item_bin, b.n_items, kChunk, b.records,
+    launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.items, b.wt,
+                grid_workgroups(b.pl.f64, b.pl.T, b.pl.max_items, ctx->n_cu), b.records,
                 a->mem + a->L.o_stack, true, true, s);
     launch_accum_chunk(b.counts, (uint32_t *)(a->mem + a->L.o_seen), a->n_bins, b.st,
-                       (ImgState *)(a->mem + a->L.o_state), a->n_img, b.overflow,
+                       (ImgState *)(a->mem + a->L.o_state), a->n_img, b.wt,
                        (uint32_t *)(a->mem + a->L.o_overflow), s);
     if (slot >= 0) {
         hipError_t e = hipEventRecord(a->slot_free[slot], s);
         if (e != hipSuccess) { a->broken = true; return fail(ctx, WSG_EDEVICE, "slot event"); }
     }
-    a->n_records += b.n_records;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { a->broken = true; return fail(ctx, WSG_EDEVICE, hipGetErrorString(e)); }
     return WSG_OK;
@@ -1559,22 +1894,24 @@ wsg_status wsg_accum_finish(wsg_accum *a, double *image, int32_t image_mem, void
         WSG_HIP(ctx, hipStreamSynchronize(s));
     }
     if (!stats) return WSG_OK;
-    rc = ensure_pin(ctx, align_up(4) + (size_t)a->n_img * sizeof(ImgState));
+    rc = ensure_pin(ctx, align_up(16) + (size_t)a->n_img * sizeof(ImgState));
     if (rc) return rc;
     char *h = (char *)ctx->pin;
-    WSG_HIP(ctx, hipMemcpyAsync(h, a->mem + a->L.o_overflow, 4, hipMemcpyDeviceToHost, s));
-    WSG_HIP(ctx, hipMemcpyAsync(h + align_up(4), st, (size_t)a->n_img * sizeof(ImgState),
+    WSG_HIP(ctx, hipMemcpyAsync(h, a->mem + a->L.o_overflow, 16, hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipMemcpyAsync(h + align_up(16), st, (size_t)a->n_img * sizeof(ImgState),
                                 hipMemcpyDeviceToHost, s));
     WSG_HIP(ctx, hipStreamSynchronize(s));
-    if (*(const uint32_t *)h != 0)
+    const uint32_t *tot = (const uint32_t *)h;
+    if (tot[0] != 0)
         return fail(ctx, WSG_EDEVICE, "internal error: binning passes disagree on record counts");
-    const ImgState *hs = (const ImgState *)(h + align_up(4));
+    const int64_t n_records = (int64_t)((uint64_t)tot[2] << 32 | tot[1]);
+    const ImgState *hs = (const ImgState *)(h + align_up(16));
     for (int i = 0; i < a->n_img; ++i) {
         std::memset(&stats[i], 0, sizeof(wsg_stats));
         stats[i].n_used = (int64_t)hs[i].n_used;
         stats[i].n_flagged = (int64_t)hs[i].n_flagged;
         stats[i].n_dropped = a->per_img_elems - stats[i].n_used - stats[i].n_flagged;
-        stats[i].n_records = a->n_records;
+        stats[i].n_records = n_records;
         stats[i].n_tiles = (int64_t)hs[i].n_tiles;
         stats[i].n_tile_rows = (int64_t)hs[i].n_tile_rows;
         stats[i].sum_w = hs[i].sum_w;
@@ -1615,10 +1952,11 @@ void wsg_accum_destroy(wsg_accum *a) {
 
 // device bytes held by a context (its arenas and cached tables), for the server
 uint64_t wsg_ctx_device_bytes(const wsg_ctx *ctx) {
-    uint64_t b = ctx->fixed.size + ctx->dyn.size;
+    uint64_t b = ctx->fixed.size;
     for (auto &kv : ctx->twiddles) b += kv.second.size;
     for (auto &kv : ctx->inv_c) b += kv.second.size;
     for (auto &kv : ctx->kb) b += kv.second.size;
+    for (auto &kv : ctx->cw) b += kv.second.size;
     b += ctx->acc_spare.size + ctx->slot_spare[0].size + ctx->slot_spare[1].size;
     return b;
 }

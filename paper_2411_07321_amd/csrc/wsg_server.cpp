@@ -258,6 +258,25 @@ wsg_status wsg_server_wait(wsg_server *srv, uint64_t ticket, wsg_job_info *info)
     return WSG_OK;
 }
 
+wsg_status wsg_server_cancel(wsg_server *srv, uint64_t ticket) {
+    if (!srv) return WSG_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end()) return WSG_EINVAL;
+    const std::shared_ptr<Job> j = it->second;
+    if (j->done) return WSG_OK;
+    for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+        if (*q == j) {
+            srv->queue.erase(q);
+            j->info.status = WSG_ECANCELED;
+            j->info.t_start = j->info.t_end = now_s();
+            j->done = true;
+            srv->cv_done.notify_all();
+            return WSG_OK;
+        }
+    return WSG_EBUSY;   // admitted: its slot is running it
+}
+
 wsg_status wsg_server_memory(wsg_server *srv, uint64_t *held, uint64_t *peak) {
     if (!srv) return WSG_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);

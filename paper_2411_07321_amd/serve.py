@@ -121,6 +121,47 @@ def replay(pool, order, arrivals, n_slots: int, hbm_budget: int = 0, device: int
             "images": kept}
 
 
+def protocol(n_pool: int = 64, n_jobs: int = 600, rates=(20, 50, 100, 200, 400), slots: int = 4,
+             budget: int = 96 << 30, n_check: int = 24, log=None) -> dict:
+    """The serving measurement: one seeded job list of n_jobs drawn from a pool of n_pool
+    datasets, replayed as a backlog (every job queued at t = 0: jobs/s at saturation) and
+    as Poisson arrivals at each rate, batched (slots) and sequential (one slot).  The
+    images of n_check jobs of the backlog runs are compared, batched against
+    sequential (a sequential job runs alone on the device)."""
+    pool = make_pool(n_pool, device="cuda", log=log)
+    rng = np.random.default_rng(synth.CONFIG_SEED0 + 40)
+    order = rng.integers(0, len(pool), n_jobs)
+    check = set(range(0, n_jobs, max(1, n_jobs // n_check)))
+    out = {"workload": "config4_serving", "pool": n_pool, "jobs": n_jobs, "slots": slots,
+           "mean_visibilities": float(np.mean([pool[i].n_vis for i in order])),
+           "backlog": {}, "sweep": []}
+    imgs = {}
+    for name, sl in (("batched", slots), ("sequential", 1)):
+        if log:
+            log(f"backlog, {name}")
+        r = replay(pool, order, np.zeros(n_jobs), sl, budget, keep_images=check)
+        imgs[name] = r.pop("images")
+        out["backlog"][name] = r
+    worst = 0.0
+    for k in check:
+        a, b = imgs["batched"][k], imgs["sequential"][k]
+        nb = np.linalg.norm(b)
+        worst = max(worst, float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)))
+    out["batched_vs_alone_max_rel"] = worst
+    out["checked_jobs"] = len(check)
+    for rate in rates:
+        arr = synth.poisson_arrivals(n_jobs, rate, np.random.default_rng(synth.CONFIG_SEED0 + 41))
+        row = {"rate_hz": rate}
+        for name, sl in (("batched", slots), ("sequential", 1)):
+            if log:
+                log(f"rate {rate}/s, {name}")
+            r = replay(pool, order, arr, sl, budget)
+            r.pop("images")
+            row[name] = {k: r[k] for k in ("jobs_per_s", "p50_ms", "p99_ms", "mean_ms", "wall_s")}
+        out["sweep"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--pool", type=int, default=24)
@@ -130,14 +171,26 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=96.0)
     ap.add_argument("--backlog", action="store_true", help="all jobs arrive at t=0")
     ap.add_argument("--m-cap", type=float, default=None, help="cap visibilities per job")
+    ap.add_argument("--protocol", action="store_true",
+                    help="the full measurement: backlog and a rate sweep, batched vs sequential")
+    ap.add_argument("--rates", default="20,50,100,200,400")
+    ap.add_argument("--modes", default="batched,sequential",
+                    help="which replays to run (without --protocol)")
     args = ap.parse_args()
     log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)
+    if args.protocol:
+        res = protocol(args.pool, args.jobs, tuple(float(x) for x in args.rates.split(",")),
+                       args.slots, int(args.budget_gb * 2**30), log=log)
+        print(json.dumps(res))
+        return
     pool = make_pool(args.pool, device="cuda", m_cap=args.m_cap, log=log)
     rng = np.random.default_rng(synth.CONFIG_SEED0 + 40)
     order = rng.integers(0, len(pool), args.jobs)
     arr = np.zeros(args.jobs) if args.backlog else synth.poisson_arrivals(args.jobs, args.rate, rng)
     res = {}
-    for name, slots in (("batched", args.slots), ("sequential", 1)):
+    modes = [(n, sl) for n, sl in (("batched", args.slots), ("sequential", 1))
+             if n in args.modes.split(",")]
+    for name, slots in modes:
         log(f"replaying {args.jobs} jobs, {name}")
         r = replay(pool, order, arr, slots, int(args.budget_gb * 2**30), log=log)
         r.pop("images")

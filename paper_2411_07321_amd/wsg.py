@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwsg.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EUNSUPPORTED, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f64": 0, "f32_phase64": 1, "f32_phase32": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1, W_FOLD = 1, 2, 4, 8, 16
@@ -29,7 +29,8 @@ SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_s
            "wsg_server_create", "wsg_server_destroy", "wsg_server_submit", "wsg_server_poll",
            "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream",
            "wsg_accum_begin", "wsg_accum_footprint", "wsg_accum_add", "wsg_accum_finish",
-           "wsg_accum_destroy")
+           "wsg_accum_destroy", "wsg_submit", "wsg_poll", "wsg_wait", "wsg_cancel",
+           "wsg_server_cancel", "wsg_probe_rates")
 
 
 class WsgError(RuntimeError):
@@ -116,6 +117,15 @@ def load() -> ctypes.CDLL:
         lib.wsg_n_images.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis)]
         lib.wsg_image.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
                                   ctypes.POINTER(Stats)]
+        lib.wsg_submit.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+        lib.wsg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(S), ctypes.POINTER(Stats)]
+        lib.wsg_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Stats)]
+        lib.wsg_cancel.argtypes = [P, ctypes.c_uint64]
+        lib.wsg_probe_rates.argtypes = [ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        lib.wsg_server_cancel.argtypes = [P, ctypes.c_uint64]
         lib.wsg_stage_grid.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
                                        ctypes.POINTER(Stats)]
         lib.wsg_stage_fft.argtypes = [P, ctypes.POINTER(Params), P, ctypes.c_int64, S, P]
@@ -149,7 +159,8 @@ def load() -> ctypes.CDLL:
                      "wsg_stage_wcorrect", "wsg_autotune", "wsg_server_create",
                      "wsg_server_submit", "wsg_server_poll", "wsg_server_wait",
                      "wsg_server_memory", "wsg_trim", "wsg_accum_begin", "wsg_accum_footprint",
-                     "wsg_accum_add", "wsg_accum_finish"):
+                     "wsg_accum_add", "wsg_accum_finish", "wsg_submit", "wsg_poll", "wsg_wait",
+                     "wsg_cancel", "wsg_server_cancel", "wsg_probe_rates"):
             getattr(lib, name).restype = S
         lib.wsg_n_images.restype = S
         _lib = lib
@@ -346,6 +357,46 @@ class Context:
         self._check(rc, "wsg_image")
         return [x.as_dict() for x in st_arr] if stats else None
 
+    def submit(self, params: Params, vb: VisBuffers, out) -> int:
+        """wsg_submit: queue a job on this context; `vb` and `out` are kept alive here
+        until the job is reported by poll / wait."""
+        po, mo = _ptr_mem(out)
+        _check_inputs(params, vb)
+        _check_out(out, max(1, n_images(params, vb)) * params.grid_n ** 2, ("f", 8), "the image")
+        t = ctypes.c_uint64(0)
+        self._check(load().wsg_submit(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
+                                      ctypes.byref(t)), "wsg_submit")
+        if not hasattr(self, "_jobs"):
+            self._jobs = {}
+        self._jobs[t.value] = (params, vb, out, max(1, n_images(params, vb)))
+        return int(t.value)
+
+    def _report(self, ticket, rc, st_arr):
+        self._jobs.pop(ticket, None)
+        return rc, ([x.as_dict() for x in st_arr] if rc == OK else None)
+
+    def poll(self, ticket: int):
+        """wsg_poll: (False, None, None) while the job runs, else (True, status, stats)."""
+        n_img = self._jobs[ticket][3]
+        done = ctypes.c_int32(0)
+        st_arr = (Stats * n_img)()
+        rc = load().wsg_poll(self._h, int(ticket), ctypes.byref(done), st_arr)
+        if not done.value:
+            self._check(rc, "wsg_poll")
+            return False, None, None
+        return (True,) + self._report(ticket, rc, st_arr)
+
+    def wait(self, ticket: int):
+        """wsg_wait: (status, stats) of the job."""
+        n_img = self._jobs[ticket][3]
+        st_arr = (Stats * n_img)()
+        rc = load().wsg_wait(self._h, int(ticket), st_arr)
+        return self._report(ticket, rc, st_arr)
+
+    def cancel(self, ticket: int) -> int:
+        """wsg_cancel: OK, or EBUSY once the job is on the device."""
+        return load().wsg_cancel(self._h, int(ticket))
+
     def stage_grid(self, params: Params, vb: VisBuffers, out, stream=None):
         po, mo = _ptr_mem(out)
         n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
@@ -491,6 +542,10 @@ class Server:
         self._keep.pop(ticket, None)
         return info.as_dict()
 
+    def cancel(self, ticket: int) -> int:
+        """wsg_server_cancel: OK (a queued job dropped, reported ECANCELED) or EBUSY."""
+        return load().wsg_server_cancel(self._h, int(ticket))
+
     def memory(self):
         held, peak = ctypes.c_uint64(0), ctypes.c_uint64(0)
         load().wsg_server_memory(self._h, ctypes.byref(held), ctypes.byref(peak))
@@ -537,3 +592,12 @@ def params_for(ds, **over) -> Params:
               precision=ds.precision, kernel_sigma=ds.kernel_sigma, per_channel=ds.per_channel)
     kw.update(over)
     return make_params(**kw)
+
+
+def probe_rates(device: int = 0, copy_bytes: int = 1 << 31) -> dict:
+    """wsg_probe_rates: measured FP64 LDS atomic-add rate and device copy bandwidth."""
+    lds, cp = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    st = load().wsg_probe_rates(int(device), int(copy_bytes), ctypes.byref(lds), ctypes.byref(cp))
+    if st != OK:
+        raise WsgError(st, f"wsg_probe_rates: {strerror(st)}")
+    return {"lds_f64_adds_per_s": lds.value, "copy_bytes_per_s": cp.value}

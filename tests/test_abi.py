@@ -43,7 +43,11 @@ def _v(n_rows=10, n_chan=1, **kw):
     (dict(), wsg.OK),
     (dict(grid_n=100), wsg.EINVAL),
     (dict(grid_n=8), wsg.EUNSUPPORTED),
-    (dict(grid_n=8192), wsg.EUNSUPPORTED),
+    (dict(grid_n=8192), wsg.OK),
+    (dict(grid_n=16384), wsg.OK),
+    (dict(grid_n=32768), wsg.EUNSUPPORTED),
+    (dict(grid_n=16384, tile=32, precision="f32_phase64"), wsg.EUNSUPPORTED),  # > 256 tiles per axis
+    (dict(grid_n=16384, tile=64, precision="f32_phase64"), wsg.OK),
     (dict(support=6), wsg.EINVAL),
     (dict(support=0), wsg.EINVAL),
     (dict(support=17), wsg.EUNSUPPORTED),

@@ -86,11 +86,12 @@ def test_stage_grid(ctx, config0, precision):
     assert st[0]["n_used"] == cnt["n_used"]
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])
 @pytest.mark.parametrize("precision", ["f64", "f32_phase64"])
 def test_stage_fft(ctx, n, precision):
+    # 8192 and 16384: one or two rows per workgroup, components exchanged one at a time
     import torch
-    n_pl = 3 if n <= 1024 else 2
+    n_pl = 3 if n <= 1024 else (2 if n <= 4096 else 1)
     g = synth.random_planes(n_pl, n, seed=100 + n)
     ctype = torch.complex128 if precision == "f64" else torch.complex64
     x = dev(g).to(ctype)

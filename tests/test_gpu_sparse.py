@@ -3,7 +3,8 @@ read only what the gridder wrote (tile occupancy).  These cases cluster the uv
 coverage so that most tiles, most tile-rows and whole w-planes are empty, with one
 blob dense enough to split its bin, at tile sizes where one transform workgroup
 spans several tile-rows (N = 64 and 128 with T = 16) and where the tile-row
-bitmap needs four words (N = 4096, T = 16).  Raw image against the FP64 oracle:
+bitmap needs four words (N = 4096, T = 16), and on the meshes above 4096 (8192,
+16384), whose transform rows take a workgroup each.  Raw image against the FP64 oracle:
 rel-L2 <= 1e-12 (FP64 path) and <= 1e-5 (FP32 mesh)."""
 import numpy as np
 import pytest
@@ -57,6 +58,9 @@ def _clustered(n, seed, n_clusters=5, per=300, dense=0):
     (128, 16, 8, 40_000, ("f64", "f32_phase64")),
     (1024, 32, 8, 40_000, ("f64", "f32_phase64")),
     (4096, 16, 4, 0, ("f32_phase64",)),
+    # meshes above 4096: transform rows of one workgroup each, at least N/256 per tile
+    (8192, 32, 2, 0, ("f32_phase64",)),
+    (16384, 64, 2, 0, ("f32_phase64", "f64")),
 ])
 def test_sparse_stack(ctx, n, tile, n_w, dense, precisions):
     uvw, vis, wts = _clustered(n, seed=n + tile, dense=dense)

@@ -613,3 +613,24 @@ def test_w_kernel_edge_planes(sw):
     err, n_planes = w_kernel_edge_plane_error(sw)
     assert err < 1e-14
     assert n_planes == 9
+
+
+def test_grid_threads_bit_identical():
+    """The oracle's gridding splits mesh rows over threads; each cell still receives its
+    terms in input order, so any thread count gives the one-thread result bit for bit."""
+    from paper_2411_07321_amd import synth
+    ds = synth.config0()
+    op = oracle.Params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad)
+    inp = oracle.Inputs.make(ds.uvw, None, ds.vis, ds.weights)
+    wmin, wmax = oracle.w_range(inp, op)
+    before = oracle.threads()
+    try:
+        res = []
+        for t in (1, 3, 8):
+            oracle.threads(t)
+            res.append(oracle.grid(inp, op, wmin, wmax))
+    finally:
+        oracle.threads(before)
+    for g, cnt in res[1:]:
+        assert np.array_equal(g, res[0][0])
+        assert cnt == res[0][1]
