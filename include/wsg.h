@@ -237,6 +237,28 @@ wsg_status wsg_poll(wsg_ctx *ctx, uint64_t ticket, int32_t *done, wsg_stats *sta
 wsg_status wsg_wait(wsg_ctx *ctx, uint64_t ticket, wsg_stats *stats);
 wsg_status wsg_cancel(wsg_ctx *ctx, uint64_t ticket);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): wsg_image without any
+ * allocation.  The workspace (binning state, records, work list, the w-stack) and the
+ * transform tables live in one static device array of 64 MiB per GPU that the library
+ * holds from its first wsg_create on that GPU until the process ends; nothing else is
+ * allocated (no device memory, no pinned host memory).
+ *   - uvw, vis, weights, flags and image must be device buffers (v->mem =
+ *     WSG_MEM_DEVICE); at most 64 channels;
+ *   - a job whose workspace exceeds 64 MiB fails with WSG_ENOMEM before any device
+ *     work (roughly: N_w x N^2 x 8 bytes of complex64 stack plus 64 bytes per
+ *     visibility, e.g. N = 512 with 8 planes and 500,000 visibilities);
+ *   - every call on one GPU uses that GPU's one array, whatever the context: calls
+ *     that overlap in time on one GPU (two host threads, or two streams whose work
+ *     interleaves) race and give wrong results; order them on one stream or wait;
+ *   - the result equals wsg_image's up to the order of floating-point sums.
+ * stream and stats as for wsg_image (stats are read back through pageable host
+ * memory, so a call with stats waits for the device).
+ */
+wsg_status wsg_image_noalloc(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                             void *stream, wsg_stats *stats);
+
 /* ---------------------------------------------------------------------------
  * Stages, separately (for checking each step)
  * ------------------------------------------------------------------------- */

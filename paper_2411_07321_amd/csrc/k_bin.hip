@@ -766,6 +766,15 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
         p[i] = v;
 }
 
+struct ScaleArgs {
+    int n;
+    double v[64];
+};
+__global__ void k_set_scales(double *__restrict__ dst, ScaleArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.n) dst[i] = a.v[i];
+}
+
 __global__ void k_init_state(ImgState *st, int n_img) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_img) return;
@@ -886,6 +895,13 @@ void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return;
     const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
     k_fill_u32<<<blocks, 256, 0, s>>>(p, n, v);
+}
+
+void launch_set_scales(double *dst, const double *vals, int n, hipStream_t s) {
+    ScaleArgs a{};
+    a.n = n < 64 ? n : 64;
+    for (int i = 0; i < a.n; ++i) a.v[i] = vals[i];
+    k_set_scales<<<1, 64, 0, s>>>(dst, a);
 }
 
 void launch_init_state(ImgState *st, int n_img, hipStream_t s) {

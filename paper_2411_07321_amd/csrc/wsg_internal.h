@@ -184,6 +184,8 @@ void launch_item_place(const uint32_t *counts, size_t n_bins, WorkTotals *wt, ui
                        hipStream_t s);
 // fill n words with v (a kernel, not a memset node, so the job can be captured in a graph)
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+// dst[0 .. n) = vals[0 .. n), n <= 64, passed by value in the launch
+void launch_set_scales(double *dst, const double *vals, int n, hipStream_t s);
 // ImgState of n_img images at the start of a job: empty w range keys, zero counters
 void launch_init_state(ImgState *st, int n_img, hipStream_t s);
 // cls_cursor[c][bin] = offsets[bin] + records of classes < c in the bin

@@ -46,6 +46,36 @@ struct DevBuf {
 
 }  // namespace
 
+// Workspace of the no-allocation entry point (wsg_image_noalloc): a static device
+// array, one copy on every GPU the library runs on, held until the process ends.
+// Host code never uses its name as an address: the device address of each GPU's copy
+// is looked up once per device (scratch_address) and kept.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxChan = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch array on `device`, which must be the current device.
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+}  // namespace
+
 namespace {
 // A job submitted to a context (wsg_submit): queued on the host, then enqueued on the
 // context's stream, then finished.
@@ -67,6 +97,7 @@ struct wsg_ctx {
     uint64_t budget = 0;
     Arena fixed;
     int n_cu = 256;                      // compute units of the device
+    void *scratch = nullptr;             // this device's copy of the static scratch array
     // cached tables
     std::map<std::pair<int, int>, DevBuf> twiddles;                       // (N, f64)
     std::map<std::tuple<int, int, int, double>, DevBuf> inv_c;            // (N, S, kernel, shape)
@@ -1274,6 +1305,10 @@ wsg_status wsg_create(int device, wsg_ctx **out) {
     wsg_ctx *ctx = new (std::nothrow) wsg_ctx();
     if (!ctx) return WSG_ENOMEM;
     ctx->device = device;
+    if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+        delete ctx;
+        return WSG_EDEVICE;
+    }
     {
         int n_cu = 0;
         if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
@@ -1642,6 +1677,80 @@ wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, con
     }
     if (best_tile) *best_tile = best;
     return WSG_OK;
+}
+
+// ---------------------------------------------------------------- no allocation
+// wsg_image on the static scratch array: device inputs and image, workspace and
+// tables in the scratch of this GPU, nothing allocated (device or pinned host memory).
+wsg_status wsg_image_noalloc(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, double *image,
+                             void *stream, wsg_stats *stats) {
+    wsg_status rc = common_checks(ctx, p, v);
+    if (rc) return rc;
+    if (!image) return fail(ctx, WSG_EINVAL, "image is NULL");
+    if (v->mem != WSG_MEM_DEVICE)
+        return fail(ctx, WSG_EINVAL, "wsg_image_noalloc takes device inputs only (nothing is staged)");
+    if (v->n_chan > kNoAllocMaxChan)
+        return fail(ctx, WSG_EUNSUPPORTED, "wsg_image_noalloc takes at most 64 channels");
+    if (!ctx->scratch) return fail(ctx, WSG_EDEVICE, "no scratch array on this device");
+    Binned b;
+    b.pl = make_plan(p, v, choose_tile(ctx, p, v), true, false);
+    const Plan &pl = b.pl;
+    if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
+    // tables after the job's workspace, copied from host tables that live as long as
+    // the process (so the copies may complete after this call returns)
+    const bool kbk = p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    const std::vector<char> *tab[5] = {
+        &host_twiddle(pl.N, pl.f64), needs_inv_c(p) ? &host_inv_c(p) : nullptr,
+        needs_cw(p) ? &host_cw(p) : nullptr, kbk ? &host_kb(p->support, kb_beta(p)) : nullptr,
+        (kbk && w_half(p) > 0) ? &host_kb(p->w_support, kb_beta_w(p)) : nullptr};
+    size_t o_tab[5], off = pl.fixed_bytes;
+    for (int i = 0; i < 5; ++i) {
+        o_tab[i] = off;
+        off = align_up(off + (tab[i] ? tab[i]->size() : 0));
+    }
+    if (off > kScratchBytes)
+        return fail(ctx, WSG_ENOMEM, "job needs " + std::to_string(off) +
+                                         " bytes of workspace; wsg_image_noalloc has " +
+                                         std::to_string(kScratchBytes));
+    hipStream_t s = pick_stream(ctx, stream);
+    char *base = (char *)ctx->scratch;
+    job_geom(p, v, pl, b.g);
+    bind_workspace(b, base, v);
+    for (int i = 0; i < 5; ++i)
+        if (tab[i])
+            WSG_HIP(ctx, hipMemcpyAsync(base + o_tab[i], tab[i]->data(), tab[i]->size(),
+                                        hipMemcpyHostToDevice, s));
+    if (tab[3]) {
+        b.g.kb_series = (const double *)(base + o_tab[3]);
+        b.g.kb_n = (int32_t)kb_host(p->support, kb_beta(p)).series.size();
+        b.g.kb_poly = (const float *)(base + o_tab[3] + kKbPolyOffset);
+    }
+    if (tab[4]) {
+        b.g.kbw_series = (const double *)(base + o_tab[4]);
+        b.g.kbw_n = (int32_t)kb_host(p->w_support, kb_beta_w(p)).series.size();
+    }
+    double sc[kNoAllocMaxChan];
+    for (int c = 0; c < v->n_chan; ++c) sc[c] = v->freq_hz ? v->freq_hz[c] / kSpeedOfLight : 1.0;
+    launch_set_scales((double *)(base + pl.o_scale), sc, v->n_chan, s);
+    mark(ctx, kMarkStart, s);
+    rc = bin_device(ctx, p, b, (uint8_t *)(base + pl.o_mask), (uint32_t *)(base + pl.o_scan), s);
+    if (rc) return rc;
+    Tables t;
+    t.tw = base + o_tab[0];
+    t.inv_c = tab[1] ? (const double *)(base + o_tab[1]) : nullptr;
+    t.cw = tab[2] ? (const double *)(base + o_tab[2]) : nullptr;
+    t.n_cw = tab[2] ? kCwNodes : 0;
+    rc = image_binned(ctx, p, b, image, t, s);
+    if (rc) return rc;
+    mark(ctx, kMarkEnd, s);
+    if (!stats) return WSG_OK;
+    // stats through pageable host memory: no pinned staging block either
+    WorkTotals ht;
+    ImgState hs[kNoAllocMaxChan];
+    WSG_HIP(ctx, hipMemcpyAsync(&ht, b.wt, sizeof(WorkTotals), hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipMemcpyAsync(hs, b.st, (size_t)pl.n_img * sizeof(ImgState), hipMemcpyDeviceToHost, s));
+    WSG_HIP(ctx, hipStreamSynchronize(s));
+    return fill_stats(ctx, b, v, ht, hs, stats, ctx->timing != 0);
 }
 
 // ---------------------------------------------------------------- device probes

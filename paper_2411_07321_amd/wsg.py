@@ -25,6 +25,7 @@ GRID_CORRECT, NORMALIZE, PER_CHANNEL, NAIVE_NM1, W_FOLD = 1, 2, 4, 8, 16
 # symbols declared in include/wsg.h
 SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_set_budget",
            "wsg_set_timing", "wsg_check", "wsg_footprint", "wsg_n_images", "wsg_image",
+           "wsg_image_noalloc",
            "wsg_stage_grid", "wsg_stage_fft", "wsg_stage_wcorrect", "wsg_autotune",
            "wsg_server_create", "wsg_server_destroy", "wsg_server_submit", "wsg_server_poll",
            "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream",
@@ -117,6 +118,8 @@ def load() -> ctypes.CDLL:
         lib.wsg_n_images.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Vis)]
         lib.wsg_image.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
                                   ctypes.POINTER(Stats)]
+        lib.wsg_image_noalloc.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, P,
+                                          ctypes.POINTER(Stats)]
         lib.wsg_submit.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S,
                                    ctypes.POINTER(ctypes.c_uint64)]
         lib.wsg_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(S), ctypes.POINTER(Stats)]
@@ -155,7 +158,7 @@ def load() -> ctypes.CDLL:
         lib.wsg_accum_destroy.argtypes = [P]
         lib.wsg_accum_destroy.restype = None
         for name in ("wsg_create", "wsg_set_budget", "wsg_set_timing", "wsg_check",
-                     "wsg_footprint", "wsg_image", "wsg_stage_grid", "wsg_stage_fft",
+                     "wsg_footprint", "wsg_image", "wsg_image_noalloc", "wsg_stage_grid", "wsg_stage_fft",
                      "wsg_stage_wcorrect", "wsg_autotune", "wsg_server_create",
                      "wsg_server_submit", "wsg_server_poll", "wsg_server_wait",
                      "wsg_server_memory", "wsg_trim", "wsg_accum_begin", "wsg_accum_footprint",
@@ -355,6 +358,22 @@ class Context:
         rc = load().wsg_image(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, mo,
                               s, st_arr)
         self._check(rc, "wsg_image")
+        return [x.as_dict() for x in st_arr] if stats else None
+
+    def image_noalloc(self, params: Params, vb: VisBuffers, out, stream=None, stats: bool = True):
+        """wsg_image_noalloc: the method with no allocation, on the library's static
+        workspace (device inputs and image only; small jobs)."""
+        po, mo = _ptr_mem(out)
+        if mo != MEM_DEVICE or vb.desc.mem != MEM_DEVICE:
+            raise ValueError("image_noalloc takes device inputs and a device image")
+        n_img = load().wsg_n_images(ctypes.byref(params), ctypes.byref(vb.desc))
+        _check_inputs(params, vb)
+        _check_out(out, max(1, n_img) * params.grid_n ** 2, ("f", 8), "the image")
+        st_arr = (Stats * max(1, n_img))() if stats else None
+        s = _stream_of(out, stream)
+        rc = load().wsg_image_noalloc(self._h, ctypes.byref(params), ctypes.byref(vb.desc), po, s,
+                                      st_arr)
+        self._check(rc, "wsg_image_noalloc")
         return [x.as_dict() for x in st_arr] if stats else None
 
     def submit(self, params: Params, vb: VisBuffers, out) -> int:
