@@ -256,6 +256,45 @@ def f64_job(args, d, n) -> dict:
             "stages_ms": {k: round(float(np.mean([s[k] for s in sts])), 3) for k in STAGES}}
 
 
+def config3_job(steps: int = 5) -> dict:
+    """Batched channels: 32 channels sharing one uvw set (128 antennas, 512 times), uneven
+    flagging, one 1024^2 x 16-plane stack and image per channel, every stage one launch
+    over all channels (the gridder one persistent launch over every channel's (plane,
+    tile) items, largest first), tile and planes per pass autotuned on the data."""
+    import numpy as np
+    import torch
+    from paper_2411_07321_amd import synth, wsg
+    progress("config 3: generating")
+    ds = synth.config3(device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    vb = wsg.make_vis(dev(ds.uvw), dev(ds.vis), dev(ds.weights), dev(ds.flags), ds.freq_hz,
+                      ds.row_period)
+    n = ds.grid_n
+    out = torch.empty((ds.n_chan, n, n), dtype=torch.float64, device="cuda")
+    with wsg.Context(0) as c:
+        tile, ppp = c.autotune(wsg.params_for(ds), vb)
+        prm = wsg.params_for(ds)
+        c.image(prm, vb, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = c.image(prm, vb, out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+    used = int(sum(x["n_used"] for x in st))
+    rows, nch = ds.uvw.shape[0], ds.n_chan
+    b_in = rows * 24 + rows * nch * (8 + 4 + 1)
+    b_grid = nch * ds.n_wplanes * n * n * 8
+    b_alg = b_in + 2 * b_grid + nch * n * n * 8
+    rate = used / (ms * 1e-3)
+    progress(f"config 3: {ms:.2f} ms/job, {rate:.3e} unflagged vis/s (tile {tile}, ppp {ppp})")
+    return {"ms_per_step": round(ms, 3), "value": rate, "unit": "unflagged visibilities/s",
+            "target": 3.5e10, "vs_target": round(rate / 3.5e10, 4), "n_used": used,
+            "visibilities": rows * nch, "tile": tile, "planes_per_pass": ppp,
+            "B_alg_bytes": b_alg,
+            "path_roofline_frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +305,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true",
                     help="skip the extra timing of the job at the paper's FP64 arithmetic")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the extra timing of the 32-channel cube (config 3)")
     ap.add_argument("--kernel", choices=("gauss", "kb"), default="gauss",
                     help="gridding kernel: Gaussian (sigma 0.9) or Kaiser-Bessel")
     ap.add_argument("--w-support", type=int, default=1,
@@ -407,6 +448,9 @@ def main():
     if not args.no_f64:
         ctx.close()
         result["f64_config1"] = f64_job(args, d, n)
+    if not args.no_config3:
+        ctx.close()
+        result["config3"] = config3_job()
     if not args.no_cpu_baseline:
         progress("cpu baseline: oracle on a bounded sample")
         k = max(1, d["uvw"].shape[0] // args.cpu_sample_rows)

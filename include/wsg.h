@@ -122,6 +122,11 @@ typedef struct {
                            /*   covering the middle N_w - 2 h_w planes, and WSG_GRID_CORRECT   */
                            /*   also divides by its transform at dw (n - 1).  Needs N_w >=    */
                            /*   w_support and the full plane range                             */
+    int32_t planes_per_pass; /* planes of each image held in the w-stack at a time: 0 = all   */
+                           /*   (or the choice wsg_autotune stored); fewer make several passes */
+                           /*   over the planes, each gridding, transforming and w-correcting  */
+                           /*   its planes into the image, with that fraction of the stack's   */
+                           /*   memory (wsg_image and wsg_image_noalloc)                       */
 } wsg_params;
 
 typedef struct {
@@ -327,12 +332,17 @@ void wsg_accum_destroy(wsg_accum *a);
 /* ---------------------------------------------------------------------------
  * Tuning
  * ------------------------------------------------------------------------- */
-/* Time the whole imaging path at each binning tile size (16, 32, 64) on this
- * job's data, on the context's own stream, and store the fastest per (N, N_w, S,
- * precision, visibility-count decade) in the context (and in the text file
- * cache_path if not NULL).  *best_tile receives the choice.  Waits for the device. */
+/* Time the whole imaging path on this job's data, on the context's own stream, at each
+ * binning tile size (16, 32, 64, at least grid_n / 256) and each number of planes per
+ * pass over the w-stack (all, half, a quarter; candidates whose footprint exceeds the
+ * context's budget are skipped), and store the fastest pair per (N, N_w, S, precision,
+ * visibility-count decade) in the context: later calls with tile = 0 and
+ * planes_per_pass = 0 use it.  With cache_path, a line for this job shape already in the
+ * file (the last one) is taken without timing; otherwise the choice is appended as
+ * "N N_w S precision decade tile planes_per_pass ms".  *best_tile and *best_ppp (0 = all
+ * planes at once) receive the choice (each may be NULL).  Waits for the device. */
 wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v,
-                        const char *cache_path, int32_t *best_tile);
+                        const char *cache_path, int32_t *best_tile, int32_t *best_ppp);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent imaging jobs on one device

@@ -90,21 +90,14 @@ struct ElemIO<float, float> {
 
 __device__ __forceinline__ bool is_finite(double a) { return isfinite(a); }
 
-// Every test except the w range (O2 of the method's reading).
-template <typename VT>
-__device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, const void *vis,
-                                       const void *wts, const uint8_t *flags, int64_t e,
-                                       int64_t r, int c, bool &flagged, double &w_out,
-                                       double &wt) {
-    flagged = flags && flags[e];
-    if (flagged) return false;
-    double vr, vi;
-    ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
+// Every test but the flag and the w range (O2 of the method's reading), on the
+// row's stored (u, v, w), the channel's scale, the visibility and its weight.
+__device__ __forceinline__ bool valid_vals(const JobGeom &g, double um, double vm, double wm, double sc,
+                                           double vr, double vi, double wt, double &w_out) {
     if (!(wt > 0.0) || !is_finite(wt)) return false;
-    double sc = g.chan_scale[c];
-    double u = uvw[3 * r] * sc, v = uvw[3 * r + 1] * sc, w = uvw[3 * r + 2] * sc;
+    double u = um * sc, v = vm * sc, w = wm * sc;
     if (!is_finite(u) || !is_finite(v) || !is_finite(w)) return false;
-    if (g.w_fold && uvw[3 * r + 2] < 0.0) {
+    if (g.w_fold && wm < 0.0) {
         u = -u;
         v = -v;
         w = -w;
@@ -115,6 +108,19 @@ __device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, cons
     if (!footprint_fits(mesh_coord(v, g.scale, g.half), g.N, g.h, j0)) return false;
     w_out = w;
     return true;
+}
+
+// Every test except the w range (O2 of the method's reading).
+template <typename VT>
+__device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, const void *vis,
+                                       const void *wts, const uint8_t *flags, int64_t e,
+                                       int64_t r, int c, bool &flagged, double &w_out,
+                                       double &wt) {
+    flagged = flags && flags[e];
+    if (flagged) return false;
+    double vr, vi;
+    ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
+    return valid_vals(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], g.chan_scale[c], vr, vi, wt, w_out);
 }
 
 // grid-stride geometry: stride a multiple of n_chan
@@ -220,6 +226,116 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
             atomicAdd(&st[i].sum_w, s_sumw[i]);
         }
         if (s_flag[i]) atomicAdd(&st[i].n_flagged, s_flag[i]);
+    }
+}
+
+// The validity pass of a single-image complex64 job with NC = 1, 2 or 4 channels, one
+// thread per row: the row's (u, v, w) is loaded once for all its channels, and the
+// channels' visibilities, weights, flags and mask bytes move in one vector access each.
+template <int NC>
+struct RowVec;
+template <> struct RowVec<1> { using V = float2; using W = float; using F = uint8_t; };
+template <> struct RowVec<2> { using V = float4; using W = float2; using F = uint16_t; };
+template <> struct RowVec<4> { using V = float4; using W = float4; using F = uint32_t; };
+
+template <int NC>
+__global__ __launch_bounds__(kThreads) void k_prep_rows(JobGeom g, const double *__restrict__ uvw,
+                                                        const float *__restrict__ vis,
+                                                        const float *__restrict__ wts,
+                                                        const uint8_t *__restrict__ flags,
+                                                        uint8_t *__restrict__ mask, ImgState *st) {
+    using RV = RowVec<NC>;
+    __shared__ unsigned long long s_min, s_max, s_flag, s_valid, s_used;
+    __shared__ double s_sumw;
+    if (threadIdx.x == 0) {
+        s_min = ~0ull;
+        s_max = 0ull;
+        s_flag = s_valid = s_used = 0ull;
+        s_sumw = 0.0;
+    }
+    __syncthreads();
+    unsigned long long kmin = ~0ull, kmax = 0ull, nf = 0, nv = 0, nu = 0;
+    double sw = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < g.n_rows; r += stride) {
+        const double um = uvw[3 * r], vm = uvw[3 * r + 1], wm = uvw[3 * r + 2];
+        float vv[2 * NC], ww[NC];
+        uint8_t ff[NC];
+        if constexpr (NC == 4) {
+            const float4 a = ((const float4 *)vis)[2 * r], b = ((const float4 *)vis)[2 * r + 1];
+            vv[0] = a.x; vv[1] = a.y; vv[2] = a.z; vv[3] = a.w;
+            vv[4] = b.x; vv[5] = b.y; vv[6] = b.z; vv[7] = b.w;
+        } else if constexpr (NC == 2) {
+            const float4 a = ((const float4 *)vis)[r];
+            vv[0] = a.x; vv[1] = a.y; vv[2] = a.z; vv[3] = a.w;
+        } else {
+            const float2 a = ((const float2 *)vis)[r];
+            vv[0] = a.x; vv[1] = a.y;
+        }
+        if (wts) {
+            const typename RV::W x = ((const typename RV::W *)wts)[r];
+            if constexpr (NC == 4) { ww[0] = x.x; ww[1] = x.y; ww[2] = x.z; ww[3] = x.w; }
+            else if constexpr (NC == 2) { ww[0] = x.x; ww[1] = x.y; }
+            else { ww[0] = x; }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ww[c] = 1.0f;
+        }
+        typename RV::F fl = 0;
+        if (flags) fl = ((const typename RV::F *)flags)[r];
+        typename RV::F m = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if ((fl >> (8 * c)) & 0xffu) {
+                ++nf;
+                continue;
+            }
+            double w;
+            if (!valid_vals(g, um, vm, wm, g.chan_scale[c], (double)vv[2 * c], (double)vv[2 * c + 1],
+                            (double)ww[c], w))
+                continue;
+            m |= (typename RV::F)(1u << (8 * c));
+            ++nv;
+            const unsigned long long k = order_key(w);
+            kmin = k < kmin ? k : kmin;
+            kmax = k > kmax ? k : kmax;
+            if (!g.range_given || (w >= g.w_min_given && w <= g.w_max_given)) {
+                ++nu;
+                sw += (double)ww[c];
+            }
+        }
+        ((typename RV::F *)mask)[r] = m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long a = __shfl_xor(kmin, off);
+        unsigned long long b = __shfl_xor(kmax, off);
+        kmin = a < kmin ? a : kmin;
+        kmax = b > kmax ? b : kmax;
+        nf += __shfl_xor(nf, off);
+        nv += __shfl_xor(nv, off);
+        nu += __shfl_xor(nu, off);
+        sw += __shfl_xor(sw, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&s_min, kmin);
+        atomicMax(&s_max, kmax);
+        atomicAdd(&s_flag, nf);
+        atomicAdd(&s_valid, nv);
+        atomicAdd(&s_used, nu);
+        atomicAdd(&s_sumw, sw);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_valid) {
+            atomicMin(&st[0].wmin_key, s_min);
+            atomicMax(&st[0].wmax_key, s_max);
+            atomicAdd(&st[0].n_valid0, s_valid);
+        }
+        if (s_used) {
+            atomicAdd(&st[0].n_used, s_used);
+            atomicAdd(&st[0].sum_w, s_sumw);
+        }
+        if (s_flag) atomicAdd(&st[0].n_flagged, s_flag);
     }
 }
 
@@ -411,17 +527,30 @@ static_assert(kBinThreads % kBinStretches == 0, "phase A keeps one stretch per t
 
 // The keys of a wave, slot by slot (a lane's first key, then its second, ...), as
 // runs of consecutive lanes (consecutive time slices of one track) holding the same
-// key.  f(key, len, head_lane, rank, head, mine) is called by every lane for every
+// key; where all lanes holding a slot hold one key, they are one run even with gaps
+// (lanes without the slot between them).  f(key, len, head_lane, rank, head, mine) is called by every lane for every
 // slot in use: `head` marks a run's first lane, `len` its length there, and `rank`
 // is the lane's position in its run.  All runs of a slot are handled by the same
-// instructions, so a wave takes one atomic round trip per slot, not per bin.
+// instructions, so a wave takes one atomic round trip per slot, not per bin.  f also
+// receives the slot index i first (a compile-time-unrolled constant).
 template <typename F>
 __device__ __forceinline__ void for_each_run(const Keys &ks, int lane, F &&f) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const bool has = i < ks.n;
-        if (__ballot(has) == 0ull) break;   // slots are filled in order
+        const unsigned long long hm = __ballot(has);
+        if (hm == 0ull) break;   // slots are filled in order
         const uint32_t key = has ? ks.k[i] : kNoKey;
+        // common case along a track: every lane holding slot i holds the same bin, and
+        // those lanes (in time order, gaps allowed) form one run
+        const int fl = __ffsll((long long)hm) - 1;
+        const uint32_t k0 = (uint32_t)__shfl((int)key, fl);
+        if (__ballot(has && key != k0) == 0ull) {
+            const uint32_t rank = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
+            const bool head = lane == fl;
+            f(i, key, head ? (uint32_t)__popcll(hm) : 0u, fl, rank, head, has);
+            continue;
+        }
         const uint32_t prev = (uint32_t)__shfl_up((int)key, 1);
         const uint32_t next = (uint32_t)__shfl_down((int)key, 1);
         const bool head = has && (lane == 0 || prev != key);
@@ -433,7 +562,7 @@ __device__ __forceinline__ void for_each_run(const Keys &ks, int lane, F &&f) {
         const int hl = has && hu ? 63 - __clzll((long long)hu) : lane;
         const int tl = __ffsll((long long)(tails & from)) - 1;
         const uint32_t len = head ? (uint32_t)(tl - lane + 1) : 0u;
-        f(key, len, hl, (uint32_t)(lane - hl), head, has);
+        f(i, key, len, hl, (uint32_t)(lane - hl), head, has);
     }
 }
 
@@ -506,7 +635,7 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
         const int hw = WK ? g.w_h : 0;
         for (int dk = -hw; dk <= hw; ++dk) {
             const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
-            for_each_run(kd, lane, [&](uint32_t bin, uint32_t len, int, uint32_t, bool head, bool) {
+            for_each_run(kd, lane, [&](int, uint32_t bin, uint32_t len, int, uint32_t, bool head, bool) {
                 if (head) atomicAdd(&counts[bin], len);
             });
         }
@@ -632,14 +761,46 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
     const size_t n_bins = (size_t)g.n_img * g.n_pl << (2 * g.logNT);
     uint32_t *cursor = cls_cursor + (size_t)(blk % n_cls) * n_bins;
     const uint32_t tmask = (1u << (2 * g.logNT)) - 1u;
+    // the record of element q in bin `bin` (plane weight gw) at `slot`
+    auto put = [&](int q, uint32_t pk, uint32_t bin, uint32_t slot, double gw) {
+        // the counting pass sized the buffer; a slot beyond it would mean the two
+        // passes disagree: never write there, report it instead
+        if (slot >= capacity) {
+            atomicAdd(overflow, 1u);
+            return;
+        }
+        const uint32_t tb0 = pk & tmask;   // lowest tile of the footprint
+        const int tx0 = (int)(tb0 & (uint32_t)(g.NT - 1)), ty0 = (int)(tb0 >> g.logNT);
+        const uint32_t tt = bin & tmask;
+        const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
+        if constexpr (sizeof(VT) == 8) {
+            const uint32_t lij = L.lij[q];
+            RecF64 rec;
+            rec.fx = L.fx[q];
+            rec.fy = L.fy[q];
+            rec.re = WK ? L.re[q] * gw : L.re[q];
+            rec.im = WK ? L.im[q] * gw : L.im[q];
+            rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
+            rec.lj = (int)(lij >> 16) - (dy << g.logT);
+            ((RecF64 *)records)[slot] = rec;
+        } else {
+            const uint32_t a = L.a[q], b = L.b[q];
+            RecF32 rec;
+            rec.px = (((a >> kFracBits) - ((uint32_t)dx << g.logT) + (uint32_t)g.h) << kFracBits) |
+                     (a & 0xffffffu);
+            rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
+                     (b & 0xffffffu);
+            rec.re = WK ? L.re[q] * (float)gw : L.re[q];
+            rec.im = WK ? L.im[q] * (float)gw : L.im[q];
+            ((RecF32 *)records)[slot] = rec;
+        }
+    };
     for (int j = 0; j < kPerWave; ++j) {
         const int s = wave * kPerWave + j;
         const int q = lane * kPitch + s;
         const uint32_t pk = L.pk[q];
         Keys ks;
         unpack_keys(pk, g.NT, ks);
-        const uint32_t tb0 = pk & tmask;   // lowest tile of the footprint
-        const int tx0 = (int)(tb0 & (uint32_t)(g.NT - 1)), ty0 = (int)(tb0 >> g.logNT);
         const int hw = WK ? g.w_h : 0;
         for (int dk = -hw; dk <= hw; ++dk) {
             // weight of plane k0 + dk under the kernel in w (1 without one)
@@ -650,42 +811,13 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
                     gw = w_weight(g, plane_offset(st[ki >> 16], (int)(ki & 0xffffu) + dk, L.wv[q]));
                 }
             const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
-            for_each_run(kd, lane, [&](uint32_t bin, uint32_t len, int hl, uint32_t rank, bool head,
+            for_each_run(kd, lane, [&](int, uint32_t bin, uint32_t len, int hl, uint32_t rank, bool head,
                                        bool mine) {
                 uint32_t base = 0u;
                 if (head) base = atomicAdd(&cursor[bin], len);
                 base = (uint32_t)__shfl((int)base, hl);
                 if (!mine) return;
-                const uint32_t slot = base + rank;
-                // the counting pass sized the buffer; a slot beyond it would mean the
-                // two passes disagree: never write there, report it instead
-                if (slot >= capacity) {
-                    atomicAdd(overflow, 1u);
-                    return;
-                }
-                const uint32_t tt = bin & tmask;
-                const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
-                if constexpr (sizeof(VT) == 8) {
-                    const uint32_t lij = L.lij[q];
-                    RecF64 rec;
-                    rec.fx = L.fx[q];
-                    rec.fy = L.fy[q];
-                    rec.re = WK ? L.re[q] * gw : L.re[q];
-                    rec.im = WK ? L.im[q] * gw : L.im[q];
-                    rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
-                    rec.lj = (int)(lij >> 16) - (dy << g.logT);
-                    ((RecF64 *)records)[slot] = rec;
-                } else {
-                    const uint32_t a = L.a[q], b = L.b[q];
-                    RecF32 rec;
-                    rec.px = (((a >> kFracBits) - ((uint32_t)dx << g.logT) + (uint32_t)g.h) << kFracBits) |
-                             (a & 0xffffffu);
-                    rec.py = (((b >> kFracBits) - ((uint32_t)dy << g.logT) + (uint32_t)g.h) << kFracBits) |
-                             (b & 0xffffffu);
-                    rec.re = WK ? L.re[q] * (float)gw : L.re[q];
-                    rec.im = WK ? L.im[q] * (float)gw : L.im[q];
-                    ((RecF32 *)records)[slot] = rec;
-                }
+                put(q, pk, bin, base + rank, gw);
             });
         }
     }
@@ -701,21 +833,35 @@ __device__ __forceinline__ uint32_t bin_pieces(uint32_t cnt) {
 
 __global__ __launch_bounds__(256) void k_class_totals(const uint32_t *__restrict__ cls_counts,
                                                       int n_cls, size_t n_bins,
-                                                      uint32_t *__restrict__ counts, WorkTotals *wt) {
+                                                      uint32_t *__restrict__ counts) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n_bins) return;
+    uint32_t t = 0;
+    if (i < n_bins)
+        for (int c = 0; c < n_cls; ++c) t += cls_counts[(size_t)c * n_bins + i];
+    counts[i] = t;   // the entry after the last bin stays 0: its offset is the total
+}
+
+// records of bin i if its plane lies in the stack window, else 0
+__device__ __forceinline__ uint32_t window_count(const JobGeom &g, const uint32_t *__restrict__ counts,
+                                                 size_t i, size_t n_bins) {
+    if (i >= n_bins) return 0u;
+    const int kl = (int)((i >> (2 * g.logNT)) % (uint32_t)g.n_pl);
+    if (kl < g.stack_k0 || kl >= g.stack_k0 + g.stack_pl) return 0u;
+    return counts[i];
+}
+
+__global__ __launch_bounds__(256) void k_item_hist(JobGeom g, const uint32_t *__restrict__ counts,
+                                                   size_t n_bins, WorkTotals *wt) {
     __shared__ uint32_t s_hist[kItemClasses];
     if (threadIdx.x < kItemClasses) s_hist[threadIdx.x] = 0u;
     __syncthreads();
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= n_bins) {
-        uint32_t t = 0;
-        if (i < n_bins)
-            for (int c = 0; c < n_cls; ++c) t += cls_counts[(size_t)c * n_bins + i];
-        counts[i] = t;   // the entry after the last bin stays 0: its offset is the total
-        if (t) {
-            const uint32_t np = bin_pieces(t);
-            if (np > 1u) atomicAdd(&s_hist[kItemClasses - 1], np - 1u);
-            atomicAdd(&s_hist[item_class(t - (np - 1u) * kGridChunk)], 1u);
-        }
+    const uint32_t t = window_count(g, counts, i, n_bins);
+    if (t) {
+        const uint32_t np = bin_pieces(t);
+        if (np > 1u) atomicAdd(&s_hist[kItemClasses - 1], np - 1u);
+        atomicAdd(&s_hist[item_class(t - (np - 1u) * kGridChunk)], 1u);
     }
     __syncthreads();
     if (threadIdx.x < kItemClasses && s_hist[threadIdx.x])
@@ -737,13 +883,14 @@ __global__ void k_item_bases(const uint32_t *__restrict__ offsets, size_t n_bins
 
 // Every piece of every non-empty bin takes a slot of its class: slots are reserved
 // per workgroup (one global atomic per class) and dealt out through LDS.
-__global__ __launch_bounds__(256) void k_item_place(const uint32_t *__restrict__ counts, size_t n_bins,
-                                                    WorkTotals *wt, uint2 *__restrict__ items) {
+__global__ __launch_bounds__(256) void k_item_place(JobGeom g, const uint32_t *__restrict__ counts,
+                                                    size_t n_bins, WorkTotals *wt,
+                                                    uint2 *__restrict__ items) {
     __shared__ uint32_t s_cnt[kItemClasses], s_base[kItemClasses];
     if (threadIdx.x < kItemClasses) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t t = i < n_bins ? counts[i] : 0u;
+    const uint32_t t = window_count(g, counts, i, n_bins);
     const uint32_t np = t ? bin_pieces(t) : 0u;
     const int cl = t ? item_class(t - (np - 1u) * kGridChunk) : 0;
     uint32_t full_at = 0u, last_at = 0u;
@@ -845,6 +992,18 @@ void launch_prep(const JobGeom &g, bool f64, const double *uvw, const void *vis,
                  const uint8_t *flags, uint8_t *mask, ImgState *st, hipStream_t s) {
     int64_t n_elem = g.n_rows * (int64_t)g.n_chan;
     if (n_elem == 0) return;
+    // single complex64 image of 1, 2 or 4 channels with aligned rows: a thread per row
+    const int nc = g.n_chan;
+    const auto aligned = [](const void *p, size_t a) { return ((uintptr_t)p % a) == 0; };
+    if (!f64 && g.n_img == 1 && (nc == 1 || nc == 2 || nc == 4) && aligned(vis, 8 * nc) &&
+        aligned(wts, 4 * nc) && aligned(flags, nc) && aligned(mask, nc)) {
+        const unsigned blocks = (unsigned)std::min<int64_t>((g.n_rows + kThreads - 1) / kThreads, 4096);
+        const float *vf = (const float *)vis, *wf = (const float *)wts;
+        if (nc == 4) k_prep_rows<4><<<blocks, kThreads, 0, s>>>(g, uvw, vf, wf, flags, mask, st);
+        else if (nc == 2) k_prep_rows<2><<<blocks, kThreads, 0, s>>>(g, uvw, vf, wf, flags, mask, st);
+        else k_prep_rows<1><<<blocks, kThreads, 0, s>>>(g, uvw, vf, wf, flags, mask, st);
+        return;
+    }
     int blocks = blocks_for(n_elem, g.n_chan);
     if (f64)
         k_prep<double><<<blocks, kThreads, 0, s>>>(g, uvw, vis, wts, flags, mask, st);
@@ -876,19 +1035,17 @@ void launch_count(const JobGeom &g, const double *uvw, const uint8_t *mask, cons
 }
 
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
-                         WorkTotals *wt, hipStream_t s) {
-    k_class_totals<<<(unsigned)((n_bins + 1 + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, counts,
-                                                                        wt);
+                         hipStream_t s) {
+    k_class_totals<<<(unsigned)((n_bins + 1 + 255) / 256), 256, 0, s>>>(cls_counts, n_cls, n_bins, counts);
 }
 
-void launch_item_bases(const uint32_t *offsets, size_t n_bins, WorkTotals *wt, hipStream_t s) {
+void launch_work_list(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
+                      size_t n_bins, WorkTotals *wt, uint2 *items, hipStream_t s) {
+    launch_fill_u32((uint32_t *)((char *)wt + offsetof(WorkTotals, cls_count)), kItemClasses, 0u, s);
+    const unsigned blocks = (unsigned)std::max<size_t>((n_bins + 255) / 256, 1);
+    k_item_hist<<<blocks, 256, 0, s>>>(g, counts, n_bins, wt);
     k_item_bases<<<1, 64, 0, s>>>(offsets, n_bins, wt);
-}
-
-void launch_item_place(const uint32_t *counts, size_t n_bins, WorkTotals *wt, uint2 *items,
-                       hipStream_t s) {
-    if (n_bins == 0) return;
-    k_item_place<<<(unsigned)((n_bins + 255) / 256), 256, 0, s>>>(counts, n_bins, wt, items);
+    k_item_place<<<blocks, 256, 0, s>>>(g, counts, n_bins, wt, items);
 }
 
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {

@@ -586,11 +586,11 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_wcorr(const C
         if (a.cw && inside && dw > 0.0) d /= w_transform<PM>(a.cw, a.n_cw, dw * (double)nm1_of(s));
         if ((p + q) & 1) d = -d;
         if constexpr (STAGE) stg[ix.r * N + p] = d;
-        else D[(size_t)ix.r * N + p] = d;
+        else D[(size_t)ix.r * N + p] = a.accumulate ? D[(size_t)ix.r * N + p] + d : d;
     }
     if constexpr (STAGE) {
         __syncthreads();
-        for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = stg[i];
+        for (int i = threadIdx.x; i < NTR * N; i += blockDim.x) D[i] = a.accumulate ? D[i] + stg[i] : stg[i];
     }
 }
 

@@ -122,10 +122,12 @@ __device__ __forceinline__ void bin_coords(const JobGeom &g, uint32_t b, int &im
     kl = (int)(pl - (uint32_t)img * g.n_pl);
 }
 
+// cell (i, j) of plane kl (counted from plane_lo) of image img in the stack, which
+// holds planes [stack_k0, stack_k0 + stack_pl) of every image
 template <typename T>
 __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, int i, int j,
                                              bool transposed) {
-    size_t plane = ((size_t)img * g.n_pl + kl) * (size_t)g.N * g.N;
+    size_t plane = ((size_t)img * g.stack_pl + (kl - g.stack_k0)) * (size_t)g.N * g.N;
     return plane + (transposed ? ((size_t)i * g.N + j) : ((size_t)j * g.N + i));
 }
 
@@ -380,6 +382,7 @@ __global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const ui
     if (!(c > chunk || (zero_empty && c == 0))) return;
     int img, kl, ty, tx;
     bin_coords(g, b, img, kl, ty, tx);
+    if (kl < g.stack_k0 || kl >= g.stack_k0 + g.stack_pl) return;   // not in this pass
     const int gi0 = tx * TT, gj0 = ty * TT;
     for (int t = threadIdx.x; t < TT * TT; t += blockDim.x) {
         int fast = t % TT, slow = t / TT;
@@ -400,11 +403,13 @@ __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__
                                                    int nw) {
     __shared__ unsigned long long s_tiles[256 * 4];   // [tx][word], NT <= 256
     __shared__ unsigned long long s_rows[4];
-    const int pi = blockIdx.x;
+    const int pi = blockIdx.x;                         // plane of the stack
+    const int img = pi / g.stack_pl;
+    const int kl = g.stack_k0 + (pi - img * g.stack_pl);
     const int NT = g.NT, N = g.N, P = N / 16;
     if (threadIdx.x < 4) s_rows[threadIdx.x] = 0ull;
     __syncthreads();
-    const uint32_t *c = counts + ((size_t)pi << (2 * g.logNT));
+    const uint32_t *c = counts + (((size_t)img * g.n_pl + kl) << (2 * g.logNT));
     for (int t = threadIdx.x; t < NT * nw; t += blockDim.x) {
         const int tx = t % NT, wd = t / NT;
         unsigned long long word = 0ull;
@@ -421,7 +426,6 @@ __global__ __launch_bounds__(256) void k_occupancy(JobGeom g, const uint32_t *__
         unsigned long long nt = 0, nr = 0;
         for (int i = 0; i < NT * nw; ++i) nt += __popcll(s_tiles[i]);
         for (int i = 0; i < nw; ++i) nr += __popcll(s_rows[i]);
-        const int img = pi / g.n_pl;
         if (nt) atomicAdd(&st[img].n_tiles, nt);
         if (nr) atomicAdd(&st[img].n_tile_rows, nr);
     }
@@ -547,7 +551,7 @@ __global__ void k_accum_chunk(const uint32_t *__restrict__ counts, uint32_t *__r
 
 void launch_occupancy(const JobGeom &g, const uint32_t *counts, uint64_t *rows, uint32_t *live1,
                       uint16_t *live2, ImgState *st, hipStream_t s) {
-    const unsigned n_planes = (unsigned)(g.n_img * g.n_pl);
+    const unsigned n_planes = (unsigned)(g.n_img * g.stack_pl);
     if (n_planes == 0) return;
     k_occupancy<<<n_planes, 256, 0, s>>>(g, counts, rows, live1, live2, st, occupancy_words(g.NT));
 }

@@ -98,6 +98,10 @@ struct JobGeom {
     int32_t N;
     int32_t n_w;            // planes over [w_min, w_max]
     int32_t plane_lo, n_pl; // planes imaged: [plane_lo, plane_lo + n_pl)
+    // the w-stack holds planes [stack_k0, stack_k0 + stack_pl) of the n_pl of every
+    // image (planes counted from plane_lo): the whole range in one pass, or one pass
+    // of several over the planes
+    int32_t stack_k0, stack_pl;
     int32_t S, h;
     int32_t T, NT;          // tile edge and tiles per axis (powers of two)
     int32_t logT, logNT;
@@ -173,15 +177,15 @@ struct WorkTotals {
     uint32_t cls_count[kItemClasses];    // items per size class
     uint32_t cls_cursor[kItemClasses];   // placement cursors, then ends of the classes
 };
-// counts[bin] = sum over classes (counts[n_bins] = 0), and the item count of every
-// size class into wt->cls_count (which must start at 0)
+// counts[bin] = sum over classes (counts[n_bins] = 0)
 void launch_class_totals(const uint32_t *cls_counts, int n_cls, size_t n_bins, uint32_t *counts,
-                         WorkTotals *wt, hipStream_t s);
-// class bases (largest class first), n_items, n_records = offsets[n_bins], queue head 0
-void launch_item_bases(const uint32_t *offsets, size_t n_bins, WorkTotals *wt, hipStream_t s);
-// items[slot] = (bin, piece) for every piece of every non-empty bin
-void launch_item_place(const uint32_t *counts, size_t n_bins, WorkTotals *wt, uint2 *items,
-                       hipStream_t s);
+                         hipStream_t s);
+// The work list of the bins whose plane lies in the stack window of g: the item count
+// of every size class (wt->cls_count is cleared first), class bases (largest class
+// first), n_items, n_records = offsets[n_bins] and queue head 0, then items[slot] =
+// (bin, piece) for every piece of every non-empty bin of the window.
+void launch_work_list(const JobGeom &g, const uint32_t *counts, const uint32_t *offsets,
+                      size_t n_bins, WorkTotals *wt, uint2 *items, hipStream_t s);
 // fill n words with v (a kernel, not a memset node, so the job can be captured in a graph)
 void launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 // dst[0 .. n) = vals[0 .. n), n <= 64, passed by value in the launch
@@ -203,8 +207,8 @@ void launch_post_norm(int n_img, ImgState *st, bool normalize, hipStream_t s);
 // gridding of binned records into the plane stack [n_img][n_pl][N][N]
 // transposed: store plane k as [i][j] (u index slow) instead of [j][i]
 // Tile occupancy of the plane stack, so that the transform passes of the imaging
-// path read only what the gridder wrote.  For plane pi (= img * n_pl + kl) of the
-// transposed stack G[i][j], tile-row tx (rows i in [tx*T, tx*T + T)), and the
+// path read only what the gridder wrote.  For plane pi (= img * stack_pl + kl -
+// stack_k0) of the transposed stack G[i][j], tile-row tx (rows i in [tx*T, tx*T + T)), and the
 // thread index t < P = N/16 of a length-N transform, whose points are
 // t + m*P (m < 16):
 //   rows[pi*nw + (tx >> 6)] bit (tx & 63): tile-row tx has a bin with records
@@ -259,6 +263,8 @@ struct WcorrArgs {
     int n_img;
     int n_pl;                // planes per image in the stack
     int plane_lo;            // absolute index of the first plane
+    int accumulate;          // add to the image (a later pass over the planes) instead of
+                             //   writing it
     int n_w;
     int phase32;             // FP32 phase screen
     int naive_nm1;           // FP32 phase with sqrt(1-eta)-1

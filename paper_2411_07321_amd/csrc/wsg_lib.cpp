@@ -108,6 +108,7 @@ struct wsg_ctx {
     // not allocate
     DevBuf acc_spare, slot_spare[2];
     std::map<std::tuple<int, int, int, int, int>, int> tuned;             // -> tile
+    std::map<std::tuple<int, int, int, int, int>, int> tuned_ppp;         // -> planes per pass
     // pinned host staging
     void *pin = nullptr;
     size_t pin_size = 0;
@@ -350,6 +351,7 @@ wsg_status check_params(const wsg_params *p, std::string &why) {
         why = "unknown flag bits";
         return WSG_EINVAL;
     }
+    if (p->planes_per_pass < 0) { why = "planes_per_pass < 0"; return WSG_EINVAL; }
     if (p->tile != 0) {
         if (!(p->tile == 16 || p->tile == 32 || p->tile == 64 || p->tile == 128) || p->tile > p->grid_n) {
             why = "tile must be 16, 32, 64 or 128 and <= grid_n";
@@ -413,6 +415,7 @@ struct Plan {
         o_stack, o_image,
         o_aux, fixed_bytes;
     size_t max_records, max_items;
+    int ppp;                           // planes of each image held in the stack per pass
     int64_t P, n_t, n_tb, n_stretch;   // binning traversal (see JobGeom)
     int n_cls;                         // atomic classes of the binning passes
     size_t o_cls_counts;
@@ -421,7 +424,7 @@ struct Plan {
 // with_stack false: binning workspace only (chunks of a chunked job, whose stack,
 // occupancy and image live in the accumulator)
 Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
-               bool host_out_image) {
+               bool host_out_image, int ppp = 0) {
     Plan pl{};
     pl.N = p->grid_n;
     pl.n_w = p->n_wplanes;
@@ -435,6 +438,7 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
     pl.n_rows = v->n_rows;
     pl.n_elem = v->n_rows * (int64_t)v->n_chan;
     pl.n_bins = (size_t)pl.n_img * pl.n_pl * pl.NT * pl.NT;
+    pl.ppp = (ppp > 0 && ppp < pl.n_pl) ? ppp : pl.n_pl;
     pl.vis_sz = pl.f64 ? 16 : 8;
     pl.wt_sz = pl.f64 ? 8 : 4;
     bool host_in = v->mem == WSG_MEM_HOST;
@@ -465,7 +469,7 @@ Plan make_plan(const wsg_params *p, const wsg_vis *v, int tile, bool with_stack,
     pl.n_tb = (pl.n_t + kStretch - 1) / kStretch;
     pl.n_stretch = stretch_threads(v->n_chan, pl.P, pl.n_tb);
     {
-        const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.n_pl;
+        const size_t nw = (size_t)occupancy_words(pl.NT), np = (size_t)pl.n_img * pl.ppp;
         const size_t k = with_stack ? 1 : 0;
         pl.o_occ_rows = take(k * np * nw * 8);
         pl.o_occ_live1 = take(k * np * pl.NT * (pl.N / 16) * 4);
@@ -735,6 +739,16 @@ wsg_status get_twiddle(wsg_ctx *ctx, int N, bool f64, const void **out) {
     return cached_device(ctx, ctx->twiddles, std::make_pair(N, f64 ? 1 : 0), host_twiddle(N, f64), out);
 }
 
+// planes of each image per pass over the w-stack: the parameter, else the tuned choice
+// for this job's shape, else all of them (0)
+int choose_ppp(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
+    if (p->planes_per_pass > 0) return p->planes_per_pass;
+    auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
+                               decade(v->n_rows * (int64_t)v->n_chan));
+    auto it = ctx->tuned_ppp.find(key);
+    return it != ctx->tuned_ppp.end() ? it->second : 0;
+}
+
 int choose_tile(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v) {
     if (p->tile) return p->tile;
     auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
@@ -793,6 +807,8 @@ void job_geom(const wsg_params *p, const wsg_vis *v, const Plan &pl, JobGeom &g)
     g.n_w = pl.n_w;
     g.plane_lo = pl.plane_lo;
     g.n_pl = pl.n_pl;
+    g.stack_k0 = 0;
+    g.stack_pl = pl.n_pl;
     g.S = pl.S;
     g.h = (pl.S - 1) / 2;
     g.T = pl.T;
@@ -847,7 +863,7 @@ void bind_workspace(Binned &b, char *base, const wsg_vis *v) {
 wsg_status bin_job(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, hipStream_t s, bool image_host,
                    Binned &b, int tile_fixed = 0, bool with_stack = true) {
     int tile = tile_fixed ? tile_fixed : choose_tile(ctx, p, v);
-    b.pl = make_plan(p, v, tile, with_stack, image_host);
+    b.pl = make_plan(p, v, tile, with_stack, image_host, with_stack ? choose_ppp(ctx, p, v) : 0);
     Plan &pl = b.pl;
     if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
     if (ctx->budget && pl.fixed_bytes > ctx->budget)
@@ -893,12 +909,10 @@ wsg_status bin_device(wsg_ctx *ctx, const wsg_params *p, Binned &b, uint8_t *mas
     launch_finalize_range(g, b.st, s);
     mark(ctx, kMarkPrep, s);
     launch_count(g, b.uvw, mask, b.st, cls_counts, pl.n_cls, s);
-    launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, b.wt, s);
+    launch_class_totals(cls_counts, pl.n_cls, pl.n_bins, b.counts, s);
     launch_post_norm(pl.n_img, b.st, (p->flags & WSG_NORMALIZE) != 0, s);
     // offsets over n_bins + 1 entries: the last one is the record total
     launch_scan(b.counts, b.offsets, pl.n_bins + 1, scan_tmp, s);
-    launch_item_bases(b.offsets, pl.n_bins, b.wt, s);
-    launch_item_place(b.counts, pl.n_bins, b.wt, b.items, s);
     launch_class_cursors(cls_counts, pl.n_cls, pl.n_bins, b.offsets, b.cursor, s);
     mark(ctx, kMarkCount, s);
     mark(ctx, kMarkScatterStart, s);
@@ -911,19 +925,22 @@ wsg_status bin_device(wsg_ctx *ctx, const wsg_params *p, Binned &b, uint8_t *mas
 
 // dense: every cell of `grid` is written (the stage entry point); otherwise only
 // the tiles of non-empty bins, and the occupancy bitmaps say which those are
+// The planes of the stack window of b.g: work list, clearing, gridding, occupancy.
+// marks: record the stage events (the first pass over the planes only).
 wsg_status grid_binned(wsg_ctx *ctx, Binned &b, void *grid, bool transposed, bool dense,
-                       hipStream_t s) {
+                       hipStream_t s, bool marks = true) {
+    launch_work_list(b.g, b.counts, b.offsets, b.pl.n_bins, b.wt, b.items, s);
     launch_zero_tiles(b.g, b.pl.f64, b.counts, kChunk, dense, grid, transposed, s);
-    mark(ctx, kMarkZero, s);
+    if (marks) mark(ctx, kMarkZero, s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.items, b.wt,
                 grid_workgroups(b.pl.f64, b.pl.T, b.pl.max_items, ctx->n_cu), b.records, grid,
                 transposed, false, s);
-    mark(ctx, kMarkGrid, s);
+    if (marks) mark(ctx, kMarkGrid, s);
     if (!dense)
         launch_occupancy(b.g, b.counts, (uint64_t *)(b.fx + b.pl.o_occ_rows),
                          (uint32_t *)(b.fx + b.pl.o_occ_live1), (uint16_t *)(b.fx + b.pl.o_occ_live2),
                          b.st, s);
-    mark(ctx, kMarkOcc, s);
+    if (marks) mark(ctx, kMarkOcc, s);
     WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
 }
@@ -1018,35 +1035,48 @@ wsg_status ctx_tables(wsg_ctx *ctx, const wsg_params *p, hipStream_t s, Tables &
     return get_cw(ctx, p, &t.cw, &t.n_cw);
 }
 
+// Gridding, both transform passes and the w-correction of a binned job, into the
+// device image img_dev [n_img][N][N], in passes of pl.ppp planes per image over the
+// w-stack (one pass holds them all unless fewer are asked for): each pass grids its
+// planes into the stack, transforms them and adds their w-corrected sum to the image.
+// With several passes the stage events cover the first pass (ms_total the whole job).
 wsg_status image_binned(wsg_ctx *ctx, const wsg_params *p, Binned &b, double *img_dev,
                         const Tables &t, hipStream_t s) {
     const Plan &pl = b.pl;
     void *stack = b.fx + pl.o_stack;
-    wsg_status rc = grid_binned(ctx, b, stack, true, false, s);
-    if (rc) return rc;
     Occupancy occ;
     occ.rows = (const uint64_t *)(b.fx + pl.o_occ_rows);
     occ.live1 = (const uint32_t *)(b.fx + pl.o_occ_live1);
     occ.live2 = (const uint16_t *)(b.fx + pl.o_occ_live2);
     occ.logT = b.g.logT;
     occ.nw = occupancy_words(pl.NT);
-    launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * pl.n_pl, t.tw, occ, s);
-    mark(ctx, kMarkFft1, s);
-    WcorrArgs a{};
-    a.N = pl.N;
-    a.n_img = pl.n_img;
-    a.n_pl = pl.n_pl;
-    a.plane_lo = pl.plane_lo;
-    a.n_w = pl.n_w;
-    a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
-    a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
-    a.cell = p->cell_rad;
-    a.st = b.st;
-    a.inv_c = t.inv_c;
-    a.occ = occ;
-    a.cw = t.cw;
-    a.n_cw = t.n_cw;
-    launch_fft_pass2_wcorr(a, pl.f64, stack, t.tw, img_dev, s);
+    const int n_pass = (pl.n_pl + pl.ppp - 1) / pl.ppp;
+    for (int ps = 0; ps < n_pass; ++ps) {
+        b.g.stack_k0 = ps * pl.ppp;
+        b.g.stack_pl = std::min(pl.ppp, pl.n_pl - b.g.stack_k0);
+        wsg_status rc = grid_binned(ctx, b, stack, true, false, s, ps == 0);
+        if (rc) return rc;
+        launch_fft_pass1(pl.N, pl.f64, stack, (int64_t)pl.n_img * b.g.stack_pl, t.tw, occ, s);
+        if (ps == 0) mark(ctx, kMarkFft1, s);
+        WcorrArgs a{};
+        a.N = pl.N;
+        a.n_img = pl.n_img;
+        a.n_pl = b.g.stack_pl;
+        a.plane_lo = pl.plane_lo + b.g.stack_k0;
+        a.accumulate = ps > 0;
+        a.n_w = pl.n_w;
+        a.phase32 = p->precision == WSG_PREC_F32_PHASE32;
+        a.naive_nm1 = (p->flags & WSG_NAIVE_NM1) ? 1 : 0;
+        a.cell = p->cell_rad;
+        a.st = b.st;
+        a.inv_c = t.inv_c;
+        a.occ = occ;
+        a.cw = t.cw;
+        a.n_cw = t.n_cw;
+        launch_fft_pass2_wcorr(a, pl.f64, stack, t.tw, img_dev, s);
+    }
+    b.g.stack_k0 = 0;
+    b.g.stack_pl = pl.n_pl;
     WSG_HIP(ctx, hipGetLastError());
     return WSG_OK;
 }
@@ -1422,7 +1452,7 @@ wsg_status wsg_footprint(const wsg_params *p, const wsg_vis *v, uint64_t *bytes)
     rc = check_vis(p, v, why);
     if (rc) return rc;
     int tile = p->tile ? p->tile : default_tile(p);
-    Plan pl = make_plan(p, v, tile, true, false);
+    Plan pl = make_plan(p, v, tile, true, false, p->planes_per_pass);
     *bytes = pl.fixed_bytes;
     return WSG_OK;
 }
@@ -1629,53 +1659,90 @@ wsg_status wsg_stage_wcorrect(wsg_ctx *ctx, const wsg_params *p, const void *pla
 }
 
 wsg_status wsg_autotune(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v, const char *cache_path,
-                        int32_t *best_tile) {
+                        int32_t *best_tile, int32_t *best_ppp) {
     wsg_status rc = common_checks(ctx, p, v);
     if (rc) return rc;
-    hipStream_t s = pick_stream(ctx, ctx->stream);
-    const int cands[] = {16, 32, 64};
-    float best_ms = 1e30f;
-    int best = default_tile(p);
-    for (int t : cands) {
-        if (t > p->grid_n || t < min_tile(p->grid_n)) continue;
-        wsg_params q = *p;
-        q.tile = t;
-        float acc = 0.f;
-        for (int rep = 0; rep < 3; ++rep) {
-            WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
-            // the whole path: the tile also sets how much of the stack the
-            // transform passes skip
-            Binned b;
-            rc = bin_job(ctx, &q, v, s, true, b);
-            if (rc) return rc;
-            Tables tb;
-            rc = ctx_tables(ctx, &q, s, tb);
-            if (rc) return rc;
-            rc = image_binned(ctx, &q, b, (double *)(b.fx + b.pl.o_image), tb, s);
-            if (rc) return rc;
-            WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
-            WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
-            float ms = 0.f;
-            WSG_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-            if (rep > 0) acc += ms;   // first repetition warms the arenas
-        }
-        if (acc < best_ms) {
-            best_ms = acc;
-            best = t;
+    const auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
+                                     decade(v->n_rows * (int64_t)v->n_chan));
+    const int n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    auto choose = [&](int tile, int ppp) {
+        ctx->tuned[key] = tile;
+        ctx->tuned_ppp[key] = ppp;
+        if (best_tile) *best_tile = tile;
+        if (best_ppp) *best_ppp = ppp;
+    };
+    // a stored choice for this job shape (the last line that matches) is taken as it is
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            int n, nw, sup, prec, dec, tile, ppp, found = 0, ft = 0, fp = 0;
+            float ms;
+            char line[256];
+            while (std::fgets(line, sizeof line, f)) {
+                if (std::sscanf(line, "%d %d %d %d %d %d %d %f", &n, &nw, &sup, &prec, &dec, &tile, &ppp,
+                                &ms) == 8 &&
+                    std::make_tuple(n, nw, sup, prec, dec) == key && (tile == 16 || tile == 32 || tile == 64) &&
+                    tile >= min_tile(n) && ppp >= 0) {
+                    found = 1;
+                    ft = tile;
+                    fp = ppp;
+                }
+            }
+            std::fclose(f);
+            if (found) {
+                choose(ft, fp);
+                return WSG_OK;
+            }
         }
     }
-    auto key = std::make_tuple(p->grid_n, p->n_wplanes, p->support, p->precision,
-                               decade(v->n_rows * (int64_t)v->n_chan));
-    ctx->tuned[key] = best;
+    hipStream_t s = pick_stream(ctx, ctx->stream);
+    float best_ms = 1e30f;
+    int best_t = default_tile(p), best_p = 0;
+    std::vector<int> ppps{0};
+    for (int d : {2, 4})
+        if ((n_pl + d - 1) / d < n_pl) ppps.push_back((n_pl + d - 1) / d);
+    for (int t : {16, 32, 64}) {
+        if (t > p->grid_n || t < min_tile(p->grid_n)) continue;
+        for (int ppp : ppps) {
+            wsg_params q = *p;
+            q.tile = t;
+            q.planes_per_pass = ppp;
+            uint64_t fp = 0;
+            if (ctx->budget && wsg_footprint(&q, v, &fp) == WSG_OK && fp > ctx->budget) continue;
+            float acc = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                WSG_HIP(ctx, hipEventRecord(ctx->ev0, s));
+                // the whole path: the tile also sets how much of the stack the
+                // transform passes skip, the passes how much of it is held at once
+                Binned b;
+                rc = bin_job(ctx, &q, v, s, true, b);
+                if (rc) return rc;
+                Tables tb;
+                rc = ctx_tables(ctx, &q, s, tb);
+                if (rc) return rc;
+                rc = image_binned(ctx, &q, b, (double *)(b.fx + b.pl.o_image), tb, s);
+                if (rc) return rc;
+                WSG_HIP(ctx, hipEventRecord(ctx->ev1, s));
+                WSG_HIP(ctx, hipEventSynchronize(ctx->ev1));
+                float ms = 0.f;
+                WSG_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                if (rep > 0) acc += ms;   // first repetition warms the arena
+            }
+            if (acc < best_ms) {
+                best_ms = acc;
+                best_t = t;
+                best_p = ppp;
+            }
+        }
+    }
+    choose(best_t, best_p);
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%d %d %d %d %d %d %.4f\n", p->grid_n, p->n_wplanes, p->support, p->precision,
-                         decade(v->n_rows * (int64_t)v->n_chan), best, best_ms / 2);
+            std::fprintf(f, "%d %d %d %d %d %d %d %.4f\n", p->grid_n, p->n_wplanes, p->support, p->precision,
+                         decade(v->n_rows * (int64_t)v->n_chan), best_t, best_p, best_ms / 2);
             std::fclose(f);
         }
     }
-    if (best_tile) *best_tile = best;
     return WSG_OK;
 }
 
@@ -1693,7 +1760,7 @@ wsg_status wsg_image_noalloc(wsg_ctx *ctx, const wsg_params *p, const wsg_vis *v
         return fail(ctx, WSG_EUNSUPPORTED, "wsg_image_noalloc takes at most 64 channels");
     if (!ctx->scratch) return fail(ctx, WSG_EDEVICE, "no scratch array on this device");
     Binned b;
-    b.pl = make_plan(p, v, choose_tile(ctx, p, v), true, false);
+    b.pl = make_plan(p, v, choose_tile(ctx, p, v), true, false, choose_ppp(ctx, p, v));
     const Plan &pl = b.pl;
     if (pl.n_bins > ((size_t)1 << 27)) return fail(ctx, WSG_EUNSUPPORTED, "more than 2^27 (plane, tile) bins");
     // tables after the job's workspace, copied from host tables that live as long as
@@ -1851,6 +1918,8 @@ wsg_status wsg_accum_begin(wsg_ctx *ctx, const wsg_params *p, int32_t n_chan, vo
     g.n_w = p->n_wplanes;
     g.plane_lo = (p->plane_hi > p->plane_lo) ? p->plane_lo : 0;
     g.n_pl = (p->plane_hi > p->plane_lo) ? p->plane_hi - p->plane_lo : p->n_wplanes;
+    g.stack_k0 = 0;
+    g.stack_pl = g.n_pl;
     g.S = p->support;
     g.h = (p->support - 1) / 2;
     g.T = a->tile;
@@ -1935,6 +2004,7 @@ wsg_status wsg_accum_add(wsg_accum *a, const wsg_vis *v, void *stream) {
     Binned b;
     rc = bin_job(ctx, &a->p, vd, s, false, b, a->tile, false);
     if (rc) { a->broken = true; return rc; }
+    launch_work_list(b.g, b.counts, b.offsets, b.pl.n_bins, b.wt, b.items, s);
     launch_grid(b.g, b.pl.f64, b.counts, b.offsets, b.items, b.wt,
                 grid_workgroups(b.pl.f64, b.pl.T, b.pl.max_items, ctx->n_cu), b.records,
                 a->mem + a->L.o_stack, true, true, s);

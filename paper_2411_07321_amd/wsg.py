@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
                 ("plane_lo", ctypes.c_int32), ("plane_hi", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("kernel_beta", ctypes.c_double),
-                ("w_support", ctypes.c_int32)]
+                ("w_support", ctypes.c_int32), ("planes_per_pass", ctypes.c_int32)]
 
 
 class Vis(ctypes.Structure):
@@ -136,7 +136,8 @@ def load() -> ctypes.CDLL:
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            P, S, P]
         lib.wsg_autotune.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis),
-                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
         lib.wsg_server_create.argtypes = [ctypes.c_int, S, ctypes.c_uint64, ctypes.POINTER(P)]
         lib.wsg_server_destroy.argtypes = [P]
         lib.wsg_server_destroy.restype = None
@@ -243,17 +244,19 @@ KERNEL = {"gauss": 0, "kb": 1}
 def make_params(grid_n, n_wplanes, support, cell_rad, precision="f32_phase64", kernel_sigma=0.9,
                 w_min=None, w_max=None, plane_lo=0, plane_hi=0, grid_correct=True,
                 normalize=True, per_channel=False, naive_nm1=False, tile=0, kernel="gauss",
-                kernel_beta=0.0, w_fold=False, w_support=1) -> Params:
+                kernel_beta=0.0, w_fold=False, w_support=1, planes_per_pass=0) -> Params:
     """kernel: "gauss" (width kernel_sigma) or "kb" (Kaiser-Bessel, shape kernel_beta;
     0 = the library's default for the support).  w_fold: grid rows with w < 0 at their
-    Hermitian mirror.  w_support: planes a visibility spreads over (1: its own)."""
+    Hermitian mirror.  w_support: planes a visibility spreads over (1: its own).
+    planes_per_pass: planes of each image in the w-stack at a time (0: all)."""
     flags = (GRID_CORRECT if grid_correct else 0) | (NORMALIZE if normalize else 0) | \
         (PER_CHANNEL if per_channel else 0) | (NAIVE_NM1 if naive_nm1 else 0) | \
         (W_FOLD if w_fold else 0)
     return Params(int(grid_n), int(n_wplanes), int(support), PREC[precision], float(cell_rad),
                   float(kernel_sigma), math.nan if w_min is None else float(w_min),
                   math.nan if w_max is None else float(w_max), int(plane_lo), int(plane_hi),
-                  flags, int(tile), KERNEL[kernel], float(kernel_beta), int(w_support))
+                  flags, int(tile), KERNEL[kernel], float(kernel_beta), int(w_support),
+                  int(planes_per_pass))
 
 
 @dataclass
@@ -450,13 +453,14 @@ class Context:
                                        _stream_of(out, stream))
         self._check(rc, "wsg_stage_wcorrect")
 
-    def autotune(self, params: Params, vb: VisBuffers, cache_path: str | None = None) -> int:
-        best = ctypes.c_int32(0)
+    def autotune(self, params: Params, vb: VisBuffers, cache_path: str | None = None):
+        """wsg_autotune: (tile, planes_per_pass) chosen for this job shape (0 = all planes)."""
+        best, ppp = ctypes.c_int32(0), ctypes.c_int32(0)
         rc = load().wsg_autotune(self._h, ctypes.byref(params), ctypes.byref(vb.desc),
                                  None if cache_path is None else cache_path.encode(),
-                                 ctypes.byref(best))
+                                 ctypes.byref(best), ctypes.byref(ppp))
         self._check(rc, "wsg_autotune")
-        return int(best.value)
+        return int(best.value), int(ppp.value)
 
 
 class Accum:

@@ -63,6 +63,9 @@ def _v(n_rows=10, n_chan=1, **kw):
     (dict(plane_lo=4, plane_hi=4, w_min=0.0, w_max=1.0), wsg.EINVAL),
     (dict(plane_lo=0, plane_hi=9, w_min=0.0, w_max=1.0), wsg.EINVAL),
     (dict(tile=48), wsg.EINVAL),
+    (dict(planes_per_pass=-1), wsg.EINVAL),
+    (dict(planes_per_pass=3), wsg.OK),
+    (dict(planes_per_pass=20), wsg.OK),                 # more than N_w: one pass
     (dict(tile=128), wsg.EUNSUPPORTED),                  # FP64 LDS tile limit
     (dict(tile=128, precision="f32_phase64"), wsg.EUNSUPPORTED),
     (dict(tile=16, precision="f32_phase64"), wsg.OK),
@@ -129,6 +132,14 @@ def test_footprint_scales_with_mesh():
     assert f3 < f1
     assert wsg.n_images(_p(per_channel=True), _v(n_chan=5)) == 5
     assert wsg.n_images(_p(), _v(n_chan=5)) == 1
+
+
+def test_footprint_shrinks_with_planes_per_pass():
+    """A pass over a quarter of the planes holds a quarter of the w-stack."""
+    full = wsg.footprint(_p(n_wplanes=8), _v(n_rows=1000))
+    quarter = wsg.footprint(_p(n_wplanes=8, planes_per_pass=2), _v(n_rows=1000))
+    stack = 8 * 256 * 256 * 16
+    assert full - quarter >= 0.74 * stack
 
 
 def test_strerror():

@@ -57,12 +57,46 @@ def test_cube_matches_single_channels_and_oracle(c3):
         assert peak(cube[c], ref["image"][0]) <= PEAK32
 
 
-def test_autotune_picks_a_tile(c3):
+def test_passes_over_the_planes_equal_one_pass(c3):
+    """planes_per_pass: the cube imaged 4 and 5 planes at a time (passes of 4, 4, 4, 4 and
+    5, 5, 5, 1 planes) equals the one-pass cube."""
+    import torch
+    ds = c3
+    n = ds.grid_n
+    vb = wsg.make_vis(dev(ds.uvw), dev(ds.vis), dev(ds.weights), dev(ds.flags), ds.freq_hz,
+                      ds.row_period)
+    with wsg.Context(0) as ctx:
+        ref = torch.empty((ds.n_chan, n, n), dtype=torch.float64, device=DEV)
+        st = ctx.image(wsg.params_for(ds, grid_correct=False, normalize=False), vb, ref)
+        for ppp in (4, 5):
+            out = torch.empty_like(ref)
+            st2 = ctx.image(wsg.params_for(ds, grid_correct=False, normalize=False,
+                                           planes_per_pass=ppp), vb, out)
+            torch.cuda.synchronize()
+            a, b = out.cpu().numpy(), ref.cpu().numpy()
+            worst = max(rel(a[c], b[c]) for c in range(ds.n_chan))
+            log(f"{ppp} planes per pass: worst channel rel {worst:.2e}")
+            assert worst <= 1e-6
+            assert [x["n_used"] for x in st2] == [x["n_used"] for x in st]
+            assert [x["n_tiles"] for x in st2] == [x["n_tiles"] for x in st]
+
+
+def test_autotune_picks_tile_and_passes_and_reads_its_cache(c3, tmp_path):
     ds = c3
     prm = wsg.params_for(ds)
     vb = wsg.make_vis(dev(ds.uvw), dev(ds.vis), dev(ds.weights), dev(ds.flags), ds.freq_hz,
                       ds.row_period)
+    cache = str(tmp_path / "tune.txt")
     with wsg.Context(0) as ctx:
-        best = ctx.autotune(prm, vb)
-        assert best in (16, 32, 64)
-        log(f"autotuned tile: {best}")
+        tile, ppp = ctx.autotune(prm, vb, cache)
+        assert tile in (16, 32, 64)
+        assert ppp in (0, 8, 4)
+        log(f"autotuned tile {tile}, planes per pass {ppp or 'all'}")
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[5:7] == [str(tile), str(ppp)]
+    # a new context takes the stored choice without timing (no new line)
+    with open(cache, "a") as f:
+        f.write(lines[0].replace(f" {tile} {ppp} ", " 32 4 ", 1) + "\n")
+    with wsg.Context(0) as ctx:
+        assert ctx.autotune(prm, vb, cache) == (32, 4)
+    assert len(open(cache).read().splitlines()) == 2

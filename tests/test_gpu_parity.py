@@ -41,6 +41,19 @@ def test_config0_f64_image(ctx, config0, on_device, row_period):
     assert rel(img[0], ref["image"][0]) <= TOL64
 
 
+@pytest.mark.parametrize("ppp", [1, 3])
+def test_config0_f64_passes_over_planes(ctx, config0, ppp):
+    # the 8 planes in passes of 1 or 3 (3, 3, 2) planes: each pass grids, transforms
+    # and w-corrects its planes into the image
+    ds = config0
+    wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, "f64")
+    wp.planes_per_pass = ppp
+    img, st = gpu_image(ctx, wp, ds.uvw, ds.vis, ds.weights, row_period=ds.row_period)
+    ref = oracle_image(op, ds.uvw, ds.vis, ds.weights)
+    assert_stats(st, ref["stats"])
+    assert rel(img[0], ref["image"][0]) <= TOL64
+
+
 def test_config0_f64_raw(ctx, config0):
     ds = config0
     wp, op = both_params(ds.grid_n, ds.n_wplanes, ds.support, ds.cell_rad, "f64",
@@ -189,6 +202,41 @@ def test_bad_values_and_footprint_edges(ctx):
     ref = oracle_image(op, uvw, vis, wts, fl)
     assert_stats(st, ref["stats"])
     assert rel(img[0], ref["image"][0]) <= TOL64
+
+
+@pytest.mark.parametrize("n_chan,offset", [(4, 0), (2, 0), (4, 1)])
+def test_f32_channels_flags_and_bad_values(ctx, n_chan, offset):
+    """Single-image complex64 jobs of 2 and 4 channels (the validity pass takes one
+    thread per row with vector loads of the channels), with flags, weights <= 0, NaN
+    and infinite values and footprints off the mesh; offset 1: the arrays start one
+    row into their buffers, so the loads are not 16-byte aligned and the pass takes
+    one thread per (row, channel) instead.  Counts equal the oracle's, raw image
+    within the FP32 bar."""
+    import torch
+    rng = np.random.default_rng(40 + n_chan + offset)
+    m, n = 6001, 128
+    uvw, vis1, wts1 = synth.random_visibilities(m + offset, 1, n, 0.2 / n, seed=41, w_extent=300.0)
+    freq = 150e6 * (1.0 + 0.01 * np.arange(n_chan))
+    uvw = uvw * (299792458.0 / 150e6)              # metres: channels scale u, v, w
+    vis = (rng.standard_normal((m + offset, n_chan)) + 1j * rng.standard_normal((m + offset, n_chan)))
+    wts = rng.uniform(0.5, 1.5, (m + offset, n_chan))
+    flags = (rng.random((m + offset, n_chan)) < 0.1).astype(np.uint8)
+    wts[rng.random(wts.shape) < 0.02] = 0.0
+    vis[rng.random(vis.shape) < 0.01] = np.nan
+    uvw[rng.random(m + offset) < 0.01, 0] = np.inf
+    uvw[::97, 0] = 1e6                               # off the mesh
+    vis, wts = cast_inputs("f32_phase64", vis, wts)
+    wp, op = both_params(n, 6, 7, 0.2 / n, "f32_phase64", grid_correct=False, normalize=False)
+    sl = slice(offset, None)
+    vb = wsg.make_vis(dev(uvw)[sl], dev(vis)[sl], dev(wts)[sl], dev(flags)[sl], freq)
+    out = torch.full((1, n, n), float("nan"), dtype=torch.float64, device=DEV)
+    st = ctx.image(wp, vb, out)
+    torch.cuda.synchronize()
+    ref = oracle_image(op, uvw[sl], vis[sl], wts[sl], flags[sl], freq)
+    assert_stats(st, ref["stats"])
+    e = rel(out.cpu().numpy()[0], ref["raw"][0].real)
+    log(f"f32 {n_chan} channels offset {offset}: {st[0]['n_used']} used of {m * n_chan}, rel {e:.2e}")
+    assert e <= TOL32
 
 
 def test_single_visibility_and_zero_w_spread(ctx):
