@@ -90,6 +90,14 @@ struct ElemIO<float, float> {
 
 __device__ __forceinline__ bool is_finite(double a) { return isfinite(a); }
 
+// An empty statement that takes x and may change it: the compiler has to hold the
+// loaded value here and cannot move its load into the branch that uses it.  Applied
+// to every value of a thread's slots, it keeps all their loads in flight together
+// instead of one slot's loads after another's.
+__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(float &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
 // Every test but the flag and the w range (O2 of the method's reading), on the
 // row's stored (u, v, w), the channel's scale, the visibility and its weight.
 __device__ __forceinline__ bool valid_vals(const JobGeom &g, double um, double vm, double wm, double sc,
@@ -373,7 +381,7 @@ __device__ __forceinline__ int plane_of(double w, double w_min, double dw, doubl
     const double d = w - w_min;
     double q = d * inv_dw;
     double f = q - floor(q);
-    if (f < 1e-9 || f > 1.0 - 1e-9) q = d / dw;
+    if (__builtin_expect(f < 1e-9 || f > 1.0 - 1e-9, 0)) q = d / dw;
     int k = (int)floor(q);
     return k > n_w - 1 ? n_w - 1 : k;
 }
@@ -594,7 +602,12 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
     const int64_t blk = bin_block(blockIdx.x, gridDim.x);
     const int64_t s0 = blk * kBinStretches;
     const StretchPos pos = stretch_pos(g, (uint32_t)(s0 + (int)threadIdx.x % kBinStretches));
-    // phase A: all loads first
+    // every element of a thread belongs to its stretch: one channel, one image
+    const int img = (g.n_img > 1) ? pos.c : 0;
+    const ImgState sti = st[img];
+    const double sc = g.chan_scale[pos.c];
+    // phase A: all loads first, none of them conditional (a slot past the data reads
+    // element 0 and is masked afterwards), so that they are all in flight together
     Slice sl[kPerThread];
     uint8_t mk[kPerThread];
     double u[kPerThread], v[kPerThread], w[kPerThread];
@@ -603,22 +616,31 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
         int t, s;
         tile_slot(k, t, s);
         sl[k] = slice_at(g, pos, t);
-        mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
         const int64_t r = sl[k].ok ? sl[k].r : 0;
-        u[k] = mk[k] ? uvw[3 * r] : 0.0;
-        v[k] = mk[k] ? uvw[3 * r + 1] : 0.0;
-        w[k] = mk[k] ? uvw[3 * r + 2] : 0.0;
+        const int64_t e = sl[k].ok ? sl[k].e : 0;
+        mk[k] = mask[e];
+        u[k] = uvw[3 * r];
+        v[k] = uvw[3 * r + 1];
+        w[k] = uvw[3 * r + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        uint32_t m = mk[k];
+        pin(m);
+        pin(u[k]);
+        pin(v[k]);
+        pin(w[k]);
+        mk[k] = sl[k].ok ? (uint8_t)m : (uint8_t)0;
     }
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
         tile_slot(k, t, s);
-        const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;
-        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl)) {
+        if (mk[k] && place_vals(g, sti, u[k], v[k], w[k], sc, pl)) {
             pk = pack_placed(g, img, pl);
-            if (WK && pk != kNoKey && st[img].dw > 0.0) pk |= kSpread;
+            if (WK && pk != kNoKey && sti.dw > 0.0) pk |= kSpread;
         }
         s_pk[t * kPitch + s] = pk;
     }
@@ -670,6 +692,20 @@ struct ScatterLdsW<VT, true> : ScatterLds<VT> {
     uint32_t kimg[kTileElems];
 };
 
+// Slot reservation per workgroup: each wave lists the runs of its stretches (bin and
+// length) in its part of an LDS run list, the workgroup's threads then reserve the
+// slots of every listed run with parallel atomics (one round trip for the whole
+// workgroup instead of one per key slot of every stretch), and each wave finally walks
+// its stretches again, in the same order, to write the records from the returned
+// bases.  Runs beyond a wave's kWaveRuns entries reserve their slots on the spot.
+constexpr int kWaveRuns = 32;
+constexpr int kRunList = kWaveRuns * (kBinThreads / 64);
+struct RunList {
+    uint32_t bin[kRunList];
+    uint32_t val[kRunList];    // run length, then the first slot reserved for it
+    int n[kBinThreads / 64];   // listed runs per wave
+};
+
 // (w_k - w) / dw for plane k, each operation rounded on its own: the Kaiser-Bessel
 // window is cut off at |d| = S_w / 2 with a non-zero value there, and the data's own
 // extreme w values fall exactly on plane edges, so d must round as the method's
@@ -697,38 +733,60 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
                                                          int n_cls, void *__restrict__ records,
                                                          uint32_t capacity, uint32_t *overflow) {
     __shared__ ScatterLdsW<VT, WK> L;
+    __shared__ RunList R;
     const int64_t blk = bin_block(blockIdx.x, gridDim.x);
     const int64_t s0 = blk * kBinStretches;
     const StretchPos pos = stretch_pos(g, (uint32_t)(s0 + (int)threadIdx.x % kBinStretches));
+    // every element of a thread belongs to its stretch: one channel, one image
+    const int img = (g.n_img > 1) ? pos.c : 0;
+    const ImgState sti = st[img];
+    const double sc = g.chan_scale[pos.c];
     Slice sl[kPerThread];
     uint8_t mk[kPerThread];
-    double u[kPerThread], v[kPerThread], w[kPerThread], vr[kPerThread], vi[kPerThread], wt[kPerThread];
+    double u[kPerThread], v[kPerThread], w[kPerThread];
+    VT vr[kPerThread], vi[kPerThread], wt[kPerThread];   // in the visibilities' own type
+    // every load issued before any is used (a slot past the data reads element 0 and
+    // is masked afterwards); without weights the load goes to the visibilities, which
+    // hold at least as many elements, and is replaced by 1
+    const VT *wsrc = wts ? (const VT *)wts : (const VT *)vis;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
         tile_slot(k, t, s);
         sl[k] = slice_at(g, pos, t);
-        mk[k] = sl[k].ok ? mask[sl[k].e] : 0;
         const int64_t r = sl[k].ok ? sl[k].r : 0;
         const int64_t e = sl[k].ok ? sl[k].e : 0;
-        u[k] = mk[k] ? uvw[3 * r] : 0.0;
-        v[k] = mk[k] ? uvw[3 * r + 1] : 0.0;
-        w[k] = mk[k] ? uvw[3 * r + 2] : 0.0;
-        vr[k] = vi[k] = wt[k] = 0.0;
-        if (mk[k]) ElemIO<VT, VT>::load(vis, wts, e, vr[k], vi[k], wt[k]);
+        mk[k] = mask[e];
+        u[k] = uvw[3 * r];
+        v[k] = uvw[3 * r + 1];
+        w[k] = uvw[3 * r + 2];
+        vr[k] = ((const VT *)vis)[2 * e];
+        vi[k] = ((const VT *)vis)[2 * e + 1];
+        wt[k] = wsrc[e];
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        uint32_t m = mk[k];
+        pin(m);
+        pin(u[k]);
+        pin(v[k]);
+        pin(w[k]);
+        pin(vr[k]);
+        pin(vi[k]);
+        pin(wt[k]);
+        if (!wts) wt[k] = VT(1);
+        mk[k] = sl[k].ok ? (uint8_t)m : (uint8_t)0;
     }
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         int t, s;
         tile_slot(k, t, s);
-        const int img = (g.n_img > 1) ? sl[k].c : 0;
         uint32_t pk = kNoKey;
         Placed pl;
-        if (mk[k] && place_vals(g, st[img], u[k], v[k], w[k], g.chan_scale[sl[k].c], pl)) {
+        if (mk[k] && place_vals(g, sti, u[k], v[k], w[k], sc, pl)) {
             pk = pack_placed(g, img, pl);
             if constexpr (WK) {
-                const ImgState &si = st[img];
-                if (pk != kNoKey && si.dw > 0.0) {
+                if (pk != kNoKey && sti.dw > 0.0) {
                     pk |= kSpread;
                     L.wv[t * kPitch + s] = pl.w;
                     L.kimg[t * kPitch + s] = (uint32_t)pl.k | ((uint32_t)img << 16);
@@ -751,8 +809,8 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
             } else {
                 L.a[q] = quant_frac(fx) | ((uint32_t)li0 << kFracBits);
                 L.b[q] = quant_frac(fy) | ((uint32_t)lj0 << kFracBits);
-                L.re[q] = (float)wt[k] * (float)vr[k];
-                L.im[q] = pl.flip ? -((float)wt[k] * (float)vi[k]) : (float)wt[k] * (float)vi[k];
+                L.re[q] = wt[k] * vr[k];
+                L.im[q] = pl.flip ? -(wt[k] * vi[k]) : wt[k] * vi[k];
             }
         }
     }
@@ -795,6 +853,36 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
             ((RecF32 *)records)[slot] = rec;
         }
     };
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // list the runs of the wave's stretches (heads in lane order, slots in order)
+    int nr = 0;
+    for (int j = 0; j < kPerWave; ++j) {
+        const int s = wave * kPerWave + j;
+        const uint32_t pk = L.pk[lane * kPitch + s];
+        Keys ks;
+        unpack_keys(pk, g.NT, ks);
+        const int hw = WK ? g.w_h : 0;
+        for (int dk = -hw; dk <= hw; ++dk) {
+            const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
+            for_each_run(kd, lane, [&](int, uint32_t bin, uint32_t len, int, uint32_t, bool head, bool) {
+                const unsigned long long heads = __ballot(head);
+                const int e = nr + __popcll(heads & below);
+                if (head && e < kWaveRuns) {
+                    R.bin[wave * kWaveRuns + e] = bin;
+                    R.val[wave * kWaveRuns + e] = len;
+                }
+                nr += __popcll(heads);
+            });
+        }
+    }
+    if (lane == 0) R.n[wave] = nr < kWaveRuns ? nr : kWaveRuns;
+    __syncthreads();
+    // reserve the slots of every listed run of the workgroup at once
+    for (int e = threadIdx.x; e < kRunList; e += kBinThreads)
+        if (e % kWaveRuns < R.n[e / kWaveRuns]) R.val[e] = atomicAdd(&cursor[R.bin[e]], R.val[e]);
+    __syncthreads();
+    // the same walk again: every lane's record goes to its run's first slot + its rank
+    nr = 0;
     for (int j = 0; j < kPerWave; ++j) {
         const int s = wave * kPerWave + j;
         const int q = lane * kPitch + s;
@@ -813,10 +901,16 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
             const Keys kd = WK ? plane_keys(ks, pk, dk, g.logNT) : ks;
             for_each_run(kd, lane, [&](int, uint32_t bin, uint32_t len, int hl, uint32_t rank, bool head,
                                        bool mine) {
-                uint32_t base = 0u;
-                if (head) base = atomicAdd(&cursor[bin], len);
-                base = (uint32_t)__shfl((int)base, hl);
+                const unsigned long long heads = __ballot(head);
+                // list entry of the run this lane belongs to (its head's)
+                const int eh = nr + __popcll(heads & ((1ull << hl) - 1ull));
+                nr += __popcll(heads);
+                const bool listed = eh < kWaveRuns;
+                uint32_t late = 0u;
+                if (head && !listed) late = atomicAdd(&cursor[bin], len);
+                late = (uint32_t)__shfl((int)late, hl);
                 if (!mine) return;
+                const uint32_t base = listed ? R.val[wave * kWaveRuns + eh] : late;
                 put(q, pk, bin, base + rank, gw);
             });
         }

@@ -44,6 +44,23 @@ template <> struct BlockRows<double> { static constexpr int value = 2; };
 // complex points would not fit in LDS.
 constexpr int kBigN = 8192;
 
+// Extra words at the end of each LDS row.  A wave holds points of several rows (the
+// lowest lane bits pick the row), and rows whose pitch is a multiple of the bank count
+// would put the same point of every row on one bank; these offsets, chosen by counting
+// the conflicts of every exchange of fft_line for 32 and 64 four-byte banks, spread
+// the rows over the banks (pass 1: 4x fewer conflicted cycles at N = 4096).
+template <typename T, int N, bool PASS2>
+__host__ __device__ constexpr int row_pad() {
+    if (N >= kBigN) return 0;
+    if constexpr (sizeof(T) == 4) {
+        if (!PASS2) return N == 64 ? 1 : N == 4096 ? 8 : N >= 512 ? 16 : 0;
+        return N == 64 ? 1 : N == 128 || N == 256 ? 4 : N == 512 ? 8 : N >= 1024 ? 16 : 0;
+    } else {
+        if (!PASS2) return N == 64 ? 1 : N == 4096 ? 8 : N >= 512 ? 16 : 0;
+        return N == 64 || N == 128 || N == 256 ? 2 : N == 512 ? 4 : N == 1024 ? 5 : N == 2048 ? 16 : 0;
+    }
+}
+
 // transforms per workgroup: at least B, enough threads for 4 waves when N is small,
 // at most 1024 threads
 // B, the rows of a block of the intermediate layout, is BlockRows unless fewer rows
@@ -59,7 +76,7 @@ struct Shape {
     static constexpr int NTR = NTR1 * P > 1024 ? 1024 / P : NTR1;  // transforms per workgroup
     static constexpr int B = B0 < NTR ? B0 : NTR;
     static constexpr int THREADS = NTR * P;
-    static constexpr int NPAD = N + N / 16;           // LDS row length with padding
+    static constexpr int NPAD = N + N / 16 + row_pad<T, N, false>();   // LDS row length
     static constexpr bool SPLIT = N >= kBigN;         // exchange one component at a time
     static constexpr int LDS_ROWS = SPLIT ? NTR : 2 * NTR;
 };
@@ -74,7 +91,7 @@ struct Shape2 {
     static constexpr int cap = (sizeof(T) == 4 ? 512 : 256) / P;
     static constexpr int NTR = Shape<T, N>::NTR < cap ? Shape<T, N>::NTR : (cap > 0 ? cap : 1);
     static constexpr int THREADS = NTR * P;
-    static constexpr int NPAD = N + N / 16;
+    static constexpr int NPAD = N + N / 16 + row_pad<T, N, true>();
     static constexpr bool SPLIT = N >= kBigN;
     static constexpr int LDS_ROWS = SPLIT ? NTR : 2 * NTR;
 };

@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kGridThreads = 256;
 constexpr int kRunCap = 16;
-constexpr int kFlushLanes = 56;
+constexpr int kFlushLanes = 60;
 
 template <typename T>
 struct RecTraits;
@@ -131,7 +131,10 @@ __device__ __forceinline__ size_t cell_index(const JobGeom &g, int img, int kl, 
     return plane + (transposed ? ((size_t)i * g.N + j) : ((size_t)j * g.N + i));
 }
 
-// LDS tile: TP = T+1 columns per row, separate real / imaginary arrays.
+// LDS tile: separate real / imaginary FP64 arrays of T rows of TP = T + 8 cells, the
+// last 8 of each row padding, and 8 more cells before the first row, so that every
+// column from -8 to T + 7 of a row lies inside the arrays (columns outside the tile
+// land in padding, which is never read).
 //
 // Each lane takes a contiguous stretch of the work item's records.  The
 // binning pass keeps the records of one track (one baseline and channel over
@@ -157,13 +160,14 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                                                         const typename RecTraits<T>::Rec *__restrict__ rec,
                                                         C2<T> *__restrict__ grid, int transposed,
                                                         int accumulate) {
-    constexpr int TP = TT + 1;
+    constexpr int TP = TT + 8;
+    constexpr int L0 = 8;                  // cell (j, i) is element L0 + j * TP + i
     constexpr int H = (SS - 1) / 2;
     constexpr uint32_t chunk = kGridChunk;
     // the tile sums many contributions per cell: kept in FP64 for every mesh type,
     // rounded once when the cell is stored
-    __shared__ double s_re[TT * TP];
-    __shared__ double s_im[TT * TP];
+    __shared__ double s_re[TT * TP + 2 * L0];
+    __shared__ double s_im[TT * TP + 2 * L0];
     __shared__ uint32_t s_item;
     const uint32_t n_items = wt->n_items;
     for (;;) {
@@ -180,7 +184,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     const uint32_t r0 = offsets[b] + c * chunk;
     const uint32_t r1 = offsets[b] + min(cnt, (c + 1) * chunk);
 
-    for (int i = threadIdx.x; i < TT * TP; i += blockDim.x) {
+    for (int i = threadIdx.x; i < TT * TP + 2 * L0; i += blockDim.x) {
         s_re[i] = 0.0;
         s_im[i] = 0.0;
     }
@@ -200,18 +204,32 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     constexpr int W = ACC ? SS + 2 : 1;
     T ar[W][W], ai[W][W];
     int ax = 0, ay = 0, lx = 0, hx = 0, ly = 0, hy = 0, run = 0;
+    // The flush adds the cells of the window the run used (rows ly .. hy + S - 1,
+    // columns lx .. hx + S - 1) that lie in the tile rows.  Columns outside the tile
+    // need no test (columns -7 .. T + 6 occur, the nearest cell lying within S/2 of the
+    // tile, and fall into the padding), so the per-cell condition is the AND of a row
+    // and a column condition, each evaluated once per flush.
     auto flush = [&]() {
         if constexpr (ACC) {
+            bool col_used[W];
+#pragma unroll
+            for (int a = 0; a < W; ++a) col_used[a] = a >= lx && a < SS + hx;
 #pragma unroll
             for (int bb = 0; bb < W; ++bb) {
-                int j = ay + bb - H;
+                const int j = ay + bb - H;
+                if (bb >= ly && bb < SS + hy && j >= 0 && j < TT) {
+                    double *pr = s_re + (L0 + j * TP + ax - H);
+                    double *pm = s_im + (L0 + j * TP + ax - H);
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        if (col_used[a]) {
+                            atomicAdd(pr + a, (double)ar[bb][a]);
+                            atomicAdd(pm + a, (double)ai[bb][a]);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int a = 0; a < W; ++a) {
-                    int i = ax + a - H;
-                    if (bb >= ly && bb < SS + hy && a >= lx && a < SS + hx && j >= 0 && j < TT && i >= 0 && i < TT) {
-                        atomicAdd(&s_re[j * TP + i], (double)ar[bb][a]);
-                        atomicAdd(&s_im[j * TP + i], (double)ai[bb][a]);
-                    }
                     ar[bb][a] = T(0);
                     ai[bb][a] = T(0);
                 }
@@ -343,8 +361,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
             for (int a = 0; a < SS; ++a) {
                 int i = li + a - H;
                 if (i < 0 || i >= TT) continue;
-                atomicAdd(&s_re[j * TP + i], (double)(wr * gx[a]));
-                atomicAdd(&s_im[j * TP + i], (double)(wi * gx[a]));
+                atomicAdd(&s_re[L0 + j * TP + i], (double)(wr * gx[a]));
+                atomicAdd(&s_im[L0 + j * TP + i], (double)(wi * gx[a]));
             }
         }
     }
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         int fast = t % TT, slow = t / TT;
         int i, j;
         if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
-        T vr = (T)s_re[j * TP + i], vi = (T)s_im[j * TP + i];
+        T vr = (T)s_re[L0 + j * TP + i], vi = (T)s_im[L0 + j * TP + i];
         size_t idx = cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0);
         if (split) {
             atomicAdd(&grid[idx].x, vr);
@@ -566,12 +584,12 @@ void launch_grid(const JobGeom &g, bool f64, const uint32_t *counts, const uint3
         dispatch_grid<float>(g, counts, offsets, items, wt, n_wg, records, grid, transposed, accumulate, s);
 }
 
-// Resident workgroups per CU: the FP64 LDS tile, 2 x T x (T+1) x 8 bytes, limits them
+// Resident workgroups per CU: the FP64 LDS tile, 2 x (T (T+8) + 16) x 8 bytes, limits them
 // (two for T = 64, eight for T <= 32, with four waves each); a launch of that many
 // per CU keeps every CU busy until the list runs dry.
 unsigned grid_workgroups(bool f64, int T, size_t max_items, int n_cu) {
     (void)f64;
-    const size_t lds = 2u * (size_t)T * (T + 1) * 8u + 64u;
+    const size_t lds = 2u * ((size_t)T * (T + 8) + 16u) * 8u + 64u;
     size_t per_cu = std::min<size_t>((size_t)(160 * 1024) / lds, 8);
     per_cu = std::max<size_t>(per_cu, 1);
     const size_t want = per_cu * (size_t)std::max(n_cu, 1);
