@@ -488,9 +488,12 @@ __device__ __forceinline__ int64_t bin_block(int64_t bid, int64_t n_blocks) {
     return (bid % kXcd) * (n_blocks / kXcd) + bid / kXcd;
 }
 
+// Row and element of one time slice of one stretch, in 32-bit arithmetic like the
+// stretch position: a job holds at most 2^29 visibilities (the values of a slice past
+// the data are not used)
 struct Slice {
     int c;
-    int64_t r, e;   // row and element of one time slice of one stretch
+    uint32_t r, e;
     bool ok;
 };
 
@@ -517,10 +520,10 @@ __device__ __forceinline__ StretchPos stretch_pos(const JobGeom &g, uint32_t str
 __device__ __forceinline__ Slice slice_at(const JobGeom &g, const StretchPos &p, int t_in) {
     Slice sl;
     sl.c = p.c;
-    const int64_t t = (int64_t)p.tb * kStretch + t_in;
-    sl.r = t * g.P + p.b;
-    sl.ok = p.ok && t < g.n_t && sl.r < g.n_rows;
-    sl.e = sl.r * g.n_chan + sl.c;
+    const uint32_t t = p.tb * (uint32_t)kStretch + (uint32_t)t_in;
+    sl.r = t * (uint32_t)g.P + p.b;
+    sl.ok = p.ok && t < (uint32_t)g.n_t && sl.r < (uint32_t)g.n_rows;
+    sl.e = sl.r * (uint32_t)g.n_chan + (uint32_t)sl.c;
     return sl;
 }
 
@@ -552,7 +555,7 @@ __device__ __forceinline__ void for_each_run(const Keys &ks, int lane, F &&f) {
         // common case along a track: every lane holding slot i holds the same bin, and
         // those lanes (in time order, gaps allowed) form one run
         const int fl = __ffsll((long long)hm) - 1;
-        const uint32_t k0 = (uint32_t)__shfl((int)key, fl);
+        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, fl);   // fl is uniform
         if (__ballot(has && key != k0) == 0ull) {
             const uint32_t rank = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
             const bool head = lane == fl;
@@ -616,8 +619,8 @@ __global__ __launch_bounds__(kBinThreads) void k_count(JobGeom g, const double *
         int t, s;
         tile_slot(k, t, s);
         sl[k] = slice_at(g, pos, t);
-        const int64_t r = sl[k].ok ? sl[k].r : 0;
-        const int64_t e = sl[k].ok ? sl[k].e : 0;
+        const uint32_t r = sl[k].ok ? sl[k].r : 0u;
+        const uint32_t e = sl[k].ok ? sl[k].e : 0u;
         mk[k] = mask[e];
         u[k] = uvw[3 * r];
         v[k] = uvw[3 * r + 1];
@@ -754,8 +757,8 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
         int t, s;
         tile_slot(k, t, s);
         sl[k] = slice_at(g, pos, t);
-        const int64_t r = sl[k].ok ? sl[k].r : 0;
-        const int64_t e = sl[k].ok ? sl[k].e : 0;
+        const uint32_t r = sl[k].ok ? sl[k].r : 0u;
+        const uint32_t e = sl[k].ok ? sl[k].e : 0u;
         mk[k] = mask[e];
         u[k] = uvw[3 * r];
         v[k] = uvw[3 * r + 1];
