@@ -391,22 +391,40 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     }
 }
 
+// Each workgroup checks kGridThreads consecutive bins (one per thread) and clears,
+// together, the tiles of those that need it: split bins (their chunks add with
+// atomics) and, with zero_empty, empty bins.  Few bins need it on the imaging path,
+// so most workgroups only read their counts.
 template <typename T, int TT>
 __global__ __launch_bounds__(kGridThreads) void k_zero_tiles(JobGeom g, const uint32_t *__restrict__ counts,
-                                                             uint32_t chunk, int zero_empty,
+                                                             size_t n_bins, uint32_t chunk, int zero_empty,
                                                              C2<T> *__restrict__ grid, int transposed) {
-    const uint32_t b = blockIdx.x;
-    const uint32_t c = counts[b];
-    if (!(c > chunk || (zero_empty && c == 0))) return;
-    int img, kl, ty, tx;
-    bin_coords(g, b, img, kl, ty, tx);
-    if (kl < g.stack_k0 || kl >= g.stack_k0 + g.stack_pl) return;   // not in this pass
-    const int gi0 = tx * TT, gj0 = ty * TT;
-    for (int t = threadIdx.x; t < TT * TT; t += blockDim.x) {
-        int fast = t % TT, slow = t / TT;
-        int i, j;
-        if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
-        grid[cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0)] = C2<T>{T(0), T(0)};
+    __shared__ uint32_t s_bins[kGridThreads];
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0u;
+    __syncthreads();
+    const size_t b = (size_t)blockIdx.x * kGridThreads + threadIdx.x;
+    if (b < n_bins) {
+        const uint32_t c = counts[b];
+        if (c > chunk || (zero_empty && c == 0)) {
+            int img, kl, ty, tx;
+            bin_coords(g, (uint32_t)b, img, kl, ty, tx);
+            if (kl >= g.stack_k0 && kl < g.stack_k0 + g.stack_pl)   // in this pass
+                s_bins[atomicAdd(&s_n, 1u)] = (uint32_t)b;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = s_n;
+    for (uint32_t k = 0; k < n; ++k) {
+        int img, kl, ty, tx;
+        bin_coords(g, s_bins[k], img, kl, ty, tx);
+        const int gi0 = tx * TT, gj0 = ty * TT;
+        for (int t = threadIdx.x; t < TT * TT; t += blockDim.x) {
+            int fast = t % TT, slow = t / TT;
+            int i, j;
+            if (transposed) { j = fast; i = slow; } else { i = fast; j = slow; }
+            grid[cell_index<T>(g, img, kl, gi0 + i, gj0 + j, transposed != 0)] = C2<T>{T(0), T(0)};
+        }
     }
 }
 
@@ -508,13 +526,15 @@ void dispatch_grid(const JobGeom &g, const uint32_t *counts, const uint32_t *off
 template <typename T>
 void dispatch_zero(const JobGeom &g, const uint32_t *counts, uint32_t chunk, int ze, void *grid,
                    bool transposed, hipStream_t s) {
-    unsigned n_bins = (unsigned)((size_t)g.n_img * g.n_pl * g.NT * g.NT);
+    const size_t n_bins = (size_t)g.n_img * g.n_pl * g.NT * g.NT;
+    const unsigned blocks = (unsigned)((n_bins + kGridThreads - 1) / kGridThreads);
+    if (blocks == 0) return;
     C2<T> *gp = (C2<T> *)grid;
     int tr = transposed ? 1 : 0;
     switch (g.T) {
-    case 16: k_zero_tiles<T, 16><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
-    case 32: k_zero_tiles<T, 32><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
-    case 64: k_zero_tiles<T, 64><<<n_bins, kGridThreads, 0, s>>>(g, counts, chunk, ze, gp, tr); break;
+    case 16: k_zero_tiles<T, 16><<<blocks, kGridThreads, 0, s>>>(g, counts, n_bins, chunk, ze, gp, tr); break;
+    case 32: k_zero_tiles<T, 32><<<blocks, kGridThreads, 0, s>>>(g, counts, n_bins, chunk, ze, gp, tr); break;
+    case 64: k_zero_tiles<T, 64><<<blocks, kGridThreads, 0, s>>>(g, counts, n_bins, chunk, ze, gp, tr); break;
     default: break;
     }
 }
