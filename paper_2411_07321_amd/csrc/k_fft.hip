@@ -231,13 +231,25 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
         }
         }
         // twiddles e^{+2 pi i (t mod ns) s / (ns E)} = W_N[(t mod ns) * s * N/(ns E)]
-        int step = (t % ns) * (N / (ns * E));
+        // (one running address, advanced by the step, instead of a product per point)
+        const int step = (t % ns) * (N / (ns * E));
+        const C2<T> *twp = tw;
 #pragma unroll
-        for (int s = 1; s < E; ++s) v[s] = cmul(v[s], tw[step * s]);
+        for (int s = 1; s < E; ++s) {
+            twp += step;
+            v[s] = cmul(v[s], *twp);
+        }
         dft_reg<T, E, 1>(v, 0);
         ns *= E;
     }
 }
+
+// Planes whose bytes fit 32-bit offsets: their point loads take a 32-bit byte offset
+// from the plane's (workgroup-uniform) base instead of a 64-bit address per point.
+template <typename T, int N>
+struct PlaneOff {
+    static constexpr bool ok = (uint64_t)N * N * sizeof(C2<T>) <= (1ull << 32);
+};
 
 // ---------------------------------------------------------------- pass 1
 template <typename T, int N>
@@ -274,13 +286,29 @@ __global__ __launch_bounds__((Shape<T, N>::THREADS)) void k_pass1(C2<T> *__restr
         on = lm & 0xffffu;
     }
     C2<T> v[E];
+    if constexpr (PlaneOff<T, N>::ok) {
+        // 32-bit byte offsets from the plane; a dead point reads the thread's first
+        // point (a cached line) and is zeroed, so no load is branched around
+        const char *base = (const char *)X;
+        const uint32_t off0 = (uint32_t)(a * N + t) * (uint32_t)sizeof(C2<T>);
+        constexpr uint32_t step = (uint32_t)P * (uint32_t)sizeof(C2<T>);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        int b = t + m * P;
-        C2<T> z = C2<T>{T(0), T(0)};
-        if ((on >> m) & 1u) z = X[(size_t)a * N + b];
-        if ((a + b) & 1) z = C2<T>{-z.x, -z.y};
-        v[m] = z;
+        for (int m = 0; m < E; ++m) {
+            const bool live = (on >> m) & 1u;
+            C2<T> z = *(const C2<T> *)(base + (live ? off0 + (uint32_t)m * step : off0));
+            z = live ? z : C2<T>{T(0), T(0)};
+            if ((a + t + m * P) & 1) z = C2<T>{-z.x, -z.y};
+            v[m] = z;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            int b = t + m * P;
+            C2<T> z = C2<T>{T(0), T(0)};
+            if ((on >> m) & 1u) z = X[(size_t)a * N + b];
+            if ((a + b) & 1) z = C2<T>{-z.x, -z.y};
+            v[m] = z;
+        }
     }
     T *lre = lds + (size_t)r * SH::NPAD;
     T *lim = SH::SPLIT ? lre : lds + (size_t)(NTR + r) * SH::NPAD;
