@@ -231,14 +231,9 @@ __device__ __forceinline__ void fft_line(C2<T> *v, T *lre, T *lim, int t, const 
         }
         }
         // twiddles e^{+2 pi i (t mod ns) s / (ns E)} = W_N[(t mod ns) * s * N/(ns E)]
-        // (one running address, advanced by the step, instead of a product per point)
-        const int step = (t % ns) * (N / (ns * E));
-        const C2<T> *twp = tw;
+        int step = (t % ns) * (N / (ns * E));
 #pragma unroll
-        for (int s = 1; s < E; ++s) {
-            twp += step;
-            v[s] = cmul(v[s], *twp);
-        }
+        for (int s = 1; s < E; ++s) v[s] = cmul(v[s], tw[step * s]);
         dft_reg<T, E, 1>(v, 0);
         ns *= E;
     }

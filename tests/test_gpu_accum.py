@@ -1,4 +1,4 @@
-"""Chunked imaging (data loaded chunk after chunk by time or by frequency, Sec. 6):
+"""Chunked imaging (data loaded chunk after chunk by time or by frequency, Sec. 5):
 an accumulator keeps the w-stack resident while chunks are binned and gridded into
 it, then transforms and w-corrects once.  Its image must equal the FP64 oracle's
 image of all chunks together: rel-L2 <= 1e-12 (FP64 mesh), <= 1e-5 on the raw
