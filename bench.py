@@ -439,6 +439,11 @@ def main():
             "copy_GBps": round(probes["copy_bytes_per_s"] / 1e9, 1),
             "note": "measured by wsg_probe_rates: FP64 LDS atomic adds (no return, no bank "
                     "conflicts) and a 2 GiB 16-byte streaming copy (read + write bytes)"}
+        lds = wsg.probe_lds(0)
+        result["device_probes"]["lds_atomic_adds_per_s"] = {k: float(f"{v:.4g}") for k, v in lds.items()}
+        result["device_probes"]["note_lds"] = (
+            "wsg_probe_lds: LDS atomic adds without a returned value, FP64 and FP32 with every "
+            "lane on its own bank, FP64 with 2 and 16 lanes per bank pair")
         result["path_roofline"]["frac_of_measured_copy"] = round(
             path_gbs / (probes["copy_bytes_per_s"] / 1e9), 4)
         progress(f"probes: LDS f64 adds {probes['lds_f64_adds_per_s']:.3e}/s, copy "

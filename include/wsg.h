@@ -401,6 +401,14 @@ wsg_status wsg_trim(wsg_ctx *ctx);
 wsg_status wsg_probe_rates(int device, uint64_t copy_bytes, double *lds_f64_adds_per_s,
                            double *copy_bytes_per_s);
 
+/* LDS atomic add rate on `device` (adds per second, best of three timed launches, no
+ * returned value), by kind: 0 FP64 with every lane on its own bank pair (as in
+ * wsg_probe_rates), 1 FP32 with every lane on its own bank, 2 FP64 with two lanes per
+ * bank pair, 3 FP64 with sixteen lanes per bank pair.  The gridder's flushes are FP64
+ * adds at positions that collide on banks; kind 1 is the rate an FP32 tile would see.
+ * WSG_EINVAL for another kind or a NULL output; waits for the device. */
+wsg_status wsg_probe_lds(int device, int32_t kind, double *adds_per_s);
+
 #ifdef __cplusplus
 }
 #endif

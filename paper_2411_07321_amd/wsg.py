@@ -31,7 +31,7 @@ SYMBOLS = ("wsg_create", "wsg_destroy", "wsg_strerror", "wsg_last_error", "wsg_s
            "wsg_server_wait", "wsg_server_memory", "wsg_trim", "wsg_context_stream",
            "wsg_accum_begin", "wsg_accum_footprint", "wsg_accum_add", "wsg_accum_finish",
            "wsg_accum_destroy", "wsg_submit", "wsg_poll", "wsg_wait", "wsg_cancel",
-           "wsg_server_cancel", "wsg_probe_rates")
+           "wsg_server_cancel", "wsg_probe_rates", "wsg_probe_lds")
 
 
 class WsgError(RuntimeError):
@@ -128,6 +128,7 @@ def load() -> ctypes.CDLL:
         lib.wsg_probe_rates.argtypes = [ctypes.c_int, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
+        lib.wsg_probe_lds.argtypes = [ctypes.c_int, S, ctypes.POINTER(ctypes.c_double)]
         lib.wsg_server_cancel.argtypes = [P, ctypes.c_uint64]
         lib.wsg_stage_grid.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(Vis), P, S, P,
                                        ctypes.POINTER(Stats)]
@@ -164,7 +165,7 @@ def load() -> ctypes.CDLL:
                      "wsg_server_submit", "wsg_server_poll", "wsg_server_wait",
                      "wsg_server_memory", "wsg_trim", "wsg_accum_begin", "wsg_accum_footprint",
                      "wsg_accum_add", "wsg_accum_finish", "wsg_submit", "wsg_poll", "wsg_wait",
-                     "wsg_cancel", "wsg_server_cancel", "wsg_probe_rates"):
+                     "wsg_cancel", "wsg_server_cancel", "wsg_probe_rates", "wsg_probe_lds"):
             getattr(lib, name).restype = S
         lib.wsg_n_images.restype = S
         _lib = lib
@@ -624,3 +625,20 @@ def probe_rates(device: int = 0, copy_bytes: int = 1 << 31) -> dict:
     if st != OK:
         raise WsgError(st, f"wsg_probe_rates: {strerror(st)}")
     return {"lds_f64_adds_per_s": lds.value, "copy_bytes_per_s": cp.value}
+
+
+# kinds of wsg_probe_lds
+LDS_PROBES = {"f64": 0, "f32": 1, "f64_2way": 2, "f64_16way": 3}
+
+
+def probe_lds(device: int = 0) -> dict:
+    """wsg_probe_lds for every kind: LDS atomic adds per second (FP64 and FP32 with
+    every lane on its own bank, FP64 with 2 and 16 lanes per bank pair)."""
+    out = {}
+    for name, kind in LDS_PROBES.items():
+        r = ctypes.c_double(0.0)
+        st = load().wsg_probe_lds(int(device), int(kind), ctypes.byref(r))
+        if st != OK:
+            raise WsgError(st, f"wsg_probe_lds: {strerror(st)}")
+        out[name] = r.value
+    return out
