@@ -227,8 +227,8 @@ def chunked(args, d, prm, ctx, out):
 
 def f64_job(args, d, n) -> dict:
     """The same job at the paper's own arithmetic: complex128 visibilities and mesh, FP64
-    transform, phase and image (FP64 weights), binning tile 32 (the library's choice for
-    the FP64 LDS tile).  Its own context; 1 warm-up and 3 timed jobs."""
+    transform, phase and image (FP64 weights), the library's default binning tile (64).
+    Its own context; 1 warm-up and 3 timed jobs."""
     import numpy as np
     import torch
     from paper_2411_07321_amd import wsg
@@ -252,7 +252,7 @@ def f64_job(args, d, n) -> dict:
     progress(f"f64 job: {ms:.2f} ms/job")
     return {"ms_per_step": round(ms, 3), "value": n_used / (ms * 1e-3), "unit": "visibilities/s",
             "dtype": "c128 mesh+FFT, f64 phase and image (the paper's arithmetic)",
-            "tile": int(prm.tile) if prm.tile else 32,
+            "tile": int(prm.tile) if prm.tile else 64,
             "stages_ms": {k: round(float(np.mean([s[k] for s in sts])), 3) for k in STAGES}}
 
 

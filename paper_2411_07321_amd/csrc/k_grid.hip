@@ -86,6 +86,25 @@ __device__ __forceinline__ void gauss_line(float f, float cl2, const float *q, f
     }
 }
 
+// The same recurrence in FP64 (q[k] = e^{-c k^2}, c = 1/(2 sigma^2)): three
+// exponentials per axis instead of S, a few ulps from a direct evaluation.
+template <int SS>
+__device__ __forceinline__ void gauss_line64(double f, double c, const double *q, double *g) {
+    constexpr int H = (SS - 1) / 2;
+    const double e0 = exp(-(f * f) * c);
+    const double r = exp((2.0 * f) * c);
+    const double ri = exp((-2.0 * f) * c);
+    g[H] = e0;
+    double pp = e0, pm = e0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        pp *= r;
+        pm *= ri;
+        g[H + k] = pp * q[k];
+        g[H - k] = pm * q[k];
+    }
+}
+
 // Kaiser-Bessel taps g[a] = G((a - H) - f), a = 0..SS-1, on an FP32 mesh: tap a and
 // tap SS-1-a are one fitted polynomial at x = 2f and at -x, E(x^2) +- x O(x^2).
 template <int SS>
@@ -201,7 +220,9 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
     // nearest cell lies at offset 0, 1 or 2 from the anchor in each axis join the
     // run, and [lx, hx] x [ly, hy] are the offsets used (the flush adds only the
     // window's columns lx .. hx + S - 1 and rows ly .. hy + S - 1)
-    constexpr int W = ACC ? SS + 2 : 1;
+    // (FP64 mesh: runs of one nearest cell, an S x S window of FP64 registers)
+    constexpr bool RUN3 = ACC && sizeof(T) == 4;
+    constexpr int W = ACC ? (RUN3 ? SS + 2 : SS) : 1;
     T ar[W][W], ai[W][W];
     int ax = 0, ay = 0, lx = 0, hx = 0, ly = 0, hy = 0, run = 0;
     // The flush adds the cells of the window the run used (rows ly .. hy + S - 1,
@@ -245,7 +266,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                 ai[bb][a] = T(0);
             }
     }
-    if constexpr (ACC) {
+    if constexpr (RUN3) {
         // exp(-k^2/(2 sigma^2)) for k = 1..H, for gauss_line
         const float cl2 = (float)g.inv2s2 * 1.4426950408889634f;
         float q[H + 1];
@@ -313,6 +334,66 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                     hx = max(hx, dx);
                     ly = min(ly, dy);
                     hy = max(hy, dy);
+                    ++run;
+                    if (pos == q1) pend = true;
+                } else {
+                    pend = true;
+                }
+            }
+            const unsigned long long pm = __ballot(pend);
+            const unsigned long long lm = __ballot(pos < q1 && !pend);
+            if (pm == 0 && lm == 0) break;
+            if (__popcll(pm) >= kFlushLanes || lm == 0) {
+                if (pend) {
+                    flush();
+                    run = 0;
+                    pend = false;
+                }
+            }
+        }
+    } else if constexpr (ACC) {
+        // FP64 mesh: the same parking and wave-level flushes, with runs of records that
+        // share one nearest cell summed in an S x S window of FP64 registers (a 3 x 3
+        // block would need (S+2)^2 complex doubles).  Taps from the three-exponential
+        // recurrence in FP64 (Gaussian) or the window's series (Kaiser-Bessel).
+        double q[H + 1];
+#pragma unroll
+        for (int k = 0; k <= H; ++k) q[k] = exp(-(double)(k * k) * g.inv2s2);
+        uint32_t pos = q0;
+        bool pend = false;
+        RecF64 nx{};   // the lane's next record, loaded ahead
+        if (pos < q1) nx = rec[pos];
+        for (;;) {
+            if (pos < q1 && !pend) {
+                const int li = nx.li, lj = nx.lj;
+                if (run == 0) {
+                    ax = li;
+                    ay = lj;
+                }
+                if (run < kRunCap && li == ax && lj == ay) {
+                    const double fx = nx.fx, fy = nx.fy, re = nx.re, im = nx.im;
+                    ++pos;
+                    if (pos < q1) nx = rec[pos];
+                    double gx[SS], gy[SS];
+                    if constexpr (KIND == 0) {
+                        gauss_line64<SS>(fx, g.inv2s2, q, gx);
+                        gauss_line64<SS>(fy, g.inv2s2, q, gy);
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < SS; ++a) {
+                            gx[a] = kb_series_value((double)(a - H) - fx, g.kb_series, g.kb_n, SS);
+                            gy[a] = kb_series_value((double)(a - H) - fy, g.kb_series, g.kb_n, SS);
+                        }
+                    }
+#pragma unroll
+                    for (int bb = 0; bb < SS; ++bb) {
+                        const double wr = re * gy[bb], wi = im * gy[bb];
+#pragma unroll
+                        for (int a = 0; a < SS; ++a) {
+                            ar[bb][a] += wr * gx[a];
+                            ai[bb][a] += wi * gx[a];
+                        }
+                    }
                     ++run;
                     if (pos == q1) pend = true;
                 } else {
@@ -488,7 +569,7 @@ template <typename T, int TT, int SS>
 void launch_tile(const JobGeom &g, unsigned n_wg, hipStream_t s, const uint32_t *counts,
                  const uint32_t *offsets, const uint2 *items, WorkTotals *wt,
                  const typename RecTraits<T>::Rec *r, C2<T> *gp, int tr, int acc) {
-    constexpr bool ACC = (sizeof(T) == 4) && SS <= 7;
+    constexpr bool ACC = SS <= 7;
     if (g.kernel == 1)
         k_grid<T, TT, SS, ACC, 1><<<n_wg, kGridThreads, 0, s>>>(g, counts, offsets, items, wt, r, gp, tr, acc);
     else

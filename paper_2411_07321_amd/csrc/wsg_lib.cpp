@@ -283,7 +283,10 @@ double kb_beta_w(const wsg_params *p) {
 int min_tile(int N) { return std::max(16, N / 256); }
 
 int default_tile(const wsg_params *p) {
-    int t = std::max(f64_mode(p) ? 32 : 64, min_tile(p->grid_n));
+    // 64: the FP64 LDS tile allows two workgroups per CU, as the registers do; the
+    // FP64 Kaiser-Bessel gridder's registers allow one at 64, so it takes 32
+    const bool kb64 = f64_mode(p) && p->kernel == WSG_KERNEL_KAISER_BESSEL;
+    int t = std::max(kb64 ? 32 : 64, min_tile(p->grid_n));
     return std::min(t, p->grid_n);
 }
 
