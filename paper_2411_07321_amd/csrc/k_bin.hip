@@ -64,30 +64,6 @@ __device__ __forceinline__ bool footprint_fits(double x, int N, int h, int &i0) 
     return true;
 }
 
-template <typename VT, typename WT>
-struct ElemIO;
-
-template <>
-struct ElemIO<double, double> {
-    static __device__ __forceinline__ void load(const void *vis, const void *wts, int64_t e,
-                                                double &vr, double &vi, double &w) {
-        const double *v = (const double *)vis;
-        vr = v[2 * e];
-        vi = v[2 * e + 1];
-        w = wts ? ((const double *)wts)[e] : 1.0;
-    }
-};
-template <>
-struct ElemIO<float, float> {
-    static __device__ __forceinline__ void load(const void *vis, const void *wts, int64_t e,
-                                                double &vr, double &vi, double &w) {
-        const float2 v = ((const float2 *)vis)[e];
-        vr = (double)v.x;
-        vi = (double)v.y;
-        w = wts ? (double)((const float *)wts)[e] : 1.0;
-    }
-};
-
 __device__ __forceinline__ bool is_finite(double a) { return isfinite(a); }
 
 // An empty statement that takes x and may change it: the compiler has to hold the
@@ -118,18 +94,9 @@ __device__ __forceinline__ bool valid_vals(const JobGeom &g, double um, double v
     return true;
 }
 
-// Every test except the w range (O2 of the method's reading).
-template <typename VT>
-__device__ __forceinline__ bool valid0(const JobGeom &g, const double *uvw, const void *vis,
-                                       const void *wts, const uint8_t *flags, int64_t e,
-                                       int64_t r, int c, bool &flagged, double &w_out,
-                                       double &wt) {
-    flagged = flags && flags[e];
-    if (flagged) return false;
-    double vr, vi;
-    ElemIO<VT, VT>::load(vis, wts, e, vr, vi, wt);
-    return valid_vals(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], g.chan_scale[c], vr, vi, wt, w_out);
-}
+
+// elements a thread of the generic validity pass loads at once
+constexpr int kPrepUnroll = 4;
 
 // grid-stride geometry: stride a multiple of n_chan
 __host__ int blocks_for(int64_t n_elem, int n_chan) {
@@ -174,11 +141,46 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
     // the stride is a multiple of n_chan: the row advances by a constant
     const int64_t dr = stride / g.n_chan;
     int64_t r = e0 / g.n_chan;
-    for (int64_t e = e0; e < n_elem; e += stride, r += dr) {
-        bool fl;
-        double w, wt;
-        bool ok = valid0<VT>(g, uvw, vis, wts, flags, e, r, c, fl, w, wt);
-        mask[e] = ok ? 1 : 0;
+    // kPrepUnroll elements per iteration, every load issued before any is used (a slot
+    // past the data repeats the first element of the iteration and is skipped)
+    constexpr int U = kPrepUnroll;
+    const double sc = g.chan_scale[c];
+    const VT *vsrc = (const VT *)vis;
+    const VT *wsrc = wts ? (const VT *)wts : vsrc;   // without weights: read and replaced by 1
+    for (int64_t e = e0; e < n_elem; e += U * stride, r += U * dr) {
+        double um[U], vm[U], wm[U];
+        VT vr[U], vi[U], wv[U];
+        uint32_t fv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = e + u * stride < n_elem;
+            const int64_t ee = in ? e + u * stride : e, rr = in ? r + u * dr : r;
+            fv[u] = flags ? (uint32_t)flags[ee] : 0u;
+            vr[u] = vsrc[2 * ee];
+            vi[u] = vsrc[2 * ee + 1];
+            wv[u] = wsrc[ee];
+            um[u] = uvw[3 * rr];
+            vm[u] = uvw[3 * rr + 1];
+            wm[u] = uvw[3 * rr + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pin(fv[u]);
+            pin(vr[u]);
+            pin(vi[u]);
+            pin(wv[u]);
+            pin(um[u]);
+            pin(vm[u]);
+            pin(wm[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+        if (e + u * stride >= n_elem) break;
+        const bool fl = fv[u] != 0u;
+        double w = 0.0;
+        const double wt = wts ? (double)wv[u] : 1.0;
+        const bool ok = !fl && valid_vals(g, um[u], vm[u], wm[u], sc, (double)vr[u], (double)vi[u], wt, w);
+        mask[e + u * stride] = ok ? 1 : 0;
         nf += fl ? 1 : 0;
         if (ok) {
             ++nv;
@@ -191,6 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_prep(JobGeom g, const double *__re
                 ++nu;
                 sw += wt;
             }
+        }
         }
     }
     const int img = (n_img > 1) ? c : 0;
