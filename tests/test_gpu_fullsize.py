@@ -23,8 +23,8 @@ def test_config1_sampled_pixels(kernel, fold, precision):
     the Gaussian job in FP64 (the complex64 visibilities widened exactly to complex128, so
     the oracle's values are the same).  Bound: 1e-5 of the largest sampled value for the
     FP32 mesh; 1e-12 for FP64 (measured 4.7e-16), where the two sides differ only in
-    summation order (the
-    mesh and transform against a sum taken visibility by visibility)."""
+    summation order (the mesh and transform against a sum taken visibility by
+    visibility)."""
     import torch
     d = synth.config1_device(DEV)
     prm = wsg.make_params(**{**d["params"], "grid_correct": False, "normalize": False,
