@@ -204,6 +204,37 @@ def test_bad_values_and_footprint_edges(ctx):
     assert rel(img[0], ref["image"][0]) <= TOL64
 
 
+@pytest.mark.parametrize("precision,per_channel", [("f64", False), ("f32_phase64", False),
+                                                   ("f64", True)])
+def test_w_range_edge_rows_invalid(ctx, precision, per_channel):
+    """The rows at both ends of the w range carry a NaN visibility and a zero weight,
+    so the rows whose uvw and flags pass span a wider range than the valid data; the
+    planes follow the valid data alone (the planes, counts and image equal the
+    oracle's).  Cube variant: 3 channels in metres, and only one channel of each edge
+    row fails, so only that image's range is narrower than its uvw range."""
+    rng = np.random.default_rng(77)
+    nch = 3 if per_channel else 1
+    uvw, vis, wts = synth.random_visibilities(4000, nch, 64, 0.2 / 64, seed=78, w_extent=150.0)
+    freq = None
+    if per_channel:
+        freq = 150e6 * (1.0 + 0.05 * np.arange(nch))
+        uvw = uvw * (299792458.0 / 150e6)
+    hi, lo = int(np.argmax(uvw[:, 2])), int(np.argmin(uvw[:, 2]))
+    ch = 1 if per_channel else 0
+    vis[hi, ch] = np.nan
+    wts[lo, ch] = 0.0
+    vis[rng.integers(0, 4000, 20), 0] = np.inf       # scattered bad values as well
+    vis, wts = cast_inputs(precision, vis, wts)
+    wp, op = both_params(64, 5, 7, 0.2 / 64, precision, per_channel=per_channel)
+    img, st = gpu_image(ctx, wp, uvw, vis, wts, freq=freq)
+    ref = oracle_image(op, uvw, vis, wts, freq=freq)
+    assert_stats(st, ref["stats"])
+    assert st[ch]["w_max"] < uvw[hi, 2] * (freq[ch] / 299792458.0 if per_channel else 1.0)
+    assert st[ch]["w_min"] > uvw[lo, 2] * (freq[ch] / 299792458.0 if per_channel else 1.0)
+    for k in range(img.shape[0]):
+        assert rel(img[k], ref["image"][k]) <= (TOL64 if precision == "f64" else TOL32)
+
+
 @pytest.mark.parametrize("n_chan,offset", [(4, 0), (2, 0), (4, 1)])
 def test_f32_channels_flags_and_bad_values(ctx, n_chan, offset):
     """Single-image complex64 jobs of 2 and 4 channels (the validity pass takes one
