@@ -422,6 +422,45 @@ __global__ __launch_bounds__((Shape2<T, N>::THREADS)) void k_pass2_store(const C
 template <int MODE>
 struct Phase;
 
+// sin and cos of 2 pi t (t in turns) in FP64.  The reduction is exact: r = t - rint(t)
+// lies in [-1/2, 1/2], and with q = rint(4 r) the octant remainder f = r - q/4 lies in
+// [-1/8, 1/8] (both differences are exact in binary floating point).  With
+// x = 2 pi f in [-pi/4, pi/4], the Taylor series of sin to x^15 and of cos to x^16
+// leave remainders below |x|^17/17! < 5e-17 and |x|^18/18! < 3e-18; the quarter turns
+// q pi/2 are then applied by exchanging and negating the two.
+__device__ __forceinline__ void sincos_turns(double t, double &s, double &c) {
+    const double r = t - rint(t);
+    const double q = rint(4.0 * r);
+    const double f = r - 0.25 * q;
+    const double x = f * 6.283185307179586476925286766559;
+    const double x2 = x * x;
+    // 1/n! for n = 3, 5, ..., 15 and n = 2, 4, ..., 16, alternating in sign
+    double ps = -7.6471637318198164759e-13;                 // -1/15!
+    ps = fma(ps, x2, 1.6059043836821614599e-10);             //  1/13!
+    ps = fma(ps, x2, -2.5052108385441718775e-08);            // -1/11!
+    ps = fma(ps, x2, 2.7557319223985890653e-06);             //  1/9!
+    ps = fma(ps, x2, -1.9841269841269841270e-04);            // -1/7!
+    ps = fma(ps, x2, 8.3333333333333333333e-03);             //  1/5!
+    ps = fma(ps, x2, -1.6666666666666666667e-01);            // -1/3!
+    const double sx = fma(ps * x2, x, x);
+    double pc = 4.7794773323873852974e-14;                  //  1/16!
+    pc = fma(pc, x2, -1.1470745597729724714e-11);            // -1/14!
+    pc = fma(pc, x2, 2.0876756987868098979e-09);             //  1/12!
+    pc = fma(pc, x2, -2.7557319223985890653e-07);            // -1/10!
+    pc = fma(pc, x2, 2.4801587301587301587e-05);             //  1/8!
+    pc = fma(pc, x2, -1.3888888888888888889e-03);            // -1/6!
+    pc = fma(pc, x2, 4.1666666666666666667e-02);             //  1/4!
+    pc = fma(pc, x2, -0.5);                                  // -1/2!
+    const double cx = fma(pc, x2, 1.0);
+    // 2 pi r = x + q pi/2, q in {-2, -1, 0, 1, 2}
+    //   q = 0: (sin x, cos x); 1: (cos x, -sin x); +-2: (-sin x, -cos x); -1: (-cos x, sin x)
+    const int qi = (int)q;
+    const bool odd = qi & 1;
+    const double so = odd ? cx : sx, co = odd ? sx : cx;
+    s = (qi == 0 || qi == 1) ? so : -so;
+    c = (qi == 0 || qi == -1) ? co : -co;
+}
+
 template <>
 struct Phase<0> {
     using R = double;
@@ -432,7 +471,7 @@ struct Phase<0> {
         return -eta / (1.0 + sqrt(1.0 - eta));
     }
     static __device__ __forceinline__ void screen(R nm1v, double w, double &c, double &s) {
-        sincospi(2.0 * (w * nm1v), &s, &c);
+        sincos_turns(w * nm1v, s, c);
     }
 };
 
