@@ -71,7 +71,7 @@ def stage_bytes(job) -> tuple[dict, dict]:
     b_in = rows * 24 + m * (vsz + wsz)
     b_grid = nw * n * n * csz
     b_img = n * n * 8
-    rec = 40 if f64 else 16
+    rec = 32 if f64 else 16
     n_rec = job["n_records"]
     tiles = job["n_tiles"] * job["tile"] ** 2 * csz
     trows = job["n_tile_rows"] * job["tile"] * n * csz

@@ -584,6 +584,11 @@ __device__ __forceinline__ void for_each_run(const Keys &ks, int lane, F &&f) {
 __device__ __forceinline__ uint32_t quant_frac(double f) {
     return (uint32_t)fmin((f + 0.5) * 16777216.0 + 0.5, 16777215.0);
 }
+// and, for the complex128 mesh, the 52 mantissa bits of f + 3/2 (the sum is exact
+// where f has no bits below 2^-52)
+__device__ __forceinline__ uint64_t quant_frac64(double f) {
+    return (uint64_t)__double_as_longlong(f + 1.5) & kFracMask64;
+}
 
 // Counting pass: records per bin, into the workgroup's atomic class.
 // Keys of plane offset dk: every bin of the element moved dk planes (a whole
@@ -685,8 +690,9 @@ struct ScatterLds<float> {
 };
 template <>
 struct ScatterLds<double> {
-    uint32_t pk[kTileElems], lij[kTileElems];
-    double fx[kTileElems], fy[kTileElems], re[kTileElems], im[kTileElems];
+    uint32_t pk[kTileElems];
+    uint64_t a[kTileElems], b[kTileElems];
+    double re[kTileElems], im[kTileElems];
 };
 
 // with a kernel in w, also the element's w and its plane and image (k0 | img << 16)
@@ -807,9 +813,8 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
             const int lj0 = pl.j0 - (((pl.j0 - g.h) >> g.logT) << g.logT);
             const double fx = pl.x - (double)pl.i0, fy = pl.y - (double)pl.j0;
             if constexpr (sizeof(VT) == 8) {
-                L.lij[q] = (uint32_t)li0 | ((uint32_t)lj0 << 16);
-                L.fx[q] = fx;
-                L.fy[q] = fy;
+                L.a[q] = quant_frac64(fx) | ((uint64_t)li0 << kFracBits64);
+                L.b[q] = quant_frac64(fy) | ((uint64_t)lj0 << kFracBits64);
                 L.re[q] = wt[k] * vr[k];
                 L.im[q] = pl.flip ? -(wt[k] * vi[k]) : wt[k] * vi[k];
             } else {
@@ -838,14 +843,14 @@ void k_scatter(JobGeom g, const double *__restrict__ uvw,
         const uint32_t tt = bin & tmask;
         const int dx = (int)(tt & (uint32_t)(g.NT - 1)) - tx0, dy = (int)(tt >> g.logNT) - ty0;
         if constexpr (sizeof(VT) == 8) {
-            const uint32_t lij = L.lij[q];
+            const uint64_t a = L.a[q], b = L.b[q];
             RecF64 rec;
-            rec.fx = L.fx[q];
-            rec.fy = L.fy[q];
+            rec.px = (((a >> kFracBits64) - ((uint64_t)dx << g.logT) + (uint64_t)g.h) << kFracBits64) |
+                     (a & kFracMask64);
+            rec.py = (((b >> kFracBits64) - ((uint64_t)dy << g.logT) + (uint64_t)g.h) << kFracBits64) |
+                     (b & kFracMask64);
             rec.re = WK ? L.re[q] * gw : L.re[q];
             rec.im = WK ? L.im[q] * gw : L.im[q];
-            rec.li = (int)(lij & 0xffffu) - (dx << g.logT);
-            rec.lj = (int)(lij >> 16) - (dy << g.logT);
             ((RecF64 *)records)[slot] = rec;
         } else {
             const uint32_t a = L.a[q], b = L.b[q];

@@ -52,12 +52,13 @@ struct RecTraits<float> {
 template <>
 struct RecTraits<double> {
     using Rec = RecF64;
-    static __device__ __forceinline__ void decode(const Rec &r, int, int &li, int &lj, double &fx,
+    static __device__ __forceinline__ void decode(const Rec &r, int h, int &li, int &lj, double &fx,
                                                   double &fy, double &re, double &im) {
-        li = r.li;
-        lj = r.lj;
-        fx = r.fx;
-        fy = r.fy;
+        li = (int)(r.px >> kFracBits64) - h;
+        lj = (int)(r.py >> kFracBits64) - h;
+        // f + 3/2 rebuilt from its mantissa bits; the difference is exact
+        fx = __longlong_as_double((long long)((r.px & kFracMask64) | kOneBits64)) - 1.5;
+        fy = __longlong_as_double((long long)((r.py & kFracMask64) | kOneBits64)) - 1.5;
         re = r.re;
         im = r.im;
     }
@@ -365,13 +366,15 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
         if (pos < q1) nx = rec[pos];
         for (;;) {
             if (pos < q1 && !pend) {
-                const int li = nx.li, lj = nx.lj;
+                const int li = (int)(nx.px >> kFracBits64) - H, lj = (int)(nx.py >> kFracBits64) - H;
                 if (run == 0) {
                     ax = li;
                     ay = lj;
                 }
                 if (run < kRunCap && li == ax && lj == ay) {
-                    const double fx = nx.fx, fy = nx.fy, re = nx.re, im = nx.im;
+                    int li2, lj2;
+                    double fx, fy, re, im;
+                    RecTraits<double>::decode(nx, H, li2, lj2, fx, fy, re, im);
                     ++pos;
                     if (pos < q1) nx = rec[pos];
                     double gx[SS], gy[SS];

@@ -39,15 +39,20 @@ struct RecF32 {
     uint32_t px, py;   // (local cell + h) << 24 | round((f + 1/2) * 2^24)
     float re, im;      // W * V
 };
-// complex128 mesh: FP64 offsets.
+// complex128 mesh: the cell in the top 12 bits and the 52 mantissa bits of
+// f + 3/2 (a double in [1, 2), so these bits are (f + 1/2) * 2^52) below them, in
+// 32 bytes rather than 40.  Exact: f = x - i0 has no bits below ulp(x), and a mesh
+// coordinate x >= 2 has none below 2^-52.
 struct RecF64 {
-    double fx, fy;     // f = x - i0
+    uint64_t px, py;   // (local cell + h) << 52 | mantissa of (f + 3/2)
     double re, im;     // W * V
-    int32_t li, lj;    // cell relative to the tile origin
 };
 
 constexpr uint32_t kFracBits = 24;
 constexpr float kFracScale = 16777216.0f;        // 2^24
+constexpr uint32_t kFracBits64 = 52;
+constexpr uint64_t kFracMask64 = (1ull << 52) - 1ull;
+constexpr uint64_t kOneBits64 = 0x3ff0000000000000ull;   // the bits of 1.0
 
 // ----------------------------------------------------------------------------
 // per-image device state: reductions of the validity pass and plane geometry
