@@ -314,6 +314,29 @@ def test_tiles_f32(ctx, tile):
     assert peak(img[0], ref["raw"][0].real) <= PEAK32
 
 
+@pytest.mark.parametrize("tile,support", [(16, 15), (32, 7), (64, 1)])
+def test_tiles_f64(ctx, tile, support):
+    """The complex128 records at every tile size: the widest kernel on the smallest tile
+    (the largest cell field of a record), and a one-cell kernel with visibilities at the
+    low edge of the mesh (coordinates below 2 cells, where a record's sub-cell offset
+    can round in its last bit).  Before the grid correction, as in test_supports."""
+    n = 256
+    cell = 0.2 / n
+    uvw, vis, wts = _small(6000, n=n, seed=31)
+    if support == 1:
+        du = 1.0 / (n * cell)
+        x = np.array([0.3, 0.7, 1.2, 1.49, 1.51, 1.999])
+        uvw[:6, 0] = (x - n / 2) * du
+        uvw[:6, 1] = (x[::-1] - n / 2) * du
+    wp, op = both_params(n, 4, support, cell, "f64", tile=tile, kernel_sigma=0.5 + support / 8,
+                         grid_correct=False)
+    img, st = gpu_image(ctx, wp, uvw, vis, wts)
+    ref = oracle_image(op, uvw, vis, wts)
+    assert_stats(st, ref["stats"])
+    assert st[0]["n_dropped"] == 0
+    assert rel(img[0], ref["image"][0]) <= TOL64
+
+
 def test_split_hot_tiles(ctx):
     # 60,000 visibilities packed into a few cells: bins far above one work item
     rng = np.random.default_rng(12)
