@@ -87,16 +87,18 @@ __device__ __forceinline__ void gauss_line(float f, float cl2, const float *q, f
     }
 }
 
-// The same recurrence in FP64 (q[k] = e^{-c k^2}, c = 1/(2 sigma^2)): three
-// exponentials per axis instead of S, a few ulps from a direct evaluation.
+// The same recurrence in FP64 (q[k] = e^{-c k^2}, c = 1/(2 sigma^2)) without the taps'
+// common factor e^{-c f^2}, which the caller takes for both axes at once
+// (exp(-c (fx^2 + fy^2)), folded into W V): g[H + k] = r^k q[k] and g[H - k] = r^-k q[k],
+// r = e^{2 c f} and its inverse by division, so a record takes three exponentials
+// rather than six.  No tap exceeds 1 (2 c f k - c k^2 <= 0 for |f| <= 1/2, k >= 1).
 template <int SS>
-__device__ __forceinline__ void gauss_line64(double f, double c, const double *q, double *g) {
+__device__ __forceinline__ void gauss_ratio_line64(double f, double c, const double *q, double *g) {
     constexpr int H = (SS - 1) / 2;
-    const double e0 = exp(-(f * f) * c);
     const double r = exp((2.0 * f) * c);
-    const double ri = exp((-2.0 * f) * c);
-    g[H] = e0;
-    double pp = e0, pm = e0;
+    const double ri = 1.0 / r;
+    g[H] = 1.0;
+    double pp = 1.0, pm = 1.0;
 #pragma unroll
     for (int k = 1; k <= H; ++k) {
         pp *= r;
@@ -379,8 +381,11 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(JobGeom g, const uint32_t
                     if (pos < q1) nx = rec[pos];
                     double gx[SS], gy[SS];
                     if constexpr (KIND == 0) {
-                        gauss_line64<SS>(fx, g.inv2s2, q, gx);
-                        gauss_line64<SS>(fy, g.inv2s2, q, gy);
+                        const double e0 = exp(-(fx * fx + fy * fy) * g.inv2s2);
+                        re *= e0;
+                        im *= e0;
+                        gauss_ratio_line64<SS>(fx, g.inv2s2, q, gx);
+                        gauss_ratio_line64<SS>(fy, g.inv2s2, q, gy);
                     } else {
 #pragma unroll
                         for (int a = 0; a < SS; ++a) {
