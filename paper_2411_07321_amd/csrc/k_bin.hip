@@ -271,7 +271,6 @@ __global__ __launch_bounds__(kThreads) void k_prep_rows(JobGeom g, const double 
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < g.n_rows; r += stride) {
         const double um = uvw[3 * r], vm = uvw[3 * r + 1], wm = uvw[3 * r + 2];
         float vv[2 * NC], ww[NC];
-        uint8_t ff[NC];
         if constexpr (NC == 4) {
             const float4 a = ((const float4 *)vis)[2 * r], b = ((const float4 *)vis)[2 * r + 1];
             vv[0] = a.x; vv[1] = a.y; vv[2] = a.z; vv[3] = a.w;
