@@ -16,7 +16,7 @@ once by the transform (2 B_grid), the image written once (B_img); binning and
 intermediate passes are implementation overhead and earn nothing.  The gridding
 kernel itself is bound by VALU and LDS atomics, not HBM, and is rated by its
 useful arithmetic (392 flop per visibility: 49 complex multiply-adds) against
-the FP32 vector peak this build can issue (no packed FP32 instructions: 256 CUs x
+the FP32 vector peak the library's kernels can issue (no packed FP32 instructions: 256 CUs x
 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); the FP64 LDS atomic-add rate
 and the copy bandwidth the device reaches are measured by the library's probes.
 The same JSON line carries the job at the paper's own arithmetic (complex128 mesh
@@ -334,7 +334,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_launch": n * 4}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build images on one GPU; multi-GPU runs (w-plane "
+        print(json.dumps({"error": "the library images on one GPU; multi-GPU runs (w-plane "
                                    "sharding) are not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 

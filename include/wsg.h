@@ -70,7 +70,7 @@ enum {
     WSG_ENOMEM = -2,        /* workspace above the context's budget or device memory        */
     WSG_EDEVICE = -3,       /* HIP runtime error (no device, launch failure, ...)           */
     WSG_EBUSY = -4,         /* the context still has enqueued work it must not overlap      */
-    WSG_EUNSUPPORTED = -5,  /* valid but outside what this build supports (e.g. N > 16384)  */
+    WSG_EUNSUPPORTED = -5,  /* valid but outside what the library supports (e.g. N > 16384) */
     WSG_ECANCELED = -6      /* a submitted job was canceled before it reached the device    */
 };
 

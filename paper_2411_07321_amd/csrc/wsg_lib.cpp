@@ -1398,7 +1398,7 @@ const char *wsg_strerror(wsg_status s) {
     case WSG_ENOMEM: return "out of memory (workspace budget or device memory)";
     case WSG_EDEVICE: return "HIP device error";
     case WSG_EBUSY: return "context busy";
-    case WSG_EUNSUPPORTED: return "unsupported by this build";
+    case WSG_EUNSUPPORTED: return "unsupported by the library";
     case WSG_ECANCELED: return "job canceled before it started";
     default: return "unknown status";
     }

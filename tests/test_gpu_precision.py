@@ -4,6 +4,7 @@ and the naive FP32 n - 1, each against the FP64 oracle on the same inputs.
 Errors are relative L2 over the raw image (Re A), the bar of the plain path."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -14,7 +15,9 @@ from tests.gpuutil import DEV, log, rel
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# the study's table is written to $WSG_STUDY_OUT (default: the system's temporary
+# directory)
+OUT = os.environ.get("WSG_STUDY_OUT") or os.path.join(tempfile.gettempdir(), "wsg_study")
 
 
 @pytest.fixture(scope="module")
